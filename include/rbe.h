@@ -1,0 +1,233 @@
+/*
+ * rbe.h -- C ABI of librbe, an MI355X (gfx950) implementation of the random
+ * batch Ewald (RBE) method of Jin, Li, Xu & Zhao, "A random batch Ewald
+ * method for particle systems with Coulomb interactions" (arXiv:2010.01559).
+ *
+ * Problem statement (paper Sec. 2, eqs. 2.1-2.3 and 2.11): N point charges
+ * q_i at positions r_i in a cubic periodic box of side L, sum q_i = 0, with
+ * Coulomb potential coulomb * q_i q_j / r (reduced units, Sec. 4.1; `coulomb`
+ * is the Bjerrum length of Sec. 4.2, 1 otherwise).  The force splits into a
+ * Fourier part (eq. 2.11, first term) -- estimated by the random batch of P
+ * modes drawn from exp(-k^2/4 alpha) (Sec. 3.1, eqs. 3.3 and 3.6) -- and an
+ * exact real-space erfc part inside r_cut (eq. 2.11, second term), plus an
+ * optional shifted Lennard-Jones repulsion (eq. 4.1 with r_off = 0).
+ *
+ * Conventions shared by every entry point:
+ *   - Arrays are device memory owned by the caller, contiguous, SoA:
+ *     positions/velocities/forces/gradients are [3][N_tot] (x block, then y,
+ *     then z), charges are [N_tot].  Element type is float for RBE_FP32 and
+ *     double for RBE_FP64.  For a batch of R systems the particles of system
+ *     r occupy [off_r, off_r + n_r) inside each block, in creation order.
+ *   - Modes are integer vectors m with k = 2 pi m / L (Sec. 2), stored
+ *     [3][M_tot] int32 with system r's p_r modes at [moff_r, moff_r + p_r).
+ *   - All calls are asynchronous on the stream given at creation, except
+ *     rbe_create*, rbe_destroy, rbe_energy and rbe_get_rho, which synchronise.
+ *   - Hot calls (sample, forces, step, vjp) never allocate: every workspace
+ *     is sized at creation.
+ *   - Functions return an rbe_status and never abort; rbe_last_error gives
+ *     the message.  Argument validation happens on the host before any
+ *     device work is enqueued, so an error return leaves the stream
+ *     untouched.
+ *   - Positions may lie outside [0, L); they are wrapped periodically.
+ */
+#ifndef RBE_H
+#define RBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbe_ctx rbe_ctx;
+
+typedef enum rbe_status {
+    RBE_OK = 0,
+    RBE_ERR_INVALID = -1,      /* bad argument or parameter */
+    RBE_ERR_NOT_NEUTRAL = -2,  /* |sum q| > 1e-6 sum |q| (eq. 2.1) */
+    RBE_ERR_CUTOFF = -3,       /* r_cut or the LJ cutoff exceeds L/2 */
+    RBE_ERR_OOM = -4,          /* device allocation failed at creation */
+    RBE_ERR_HIP = -5,          /* a HIP runtime call failed */
+    RBE_ERR_NONFINITE = -6,    /* non-finite value seen by a kernel */
+    RBE_ERR_STATE = -7,        /* call not valid in the current state */
+    RBE_ERR_NO_DEVICE = -8     /* no usable gfx950 device */
+} rbe_status;
+
+enum { RBE_FP32 = 0, RBE_FP64 = 1 };
+
+/* Integrator for rbe_step. */
+enum { RBE_LANGEVIN_BAOAB = 0, RBE_LEAPFROG_ANDERSEN = 1 };
+
+/* Mode sampler. */
+enum { RBE_SAMPLER_EXACT = 0, RBE_SAMPLER_MH = 1 };
+
+/* Parts selector for rbe_forces_vjp. */
+enum { RBE_PART_KSPACE = 1, RBE_PART_REAL = 2, RBE_PART_ALL = 3 };
+
+/* Parameters of one system (paper notation in brackets). */
+typedef struct rbe_params {
+    int32_t n;           /* particles [N], >= 1 */
+    int32_t p;           /* batch size [p], >= 1 (Sec. 3.1) */
+    double box;          /* box side [L] > 0 */
+    double alpha;        /* Ewald splitting [alpha] > 0 (Sec. 2) */
+    double r_cut;        /* real-space cutoff [r_c], 0 < r_cut <= L/2 (eq. 2.8) */
+    double coulomb;      /* Coulomb prefactor: 1 (Sec. 4.1) or l_B (Sec. 4.2) */
+    double lj_eps;       /* shifted LJ [epsilon] (eq. 4.1); 0 disables LJ */
+    double lj_sigma;     /* [sigma] */
+    double lj_rcut;      /* LJ cutoff [R_c], <= L/2 when LJ is on */
+    double kT;           /* bath temperature [T], k_B = 1 (Sec. 3.3) */
+    double gamma;        /* Langevin friction [gamma] (Sec. 3.3) */
+    double dt;           /* time step [Delta t] */
+    double mass;         /* particle mass [m_i], equal for all particles */
+    double nu;           /* Andersen collision frequency [nu] (Sec. 3.3) */
+    uint64_t seed;       /* key of the counter-based generator */
+    int32_t precision;   /* RBE_FP32 or RBE_FP64 (all systems of a batch alike) */
+    int32_t integrator;  /* RBE_LANGEVIN_BAOAB or RBE_LEAPFROG_ANDERSEN */
+    int32_t sampler;     /* RBE_SAMPLER_EXACT or RBE_SAMPLER_MH */
+    int32_t flags;       /* reserved, 0 */
+} rbe_params;
+
+/* Energies of one system (all double, host memory). */
+typedef struct rbe_energy_t {
+    double e_kspace;   /* random batch estimate of the Fourier sum (eq. 2.6 without
+                          the self term) on the active modes */
+    double e_self;     /* -coulomb sqrt(alpha/pi) sum q_i^2 (eq. 2.6) */
+    double e_real;     /* truncated real-space erfc sum (eq. 2.9, third term) */
+    double e_lj;       /* shifted LJ energy (eq. 4.1) */
+    double e_kin;      /* sum m |v_i|^2 / 2 (0 when vel is NULL) */
+    double virial;     /* sum over real-space and LJ pairs of r_ij . F_ij (pair part of eq. 4.3) */
+    double charge_sum; /* sum q_i, for the neutrality check */
+    int32_t nonfinite; /* non-zero if any kernel met a non-finite force since the last call */
+    int32_t reserved;
+} rbe_energy_t;
+
+/* Tile shapes of the kernels; 0 fields mean "library default". */
+typedef struct rbe_tiles {
+    int32_t rho_chunk;     /* particles staged per structure-factor block (<= 2048) */
+    int32_t rho_block;     /* threads per structure-factor block: 256, 512 or 1024 */
+    int32_t force_split;   /* waves sharing one particle in the force pass: 1, 2 or 4 */
+    int32_t real_split;    /* threads per particle in the real-space pass: 1, 2 or 4 */
+} rbe_tiles;
+
+/* Normaliser of the importance distribution (Sec. 3.1, eqs. 3.1-3.2):
+ * H = sum_m exp(-pi^2 m^2/(alpha L^2)) and S = H^3 - 1.  Host only; needs no
+ * device.  Returns RBE_ERR_INVALID for non-positive or non-finite inputs. */
+rbe_status rbe_normalizer(double alpha, double box, double *H, double *S);
+
+/* Create a context for one system.  stream is a hipStream_t (NULL = default
+ * stream).  Validates params (RBE_ERR_INVALID / RBE_ERR_CUTOFF), selects the
+ * current HIP device, allocates every workspace.  On failure *out is NULL
+ * and rbe_last_error(NULL) describes the failure. */
+rbe_status rbe_create(const rbe_params *params, void *stream, rbe_ctx **out);
+
+/* Create a context for R independent systems (each with its own N, L, alpha,
+ * P, seed ...) that every call processes together in single launches.
+ * params is [R]; precision must agree. */
+rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, rbe_ctx **out);
+
+/* Release the context and its device memory.  NULL is ignored. */
+void rbe_destroy(rbe_ctx *ctx);
+
+/* Message of the last failed call on ctx, or of the last failed creation on
+ * this thread when ctx is NULL.  Never NULL. */
+const char *rbe_last_error(const rbe_ctx *ctx);
+
+/* Number of systems, total particles and total modes of the context. */
+int32_t rbe_num_systems(const rbe_ctx *ctx);
+int64_t rbe_num_particles(const rbe_ctx *ctx);
+int32_t rbe_num_modes(const rbe_ctx *ctx);
+
+/* Draw a fresh batch of p modes per system from P_k (Sec. 3.1, eq. 3.3;
+ * "renew the batch at every time step"), keyed by (seed, step), and make it
+ * the active batch with weights S/p (eq. 3.6).  The exact sampler inverts
+ * the 1-D cumulative table of eq. (3.4) per component and redraws the zero
+ * vector; the MH sampler follows the paper's Metropolis-Hastings recipe
+ * (eq. 3.5) with chains that persist in the context.  modes_out, if not
+ * NULL, is device memory [3][M_tot] int32 that receives the modes. */
+rbe_status rbe_sample_k(rbe_ctx *ctx, uint64_t step, int32_t *modes_out);
+
+/* Make an explicit mode list active for a single-system context: modes is
+ * host [3][nm] int32 (no zero vector), weights host [nm] or NULL.  NULL
+ * weights mean the random batch weight S/nm; explicit weights w_l turn the
+ * Fourier pass into sum_l w_l (4 pi k_l q_i/(V k_l^2)) Im(...) -- with
+ * w_l = exp(-k_l^2/4 alpha) over all 0 < |m| <= m_c it is the classical
+ * Ewald sum (eq. 2.11).  nm must not exceed the capacity fixed at creation
+ * (max(p, 1) unless rbe_reserve_modes raised it). */
+rbe_status rbe_set_k(rbe_ctx *ctx, const int32_t *modes, int32_t nm, const double *weights);
+
+/* Raise the mode capacity of a single-system context to cap (allocates;
+ * not a hot call). */
+rbe_status rbe_reserve_modes(rbe_ctx *ctx, int32_t cap);
+
+/* Fourier-space force on every particle with the active modes (eq. 3.6):
+ *   F_i = -coulomb * sum_l w_l (4 pi q_i k_l / (V k_l^2)) Im(exp(-i k_l.r_i) rho(k_l)),
+ * rho(k) = sum_j q_j exp(i k.r_j) (eq. 2.7).  force is overwritten, or added
+ * to when accumulate != 0.  The structure factors are kept for rbe_get_rho,
+ * rbe_energy and rbe_forces_vjp. */
+rbe_status rbe_kspace_forces(rbe_ctx *ctx, const void *pos, const void *q, void *force, int32_t accumulate);
+
+/* Real-space force (eq. 2.11, second term, pairs with |r_ij + nL| <= r_cut,
+ * minimum image) plus shifted LJ (eq. 4.1), on a cell list built on the fly
+ * (all pairs when fewer than 3 cells fit along the box).  force is
+ * overwritten or accumulated. */
+rbe_status rbe_real_forces(rbe_ctx *ctx, const void *pos, const void *q, void *force, int32_t accumulate);
+
+/* Advance nsteps time steps (Algorithm 1 of the paper).  Step s = first_step
+ * + t draws its modes and noise with index s.  RBE_LANGEVIN_BAOAB: half
+ * kick, half drift, exact Ornstein-Uhlenbeck velocity update, half drift,
+ * force, half kick (the Langevin equation of Sec. 3.3).  On entry force must
+ * hold F(pos) (e.g. from rbe_kspace_forces + rbe_real_forces); on exit pos,
+ * vel, force hold the new state, positions wrapped into [0, L).
+ * RBE_LEAPFROG_ANDERSEN: the leapfrog + Andersen loop of Sec. 3.1 with vel
+ * the half-step velocity; the force computed at the end of step s uses the
+ * modes of index s + 1. */
+rbe_status rbe_step(rbe_ctx *ctx, void *pos, void *vel, const void *q, void *force, uint64_t first_step,
+                    int32_t nsteps);
+
+/* Same as rbe_step; the name used for multi-system contexts. */
+rbe_status rbe_batch_step(rbe_ctx *ctx, void *pos, void *vel, const void *q, void *force, uint64_t first_step,
+                          int32_t nsteps);
+
+/* Energies of every system with the active modes (Sec. 2, eqs. 2.6 and 2.9;
+ * Sec. 4.1, eqs. 4.1 and 4.3).  vel may be NULL.  out is host [R].
+ * Synchronises the stream.  Returns RBE_ERR_NOT_NEUTRAL if some system has
+ * |sum q| > 1e-6 sum |q| (energies are still filled in), RBE_ERR_NONFINITE if
+ * a kernel met a non-finite force since the previous rbe_energy call. */
+rbe_status rbe_energy(rbe_ctx *ctx, const void *pos, const void *q, const void *vel, rbe_energy_t *out);
+
+/* Structure factors of the last Fourier evaluation: host [M_tot][2] double
+ * (real, imaginary).  Synchronises the stream. */
+rbe_status rbe_get_rho(rbe_ctx *ctx, double *rho);
+
+/* Vector-Jacobian product of the forces at the active modes: given
+ * grad_force = dLoss/dF ([3][N_tot]), writes grad_pos = dLoss/dr ([3][N_tot])
+ * and grad_q = dLoss/dq ([N_tot]) through the Fourier part (eq. 3.6 with the
+ * structure factor of eq. 2.7) and/or the real-space and LJ parts (eq. 2.11,
+ * eq. 4.1), selected by parts (RBE_PART_*).  Outputs are overwritten. */
+rbe_status rbe_forces_vjp(rbe_ctx *ctx, const void *pos, const void *q, const void *grad_force, void *grad_pos,
+                          void *grad_q, int32_t parts);
+
+/* Tile shapes: read or set (validated; 0 fields keep the current value). */
+rbe_status rbe_get_tiles(const rbe_ctx *ctx, rbe_tiles *tiles);
+rbe_status rbe_set_tiles(rbe_ctx *ctx, const rbe_tiles *tiles);
+
+/* Time the Fourier pass under every candidate tile shape on the given inputs
+ * (hipEvents on the context stream, reps repetitions each), keep the fastest
+ * and return it in *best (may be NULL).  Not a hot call. */
+rbe_status rbe_autotune(rbe_ctx *ctx, const void *pos, const void *q, int32_t reps, rbe_tiles *best);
+
+/* Per-kernel timing with hipEvents recorded around every launch on the
+ * context stream while enabled (adds a little overhead). */
+rbe_status rbe_profile_enable(rbe_ctx *ctx, int32_t enable);
+/* Accumulated milliseconds and launch count of kernel `id` since enabling;
+ * synchronises.  Returns RBE_ERR_INVALID for an unknown id. */
+rbe_status rbe_profile_read(rbe_ctx *ctx, int32_t id, double *total_ms, int64_t *launches);
+/* Name of kernel `id` (0 .. rbe_profile_count()-1), NULL if out of range. */
+const char *rbe_profile_name(int32_t id);
+int32_t rbe_profile_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBE_H */

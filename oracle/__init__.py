@@ -80,6 +80,9 @@ def lib():
         L.oracle_rho.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, _ip, _dp, _dp]
         L.oracle_kspace_force.restype = None
         L.oracle_kspace_force.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, _ip, _dp, C.c_double, _dp]
+        L.oracle_kspace_force_subset.restype = None
+        L.oracle_kspace_force_subset.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, _ip, _dp, C.c_double,
+                                                 C.c_int, _ip, _dp]
         L.oracle_kspace_energy.restype = C.c_double
         L.oracle_kspace_energy.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, _ip, _dp, C.c_double]
         L.oracle_self_energy.restype = C.c_double
@@ -202,6 +205,14 @@ def kspace_force(pos, q, L, modes, weight, coulomb=1.0):
     n, nm = q.shape[0], modes.shape[1]
     F = np.zeros((3, n))
     lib().oracle_kspace_force(n, pos, q, L, nm, modes, weight, coulomb, F)
+    return F
+
+
+def kspace_force_subset(pos, q, L, modes, weight, idx, coulomb=1.0):
+    pos, q, modes, weight, idx = _f64(pos), _f64(q), _i32(modes), _f64(weight), _i32(idx)
+    F = np.zeros((3, idx.shape[0]))
+    lib().oracle_kspace_force_subset(q.shape[0], pos, q, L, modes.shape[1], modes, weight, coulomb, idx.shape[0],
+                                     idx, F)
     return F
 
 

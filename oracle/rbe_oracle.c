@@ -355,6 +355,40 @@ void oracle_kspace_force(int n, const double *pos, const double *q, double L, in
     free(im);
 }
 
+/* The same Fourier-space force on the listed particles only (rho still sums
+ * over all n particles); F is [3][nsub]. */
+void oracle_kspace_force_subset(int n, const double *pos, const double *q, double L, int nm,
+                                const int32_t *modes, const double *weight, double coulomb,
+                                int nsub, const int32_t *idx, double *F)
+{
+    double *re = (double *)malloc(sizeof(double) * nm);
+    double *im = (double *)malloc(sizeof(double) * nm);
+    oracle_rho(n, pos, q, L, nm, modes, re, im);
+    double V = L * L * L;
+#pragma omp parallel for schedule(static)
+    for (int t = 0; t < nsub; ++t) {
+        int i = idx[t];
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int l = 0; l < nm; ++l) {
+            double kx = 2.0 * ORC_PI * modes[l] / L;
+            double ky = 2.0 * ORC_PI * modes[nm + l] / L;
+            double kz = 2.0 * ORC_PI * modes[2 * nm + l] / L;
+            double k2 = kx * kx + ky * ky + kz * kz;
+            double th = orc_phase(modes, nm, l, pos, n, i, L);
+            double imag = cos(th) * im[l] - sin(th) * re[l];
+            double f = weight[l] * 4.0 * ORC_PI * q[i] / (V * k2) * imag;
+            fx -= f * kx;
+            fy -= f * ky;
+            fz -= f * kz;
+        }
+        F[t] = coulomb * fx;
+        F[nsub + t] = coulomb * fy;
+        F[2 * nsub + t] = coulomb * fz;
+    }
+    free(re);
+    free(im);
+}
+
 /* Fourier-space energy with the same per-mode weights (eq. 2.6 without the
  * self term): coulomb * sum_l weight_l * (2 pi/(V k_l^2)) |rho(k_l)|^2. */
 double oracle_kspace_energy(int n, const double *pos, const double *q, double L, int nm,

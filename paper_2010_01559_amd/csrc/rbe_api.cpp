@@ -1,0 +1,982 @@
+// rbe_api.cpp -- host side of librbe: validation, context and workspace
+// management, and the C-ABI entry points declared in include/rbe.h.
+//
+// Paper: Jin, Li, Xu & Zhao, arXiv:2010.01559.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rbe.h"
+#include "rbe_internal.h"
+
+using namespace rbe;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+const char *kKernelNames[K_COUNT] = {"sample",  "rho",    "rho_final", "kforce",     "bin",
+                                     "scan",    "scatter", "cellsort", "real",       "integrate",
+                                     "energy",  "vjp_reduce", "vjp_gather", "vjp_real", "misc"};
+
+std::string fmt(const char *f, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof buf, f, ap);
+    va_end(ap);
+    return buf;
+}
+
+// 1-D factor of the normaliser (Sec. 3.1, eq. 3.2, direct form).
+double normaliser_H(double alpha, double L)
+{
+    const double a = kPi * kPi / (alpha * L * L);
+    double h = 1.0;
+    for (long m = 1; m < 100000000L; ++m) {
+        const double t = std::exp(-a * (double)m * (double)m);
+        if (t == 0.0 || t < h * 1e-20) break;
+        h += 2.0 * t;
+    }
+    return h;
+}
+
+// Half-width M of the 1-D mode table: the continuous Gaussian of eq. (3.4)
+// has standard deviation sqrt(alpha L^2/(2 pi^2)); beyond 10 of them the
+// mass is below exp(-50).
+int table_half_width(double alpha, double L)
+{
+    const double sigma = std::sqrt(alpha * L * L / (2.0 * kPi * kPi));
+    return (int)std::ceil(10.0 * sigma) + 1;
+}
+
+// Cumulative table of the 1-D weights exp(-pi^2 m^2/(alpha L^2)) for
+// m = -M..M: running sums from m = -M upwards over the total.
+void build_cdf(double alpha, double L, std::vector<double> &out)
+{
+    const int M = table_half_width(alpha, L);
+    const int K = 2 * M + 1;
+    const double a = kPi * kPi / (alpha * L * L);
+    std::vector<double> w(K);
+    for (int k = 0; k < K; ++k) {
+        const double m = (double)(k - M);
+        w[k] = std::exp(-a * m * m);
+    }
+    double tot = 0.0;
+    for (int k = 0; k < K; ++k) tot += w[k];
+    double run = 0.0;
+    for (int k = 0; k < K; ++k) {
+        run += w[k];
+        out.push_back(run / tot);
+    }
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+rbe_status validate(const rbe_params &p, std::string &err)
+{
+    if (p.n < 1) return err = fmt("n must be >= 1 (got %d)", p.n), RBE_ERR_INVALID;
+    if (p.p < 1) return err = fmt("p must be >= 1 (got %d)", p.p), RBE_ERR_INVALID;
+    if (!finite_pos(p.box)) return err = "box must be finite and > 0", RBE_ERR_INVALID;
+    if (!finite_pos(p.alpha)) return err = "alpha must be finite and > 0", RBE_ERR_INVALID;
+    if (!finite_pos(p.r_cut)) return err = "r_cut must be finite and > 0", RBE_ERR_INVALID;
+    if (!std::isfinite(p.coulomb)) return err = "coulomb must be finite", RBE_ERR_INVALID;
+    if (p.r_cut > 0.5 * p.box)
+        return err = fmt("r_cut %.6g exceeds half the box %.6g (minimum image)", p.r_cut, 0.5 * p.box),
+               RBE_ERR_CUTOFF;
+    if (!std::isfinite(p.lj_eps) || p.lj_eps < 0.0) return err = "lj_eps must be finite and >= 0", RBE_ERR_INVALID;
+    if (p.lj_eps > 0.0) {
+        if (!finite_pos(p.lj_sigma) || !finite_pos(p.lj_rcut))
+            return err = "lj_sigma and lj_rcut must be finite and > 0 when lj_eps > 0", RBE_ERR_INVALID;
+        if (p.lj_rcut > 0.5 * p.box)
+            return err = fmt("lj_rcut %.6g exceeds half the box", p.lj_rcut), RBE_ERR_CUTOFF;
+    }
+    if (!std::isfinite(p.kT) || p.kT < 0.0) return err = "kT must be finite and >= 0", RBE_ERR_INVALID;
+    if (!std::isfinite(p.gamma) || p.gamma < 0.0) return err = "gamma must be finite and >= 0", RBE_ERR_INVALID;
+    if (!std::isfinite(p.dt) || p.dt < 0.0) return err = "dt must be finite and >= 0", RBE_ERR_INVALID;
+    if (!finite_pos(p.mass)) return err = "mass must be finite and > 0", RBE_ERR_INVALID;
+    if (!std::isfinite(p.nu) || p.nu < 0.0) return err = "nu must be finite and >= 0", RBE_ERR_INVALID;
+    if (p.precision != RBE_FP32 && p.precision != RBE_FP64) return err = "unknown precision", RBE_ERR_INVALID;
+    if (p.integrator != RBE_LANGEVIN_BAOAB && p.integrator != RBE_LEAPFROG_ANDERSEN)
+        return err = "unknown integrator", RBE_ERR_INVALID;
+    if (p.sampler != RBE_SAMPLER_EXACT && p.sampler != RBE_SAMPLER_MH) return err = "unknown sampler", RBE_ERR_INVALID;
+    if (p.flags != 0) return err = "flags must be 0", RBE_ERR_INVALID;
+    const double H = normaliser_H(p.alpha, p.box);
+    if (1.0 / (H * H * H) > 0.5)
+        return err = fmt("alpha L^2 = %.3g is too small: the zero mode would carry most of the mass",
+                         p.alpha * p.box * p.box),
+               RBE_ERR_INVALID;
+    if (table_half_width(p.alpha, p.box) > (1 << 20)) return err = "alpha L^2 too large for the mode table", RBE_ERR_INVALID;
+    return RBE_OK;
+}
+
+}  // namespace
+
+struct rbe_ctx {
+    int R = 0;
+    int prec = RBE_FP32;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<rbe_params> prm;
+    std::vector<SysDev> sysh;
+    std::vector<int> ntiles_rho;   // per system
+    int64_t ntot = 0;
+    int mtot = 0;                  // active modes in total
+    int mcap = 0;                  // capacity of the mode arrays
+    int max_p = 0;
+    bool modes_valid = false;
+    bool any_mh = false;
+    LaunchCfg cfg{};
+    Workspace w{};
+    size_t partial_cap = 0;        // doubles allocated for partial
+    std::vector<void *> allocs;
+    std::string err = "no error";
+    // profiling
+    bool prof = false;
+    struct Pend {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Pend> pend;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[K_COUNT] = {};
+    int64_t prof_n[K_COUNT] = {};
+    // host staging
+    std::vector<double> epart_h;
+};
+
+namespace {
+
+rbe_status set_err(rbe_ctx *c, rbe_status st, const std::string &m)
+{
+    if (c) c->err = m;
+    return st;
+}
+
+rbe_status hip_fail(rbe_ctx *c, hipError_t e, const char *what)
+{
+    return set_err(c, RBE_ERR_HIP, fmt("%s: %s", what, hipGetErrorString(e)));
+}
+
+#define HIPCHK(ctx, call)                                    \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+template <typename F>
+rbe_status run(rbe_ctx *c, int id, F &&f)
+{
+    if (c->prof) {
+        hipEvent_t a, b;
+        if (c->pool.size() >= 2) {
+            a = c->pool.back();
+            c->pool.pop_back();
+            b = c->pool.back();
+            c->pool.pop_back();
+        } else {
+            HIPCHK(c, hipEventCreate(&a));
+            HIPCHK(c, hipEventCreate(&b));
+        }
+        HIPCHK(c, hipEventRecord(a, c->stream));
+        hipError_t e = f();
+        if (e != hipSuccess) return hip_fail(c, e, kKernelNames[id]);
+        HIPCHK(c, hipEventRecord(b, c->stream));
+        c->pend.push_back({id, a, b});
+        if (c->pend.size() > 4096) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            for (auto &p : c->pend) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, p.a, p.b);
+                c->prof_ms[p.id] += ms;
+                c->prof_n[p.id] += 1;
+                c->pool.push_back(p.a);
+                c->pool.push_back(p.b);
+            }
+            c->pend.clear();
+        }
+        return RBE_OK;
+    }
+    hipError_t e = f();
+    if (e != hipSuccess) return hip_fail(c, e, kKernelNames[id]);
+    return RBE_OK;
+}
+
+#define RUN(ctx, id, expr)                                       \
+    do {                                                         \
+        rbe_status s_ = run(ctx, id, [&]() { return (expr); }); \
+        if (s_ != RBE_OK) return s_;                             \
+    } while (0)
+
+template <typename T>
+rbe_status dalloc(rbe_ctx *c, T **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(c, RBE_ERR_OOM, fmt("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e)));
+    }
+    c->allocs.push_back(q);
+    *p = (T *)q;
+    return RBE_OK;
+}
+
+void free_all(rbe_ctx *c)
+{
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+// Structure-factor tiles for the current chunk size, their partial offsets
+// (in (C,S) pairs) and per-system tile counts.
+void build_rho_tiles(rbe_ctx *c, std::vector<Tile> &tiles, std::vector<int32_t> &poff, int chunk, int pcap_of_sys0)
+{
+    tiles.clear();
+    poff.assign(2 * c->R, 0);
+    c->ntiles_rho.assign(c->R, 0);
+    int64_t run = 0;
+    for (int r = 0; r < c->R; ++r) {
+        const int n = c->sysh[r].n;
+        const int nt = (n + chunk - 1) / chunk;
+        c->ntiles_rho[r] = nt;
+        poff[r] = (int32_t)run;
+        poff[c->R + r] = nt;
+        for (int k = 0; k < nt; ++k) tiles.push_back(Tile{r, k * chunk, std::min(chunk, n - k * chunk), k});
+        const int pc = (c->R == 1) ? pcap_of_sys0 : c->sysh[r].p;
+        run += (int64_t)nt * pc;
+    }
+}
+
+size_t partial_need(rbe_ctx *c, int chunk)
+{
+    int64_t run = 0;
+    for (int r = 0; r < c->R; ++r) {
+        const int nt = (c->sysh[r].n + chunk - 1) / chunk;
+        const int pc = (c->R == 1) ? c->mcap : c->sysh[r].p;
+        run += (int64_t)nt * pc;
+    }
+    return (size_t)run * 2;
+}
+
+rbe_status upload_rho_tiles(rbe_ctx *c)
+{
+    std::vector<Tile> tiles;
+    std::vector<int32_t> poff;
+    build_rho_tiles(c, tiles, poff, c->cfg.rho_chunk, c->mcap);
+    c->cfg.n_rho_tiles = (int)tiles.size();
+    HIPCHK(c, hipMemcpy(c->w.rho_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->w.partial_off, poff.data(), poff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return RBE_OK;
+}
+
+rbe_status upload_sys(rbe_ctx *c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->w.sys, c->sysh.data(), c->sysh.size() * sizeof(SysDev), hipMemcpyHostToDevice));
+    return RBE_OK;
+}
+
+void refresh_cfg_modes(rbe_ctx *c)
+{
+    c->mtot = 0;
+    c->max_p = 0;
+    for (auto &s : c->sysh) {
+        c->mtot += s.p;
+        c->max_p = std::max(c->max_p, s.p);
+    }
+    c->cfg.max_p = c->max_p;
+    c->cfg.mcap = c->mcap;
+}
+
+bool check_device_ptr(const void *p) { return p != nullptr; }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+rbe_status rbe_normalizer(double alpha, double box, double *H, double *S)
+{
+    if (!finite_pos(alpha) || !finite_pos(box) || !H || !S) return RBE_ERR_INVALID;
+    const double h = normaliser_H(alpha, box);
+    *H = h;
+    *S = h * h * h - 1.0;
+    return RBE_OK;
+}
+
+const char *rbe_last_error(const rbe_ctx *ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+int32_t rbe_num_systems(const rbe_ctx *ctx) { return ctx ? ctx->R : 0; }
+int64_t rbe_num_particles(const rbe_ctx *ctx) { return ctx ? ctx->ntot : 0; }
+int32_t rbe_num_modes(const rbe_ctx *ctx) { return ctx ? ctx->mtot : 0; }
+
+rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, rbe_ctx **out)
+{
+    if (out) *out = nullptr;
+    if (!params || !out || R < 1) {
+        g_create_error = "params and out must be non-NULL and R >= 1";
+        return RBE_ERR_INVALID;
+    }
+    int64_t ntot = 0;
+    for (int r = 0; r < R; ++r) {
+        std::string e;
+        rbe_status st = validate(params[r], e);
+        if (st != RBE_OK) {
+            g_create_error = fmt("system %d: %s", r, e.c_str());
+            return st;
+        }
+        if (params[r].precision != params[0].precision) {
+            g_create_error = "all systems of a batch must share one precision";
+            return RBE_ERR_INVALID;
+        }
+        ntot += params[r].n;
+    }
+    if (ntot >= (int64_t)1 << 31) {
+        g_create_error = "total particle count must be below 2^31";
+        return RBE_ERR_INVALID;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        g_create_error = "no HIP device available";
+        return RBE_ERR_NO_DEVICE;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        g_create_error = "hipGetDevice failed";
+        return RBE_ERR_NO_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_create_error = fmt("device %d is not gfx950 (%s)", dev, prop.gcnArchName);
+        return RBE_ERR_NO_DEVICE;
+    }
+
+    rbe_ctx *c = new rbe_ctx();
+    c->R = R;
+    c->prec = params[0].precision;
+    c->device = dev;
+    c->stream = (hipStream_t)stream;
+    c->prm.assign(params, params + R);
+    c->ntot = ntot;
+
+    // ---- per-system constants ----
+    std::vector<double> cdf;
+    int64_t off = 0;
+    int moff = 0, cell_off = 0, max_cells = 0;
+    for (int r = 0; r < R; ++r) {
+        const rbe_params &p = params[r];
+        SysDev s{};
+        s.n = p.n;
+        s.p = p.p;
+        s.off = (int32_t)off;
+        s.moff = moff;
+        s.cdf_off = (int32_t)cdf.size();
+        s.M = table_half_width(p.alpha, p.box);
+        build_cdf(p.alpha, p.box, cdf);
+        const double rmax = std::max(p.r_cut, p.lj_eps > 0.0 ? p.lj_rcut : 0.0);
+        int nc = (int)std::floor(p.box / rmax);
+        nc = std::min(nc, 128);
+        if (nc < 3) nc = 1;   // fewer than 3 cells along the box: one cell, all pairs
+        s.nc = nc;
+        s.ncell = nc * nc * nc;
+        s.cell_off = cell_off;
+        s.lj_on = p.lj_eps > 0.0 ? 1 : 0;
+        s.integrator = p.integrator;
+        s.mh_state_off = 3 * r;
+        s.L = p.box;
+        s.invL = 1.0 / p.box;
+        s.alpha = p.alpha;
+        s.beta = std::sqrt(p.alpha);
+        s.rc2 = p.r_cut * p.r_cut;
+        s.coulomb = p.coulomb;
+        const double H = normaliser_H(p.alpha, p.box);
+        s.S = H * H * H - 1.0;
+        s.lj_eps = p.lj_eps;
+        s.lj_sig2 = p.lj_sigma * p.lj_sigma;
+        s.lj_rc2 = p.lj_rcut * p.lj_rcut;
+        if (s.lj_on) {
+            const double sr6 = std::pow(p.lj_sigma / p.lj_rcut, 6.0);
+            s.lj_shift = -4.0 * p.lj_eps * (sr6 * sr6 - sr6);
+        }
+        s.kT = p.kT;
+        s.gamma = p.gamma;
+        s.dt = p.dt;
+        s.mass = p.mass;
+        s.c1 = std::exp(-p.gamma * p.dt / p.mass);
+        s.c2 = std::sqrt((1.0 - s.c1 * s.c1) * p.kT / p.mass);
+        s.nu_dt = p.nu * p.dt;
+        s.seed = p.seed;
+        c->sysh.push_back(s);
+        if (p.sampler == RBE_SAMPLER_MH) c->any_mh = true;
+        off += p.n;
+        moff += p.p;
+        cell_off += s.ncell;
+        max_cells = std::max(max_cells, s.ncell);
+    }
+    c->mcap = moff;
+    refresh_cfg_modes(c);
+
+    // ---- launch configuration ----
+    LaunchCfg &g = c->cfg;
+    g.stream = c->stream;
+    g.R = R;
+    g.prec = c->prec;
+    g.ntot = ntot;
+    g.mcap = c->mcap;
+    g.rho_chunk = 256;
+    g.rho_block = 1024;
+    g.force_split = 4;
+    g.real_split = 1;
+    g.ncell_tot = cell_off;
+    g.max_cells = max_cells;
+    g.max_p = c->max_p;
+
+    std::vector<Tile> ftiles, ptiles;
+    for (int r = 0; r < R; ++r) {
+        const int n = c->sysh[r].n;
+        for (int k = 0; k < n; k += 64) ftiles.push_back(Tile{r, k, std::min(64, n - k), 0});
+        for (int k = 0; k < n; k += 256) ptiles.push_back(Tile{r, k, std::min(256, n - k), 0});
+    }
+    g.n_force_tiles = (int)ftiles.size();
+    g.n_part_tiles = (int)ptiles.size();
+
+    // ---- device memory ----
+    const size_t esz = c->prec == RBE_FP64 ? 8 : 4;
+    const size_t pack_sz = c->prec == RBE_FP64 ? 32 : 16;
+    const size_t km_sz = c->prec == RBE_FP64 ? sizeof(KModeD) : sizeof(KModeF);
+    const size_t kv_sz = c->prec == RBE_FP64 ? sizeof(KVjpD) : sizeof(KVjpF);
+    (void)esz;
+    // the largest rho tile list is the one for the smallest chunk (64)
+    int64_t max_rho_tiles = 0;
+    for (int r = 0; r < R; ++r) max_rho_tiles += (c->sysh[r].n + 63) / 64;
+    c->partial_cap = partial_need(c, 64);
+    Workspace &w = c->w;
+    rbe_status st = RBE_OK;
+#define ALLOC(ptr, bytes)                                   \
+    do {                                                    \
+        if ((st = dalloc(c, &(ptr), (bytes))) != RBE_OK) {  \
+            g_create_error = c->err;                        \
+            free_all(c);                                    \
+            delete c;                                       \
+            return st;                                      \
+        }                                                   \
+    } while (0)
+    ALLOC(w.sys, sizeof(SysDev) * R);
+    ALLOC(w.rho_tiles, sizeof(Tile) * max_rho_tiles);
+    ALLOC(w.force_tiles, sizeof(Tile) * ftiles.size());
+    ALLOC(w.part_tiles, sizeof(Tile) * ptiles.size());
+    ALLOC(w.modes, sizeof(int32_t) * 3 * c->mcap);
+    ALLOC(w.mode_w, sizeof(double) * c->mcap);
+    ALLOC(w.partial, sizeof(double) * c->partial_cap);
+    ALLOC(w.partial_off, sizeof(int32_t) * 2 * R);
+    ALLOC(w.rho, sizeof(double) * 2 * c->mcap);
+    ALLOC(w.ab, sizeof(double) * 2 * c->mcap);
+    ALLOC(w.kmode, km_sz * c->mcap);
+    ALLOC(w.kvjp, kv_sz * c->mcap);
+    ALLOC(w.cdf, sizeof(double) * cdf.size());
+    ALLOC(w.mh_state, sizeof(int32_t) * 3 * R);
+    ALLOC(w.cell_count, sizeof(int32_t) * cell_off);
+    ALLOC(w.cell_start, sizeof(int32_t) * (cell_off + R));
+    ALLOC(w.cellid, sizeof(int32_t) * ntot);
+    ALLOC(w.rank, sizeof(int32_t) * ntot);
+    ALLOC(w.sorted_idx, sizeof(int32_t) * ntot);
+    ALLOC(w.packed, pack_sz * ntot);
+    ALLOC(w.sorted, pack_sz * ntot);
+    ALLOC(w.energy_part, sizeof(double) * 8 * ptiles.size());
+    ALLOC(w.flag, sizeof(int32_t) * 4);
+#undef ALLOC
+    c->epart_h.resize(8 * ptiles.size());
+
+    auto up = [&](void *dst, const void *src, size_t bytes) -> bool {
+        return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    bool ok = up(w.sys, c->sysh.data(), sizeof(SysDev) * R) &&
+              up(w.force_tiles, ftiles.data(), sizeof(Tile) * ftiles.size()) &&
+              up(w.part_tiles, ptiles.data(), sizeof(Tile) * ptiles.size()) &&
+              up(w.cdf, cdf.data(), sizeof(double) * cdf.size()) &&
+              hipMemset(w.mh_state, 0, sizeof(int32_t) * 3 * R) == hipSuccess &&
+              hipMemset(w.cell_count, 0, sizeof(int32_t) * cell_off) == hipSuccess &&
+              hipMemset(w.flag, 0, sizeof(int32_t) * 4) == hipSuccess &&
+              hipMemset(w.modes, 0, sizeof(int32_t) * 3 * c->mcap) == hipSuccess;
+    if (ok) ok = upload_rho_tiles(c) == RBE_OK;
+    if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        g_create_error = "uploading the context constants failed";
+        free_all(c);
+        delete c;
+        return RBE_ERR_HIP;
+    }
+    *out = c;
+    return RBE_OK;
+}
+
+rbe_status rbe_create(const rbe_params *params, void *stream, rbe_ctx **out)
+{
+    return rbe_batch_create(params, 1, stream, out);
+}
+
+void rbe_destroy(rbe_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &p : ctx->pend) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    free_all(ctx);
+    delete ctx;
+}
+
+rbe_status rbe_reserve_modes(rbe_ctx *c, int32_t cap)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (c->R != 1) return set_err(c, RBE_ERR_STATE, "rbe_reserve_modes needs a single-system context");
+    if (cap < 1 || cap > (1 << 24)) return set_err(c, RBE_ERR_INVALID, "capacity must be in [1, 2^24]");
+    if (cap <= c->mcap) return RBE_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const size_t km_sz = c->prec == RBE_FP64 ? sizeof(KModeD) : sizeof(KModeF);
+    const size_t kv_sz = c->prec == RBE_FP64 ? sizeof(KVjpD) : sizeof(KVjpF);
+    // replace the mode-sized buffers
+    auto swap_alloc = [&](void **slot, size_t bytes) -> rbe_status {
+        void *old = *slot;
+        void *nw = nullptr;
+        rbe_status s = dalloc(c, &nw, bytes);
+        if (s != RBE_OK) return s;
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), old);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        (void)hipFree(old);
+        *slot = nw;
+        return RBE_OK;
+    };
+    const int old_cap = c->mcap;
+    c->mcap = cap;
+    rbe_status s;
+    if ((s = swap_alloc((void **)&c->w.modes, sizeof(int32_t) * 3 * cap)) != RBE_OK ||
+        (s = swap_alloc((void **)&c->w.mode_w, sizeof(double) * cap)) != RBE_OK ||
+        (s = swap_alloc((void **)&c->w.rho, sizeof(double) * 2 * cap)) != RBE_OK ||
+        (s = swap_alloc((void **)&c->w.ab, sizeof(double) * 2 * cap)) != RBE_OK ||
+        (s = swap_alloc(&c->w.kmode, km_sz * cap)) != RBE_OK || (s = swap_alloc(&c->w.kvjp, kv_sz * cap)) != RBE_OK) {
+        c->mcap = old_cap;
+        c->modes_valid = false;
+        return s;
+    }
+    c->partial_cap = partial_need(c, 64);
+    if ((s = swap_alloc((void **)&c->w.partial, sizeof(double) * c->partial_cap)) != RBE_OK) return s;
+    c->modes_valid = false;
+    refresh_cfg_modes(c);
+    return upload_rho_tiles(c);
+}
+
+rbe_status rbe_sample_k(rbe_ctx *c, uint64_t step, int32_t *modes_out)
+{
+    if (!c) return RBE_ERR_INVALID;
+    bool dirty = false;
+    for (int r = 0; r < c->R; ++r)
+        if (c->sysh[r].p != c->prm[r].p) {
+            c->sysh[r].p = c->prm[r].p;
+            dirty = true;
+        }
+    if (dirty) {
+        rbe_status s = upload_sys(c);
+        if (s != RBE_OK) return s;
+        refresh_cfg_modes(c);
+        if ((s = upload_rho_tiles(c)) != RBE_OK) return s;
+    }
+    RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, step, c->any_mh ? 1 : 0));
+    c->modes_valid = true;
+    if (modes_out) {
+        for (int d = 0; d < 3; ++d)
+            HIPCHK(c, hipMemcpyAsync(modes_out + (size_t)d * c->mtot, c->w.modes + (size_t)d * c->mcap,
+                                     sizeof(int32_t) * c->mtot, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return RBE_OK;
+}
+
+rbe_status rbe_set_k(rbe_ctx *c, const int32_t *modes, int32_t nm, const double *weights)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (c->R != 1) return set_err(c, RBE_ERR_STATE, "rbe_set_k needs a single-system context");
+    if (!modes || nm < 1) return set_err(c, RBE_ERR_INVALID, "modes must be non-NULL and nm >= 1");
+    if (nm > c->mcap)
+        return set_err(c, RBE_ERR_INVALID, fmt("nm = %d exceeds the mode capacity %d (rbe_reserve_modes)", nm, c->mcap));
+    std::vector<int32_t> m(3 * (size_t)c->mcap, 0);
+    std::vector<double> wv(nm);
+    const double S = c->sysh[0].S;
+    for (int l = 0; l < nm; ++l) {
+        const int32_t a = modes[l], b = modes[nm + l], d = modes[2 * nm + l];
+        if (a == 0 && b == 0 && d == 0) return set_err(c, RBE_ERR_INVALID, fmt("mode %d is the zero vector", l));
+        m[l] = a;
+        m[c->mcap + l] = b;
+        m[2 * (size_t)c->mcap + l] = d;
+        wv[l] = weights ? weights[l] : S / (double)nm;
+        if (!std::isfinite(wv[l])) return set_err(c, RBE_ERR_INVALID, "non-finite weight");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->w.modes, m.data(), sizeof(int32_t) * m.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->w.mode_w, wv.data(), sizeof(double) * nm, hipMemcpyHostToDevice));
+    if (c->sysh[0].p != nm) {
+        c->sysh[0].p = nm;
+        rbe_status s = upload_sys(c);
+        if (s != RBE_OK) return s;
+        refresh_cfg_modes(c);
+        if ((s = upload_rho_tiles(c)) != RBE_OK) return s;
+    }
+    c->modes_valid = true;
+    return RBE_OK;
+}
+
+static rbe_status kspace_impl(rbe_ctx *c, const void *pos, const void *q, void *force, int accumulate)
+{
+    RUN(c, K_RHO, launch_rho(c->cfg, c->w, pos, q));
+    RUN(c, K_RHO_FINAL, launch_rho_final(c->cfg, c->w));
+    if (force) RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, accumulate));
+    return RBE_OK;
+}
+
+static rbe_status cells_impl(rbe_ctx *c, const void *pos, const void *q)
+{
+    RUN(c, K_BIN, launch_bin(c->cfg, c->w, pos, q));
+    RUN(c, K_SCAN, launch_scan(c->cfg, c->w));
+    RUN(c, K_SCATTER, launch_scatter(c->cfg, c->w));
+    RUN(c, K_CELLSORT, launch_cellsort(c->cfg, c->w));
+    return RBE_OK;
+}
+
+rbe_status rbe_kspace_forces(rbe_ctx *c, const void *pos, const void *q, void *force, int32_t accumulate)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (!pos || !q || !force) return set_err(c, RBE_ERR_INVALID, "pos, q and force must be non-NULL");
+    if (!c->modes_valid) return set_err(c, RBE_ERR_STATE, "no active modes: call rbe_sample_k or rbe_set_k first");
+    return kspace_impl(c, pos, q, force, accumulate);
+}
+
+rbe_status rbe_real_forces(rbe_ctx *c, const void *pos, const void *q, void *force, int32_t accumulate)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (!pos || !q || !force) return set_err(c, RBE_ERR_INVALID, "pos, q and force must be non-NULL");
+    rbe_status s = cells_impl(c, pos, q);
+    if (s != RBE_OK) return s;
+    RUN(c, K_REAL, launch_real(c->cfg, c->w, force, accumulate, nullptr));
+    return RBE_OK;
+}
+
+rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force, uint64_t first_step,
+                    int32_t nsteps)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (!pos || !vel || !q || !force) return set_err(c, RBE_ERR_INVALID, "pos, vel, q and force must be non-NULL");
+    if (nsteps < 0) return set_err(c, RBE_ERR_INVALID, "nsteps must be >= 0");
+    const bool andersen = c->prm[0].integrator == RBE_LEAPFROG_ANDERSEN;
+    for (int r = 1; r < c->R; ++r)
+        if ((c->prm[r].integrator == RBE_LEAPFROG_ANDERSEN) != andersen)
+            return set_err(c, RBE_ERR_INVALID, "all systems of a batch must use one integrator");
+    for (int r = 0; r < c->R; ++r)
+        if (c->sysh[r].p != c->prm[r].p) {
+            // explicit modes were set: stepping resamples, so restore p
+            c->sysh[r].p = c->prm[r].p;
+            rbe_status s = upload_sys(c);
+            if (s != RBE_OK) return s;
+            refresh_cfg_modes(c);
+            if ((s = upload_rho_tiles(c)) != RBE_OK) return s;
+        }
+    const int mh = c->any_mh ? 1 : 0;
+    for (int32_t t = 0; t < nsteps; ++t) {
+        const uint64_t s = first_step + (uint64_t)t;
+        RUN(c, K_INTEGRATE, launch_integrate(c->cfg, c->w, pos, vel, force, s));
+        RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, andersen ? s + 1 : s, mh));
+        rbe_status st = kspace_impl(c, pos, q, force, 0);
+        if (st != RBE_OK) return st;
+        if ((st = cells_impl(c, pos, q)) != RBE_OK) return st;
+        RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, andersen ? nullptr : vel));
+    }
+    if (nsteps > 0) c->modes_valid = true;
+    return RBE_OK;
+}
+
+rbe_status rbe_batch_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force, uint64_t first_step,
+                          int32_t nsteps)
+{
+    return rbe_step(c, pos, vel, q, force, first_step, nsteps);
+}
+
+rbe_status rbe_energy(rbe_ctx *c, const void *pos, const void *q, const void *vel, rbe_energy_t *out)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (!pos || !q || !out) return set_err(c, RBE_ERR_INVALID, "pos, q and out must be non-NULL");
+    if (!c->modes_valid) return set_err(c, RBE_ERR_STATE, "no active modes: call rbe_sample_k or rbe_set_k first");
+    rbe_status s = kspace_impl(c, pos, q, nullptr, 0);
+    if (s != RBE_OK) return s;
+    if ((s = cells_impl(c, pos, q)) != RBE_OK) return s;
+    RUN(c, K_ENERGY, launch_energy(c->cfg, c->w, q, vel));
+    std::vector<double> rho(2 * (size_t)c->mtot), wts(c->mtot);
+    std::vector<int32_t> modes(3 * (size_t)c->mcap);
+    int32_t flag[4] = {0, 0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(c->epart_h.data(), c->w.energy_part, sizeof(double) * c->epart_h.size(),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(rho.data(), c->w.rho, sizeof(double) * rho.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(wts.data(), c->w.mode_w, sizeof(double) * wts.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(modes.data(), c->w.modes, sizeof(int32_t) * modes.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(flag, c->w.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, launch_fill_zero(c->stream, c->w.flag, sizeof(int32_t)));
+    std::vector<double> acc(8 * (size_t)c->R, 0.0);
+    // part tiles are laid out system after system in creation order
+    {
+        int tile = 0;
+        for (int r = 0; r < c->R; ++r) {
+            const int nt = (c->sysh[r].n + 255) / 256;
+            for (int k = 0; k < nt; ++k, ++tile)
+                for (int j = 0; j < 8; ++j) acc[8 * r + j] += c->epart_h[8 * tile + j];
+        }
+    }
+    rbe_status ret = RBE_OK;
+    for (int r = 0; r < c->R; ++r) {
+        const SysDev &S = c->sysh[r];
+        double ek = 0.0;
+        for (int l = 0; l < S.p; ++l) {
+            const int o = S.moff + l;
+            const double mx = modes[o], my = modes[c->mcap + o], mz = modes[2 * (size_t)c->mcap + o];
+            const double m2 = mx * mx + my * my + mz * mz;
+            const double rr = rho[2 * o] * rho[2 * o] + rho[2 * o + 1] * rho[2 * o + 1];
+            // (2 pi/(V k^2)) |rho|^2 with k = 2 pi m/L  ==  |rho|^2 / (2 pi L |m|^2)
+            ek += wts[o] * rr / (2.0 * kPi * S.L * m2);
+        }
+        rbe_energy_t &e = out[r];
+        e.e_kspace = S.coulomb * ek;
+        e.e_self = -S.coulomb * std::sqrt(S.alpha / kPi) * acc[8 * r + 4];
+        e.e_real = acc[8 * r + 0];
+        e.e_lj = acc[8 * r + 1];
+        e.virial = acc[8 * r + 2];
+        e.e_kin = vel ? acc[8 * r + 3] : 0.0;
+        e.charge_sum = acc[8 * r + 5];
+        e.nonfinite = flag[0];
+        e.reserved = 0;
+        if (std::fabs(acc[8 * r + 5]) > 1e-6 * acc[8 * r + 6] && ret == RBE_OK) {
+            ret = set_err(c, RBE_ERR_NOT_NEUTRAL,
+                          fmt("system %d is not neutral: sum q = %.6g, sum |q| = %.6g", r, acc[8 * r + 5],
+                              acc[8 * r + 6]));
+        }
+    }
+    if (flag[0]) ret = set_err(c, RBE_ERR_NONFINITE, "a kernel met a non-finite force");
+    return ret;
+}
+
+rbe_status rbe_get_rho(rbe_ctx *c, double *rho)
+{
+    if (!c || !rho) return c ? set_err(c, RBE_ERR_INVALID, "rho must be non-NULL") : RBE_ERR_INVALID;
+    HIPCHK(c, hipMemcpyAsync(rho, c->w.rho, sizeof(double) * 2 * c->mtot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBE_OK;
+}
+
+rbe_status rbe_forces_vjp(rbe_ctx *c, const void *pos, const void *q, const void *grad_force, void *grad_pos,
+                          void *grad_q, int32_t parts)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (!pos || !q || !grad_force || !grad_pos || !grad_q)
+        return set_err(c, RBE_ERR_INVALID, "pointers must be non-NULL");
+    if (parts < 1 || parts > 3) return set_err(c, RBE_ERR_INVALID, "parts must be RBE_PART_KSPACE, _REAL or _ALL");
+    if ((parts & RBE_PART_KSPACE) && !c->modes_valid)
+        return set_err(c, RBE_ERR_STATE, "no active modes: call rbe_sample_k or rbe_set_k first");
+    if (parts & RBE_PART_KSPACE) {
+        rbe_status s = kspace_impl(c, pos, q, nullptr, 0);
+        if (s != RBE_OK) return s;
+        RUN(c, K_VJP_REDUCE, launch_vjp_reduce(c->cfg, c->w, pos, q, grad_force));
+        RUN(c, K_VJP_REDUCE, launch_vjp_final(c->cfg, c->w));
+        RUN(c, K_VJP_GATHER, launch_vjp_gather(c->cfg, c->w, pos, q, grad_force, grad_pos, grad_q));
+    }
+    if (parts & RBE_PART_REAL) {
+        rbe_status s = cells_impl(c, pos, q);
+        if (s != RBE_OK) return s;
+        RUN(c, K_VJP_REAL, launch_vjp_real(c->cfg, c->w, grad_force, grad_pos, grad_q,
+                                           (parts & RBE_PART_KSPACE) ? 1 : 0));
+    }
+    return RBE_OK;
+}
+
+rbe_status rbe_get_tiles(const rbe_ctx *c, rbe_tiles *t)
+{
+    if (!c || !t) return RBE_ERR_INVALID;
+    t->rho_chunk = c->cfg.rho_chunk;
+    t->rho_block = c->cfg.rho_block;
+    t->force_split = c->cfg.force_split;
+    t->real_split = c->cfg.real_split;
+    return RBE_OK;
+}
+
+rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
+{
+    if (!c || !t) return RBE_ERR_INVALID;
+    rbe_tiles n{c->cfg.rho_chunk, c->cfg.rho_block, c->cfg.force_split, c->cfg.real_split};
+    if (t->rho_chunk) n.rho_chunk = t->rho_chunk;
+    if (t->rho_block) n.rho_block = t->rho_block;
+    if (t->force_split) n.force_split = t->force_split;
+    if (t->real_split) n.real_split = t->real_split;
+    if (n.rho_chunk < 64 || n.rho_chunk > 2048 || (n.rho_chunk % 64))
+        return set_err(c, RBE_ERR_INVALID, "rho_chunk must be a multiple of 64 in [64, 2048]");
+    if (n.rho_block != 256 && n.rho_block != 512 && n.rho_block != 1024)
+        return set_err(c, RBE_ERR_INVALID, "rho_block must be 256, 512 or 1024");
+    if (n.force_split != 1 && n.force_split != 2 && n.force_split != 4)
+        return set_err(c, RBE_ERR_INVALID, "force_split must be 1, 2 or 4");
+    if (n.real_split != 1) return set_err(c, RBE_ERR_INVALID, "real_split must be 1");
+    // dynamic LDS of the reduction kernels must fit
+    // (the adjoint reduction stages 48 bytes per particle, the structure factor 32)
+    if (48 * (size_t)n.rho_chunk + 16 * (size_t)n.rho_block > 64 * 1024)
+        return set_err(c, RBE_ERR_INVALID, "rho_chunk and rho_block need more than 64 KB of LDS");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cfg.rho_chunk = n.rho_chunk;
+    c->cfg.rho_block = n.rho_block;
+    c->cfg.force_split = n.force_split;
+    c->cfg.real_split = n.real_split;
+    return upload_rho_tiles(c);
+}
+
+rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps, rbe_tiles *best)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (!pos || !q) return set_err(c, RBE_ERR_INVALID, "pos and q must be non-NULL");
+    if (!c->modes_valid) return set_err(c, RBE_ERR_STATE, "no active modes: call rbe_sample_k or rbe_set_k first");
+    if (reps < 1) reps = 10;
+    const bool prof = c->prof;
+    c->prof = false;
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    auto timeit = [&](auto &&body, float *ms) -> rbe_status {
+        rbe_status s = body();  // warm-up
+        if (s != RBE_OK) return s;
+        HIPCHK(c, hipEventRecord(a, c->stream));
+        for (int k = 0; k < reps; ++k)
+            if ((s = body()) != RBE_OK) return s;
+        HIPCHK(c, hipEventRecord(b, c->stream));
+        HIPCHK(c, hipEventSynchronize(b));
+        HIPCHK(c, hipEventElapsedTime(ms, a, b));
+        return RBE_OK;
+    };
+    rbe_tiles cur;
+    rbe_get_tiles(c, &cur);
+    rbe_tiles win = cur;
+    float best_rho = 1e30f, best_f = 1e30f;
+    const int chunks[] = {128, 256, 512, 1024};
+    const int blocks[] = {256, 512, 1024};
+    rbe_status s = RBE_OK;
+    for (int ch : chunks)
+        for (int bl : blocks) {
+            rbe_tiles t{ch, bl, cur.force_split, 1};
+            if ((s = rbe_set_tiles(c, &t)) != RBE_OK) continue;
+            float ms = 0.f;
+            s = timeit(
+                [&]() -> rbe_status {
+                    RUN(c, K_RHO, launch_rho(c->cfg, c->w, pos, q));
+                    RUN(c, K_RHO_FINAL, launch_rho_final(c->cfg, c->w));
+                    return RBE_OK;
+                },
+                &ms);
+            if (s != RBE_OK) break;
+            if (ms < best_rho) {
+                best_rho = ms;
+                win.rho_chunk = ch;
+                win.rho_block = bl;
+            }
+        }
+    if (s == RBE_OK) {
+        rbe_tiles t{win.rho_chunk, win.rho_block, 0, 0};
+        s = rbe_set_tiles(c, &t);
+    }
+    void *fbuf = nullptr;
+    if (s == RBE_OK) {
+        const size_t esz = c->prec == RBE_FP64 ? 8 : 4;
+        // the force pass needs an output: borrow the sorted workspace, which
+        // is large enough (16 or 32 bytes per particle >= 3 elements)
+        fbuf = c->w.sorted;
+        (void)esz;
+        for (int sp : {1, 2, 4}) {
+            rbe_tiles t{0, 0, sp, 0};
+            if ((s = rbe_set_tiles(c, &t)) != RBE_OK) break;
+            float ms = 0.f;
+            s = timeit(
+                [&]() -> rbe_status {
+                    RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, fbuf, 0));
+                    return RBE_OK;
+                },
+                &ms);
+            if (s != RBE_OK) break;
+            if (ms < best_f) {
+                best_f = ms;
+                win.force_split = sp;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    c->prof = prof;
+    if (s != RBE_OK) return s;
+    if ((s = rbe_set_tiles(c, &win)) != RBE_OK) return s;
+    if (best) *best = win;
+    return RBE_OK;
+}
+
+rbe_status rbe_profile_enable(rbe_ctx *c, int32_t enable)
+{
+    if (!c) return RBE_ERR_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->pend) {
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pend.clear();
+    for (int k = 0; k < K_COUNT; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    c->prof = enable != 0;
+    return RBE_OK;
+}
+
+rbe_status rbe_profile_read(rbe_ctx *c, int32_t id, double *total_ms, int64_t *launches)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (id < 0 || id >= K_COUNT) return set_err(c, RBE_ERR_INVALID, "unknown kernel id");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->pend) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
+        c->prof_ms[p.id] += ms;
+        c->prof_n[p.id] += 1;
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pend.clear();
+    if (total_ms) *total_ms = c->prof_ms[id];
+    if (launches) *launches = c->prof_n[id];
+    return RBE_OK;
+}
+
+const char *rbe_profile_name(int32_t id)
+{
+    if (id < 0 || id >= K_COUNT) return nullptr;
+    return kKernelNames[id];
+}
+
+int32_t rbe_profile_count(void) { return K_COUNT; }
+
+}  // extern "C"
