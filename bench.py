@@ -1,0 +1,200 @@
+"""Benchmark of the random batch Ewald hot path on one MI355X.
+
+Workload: N = 1e5 ions (+-1) at density 0.1 (L = 100), r_c = 3.5, P = 100
+modes per step, alpha from the 1e-4 real-space error estimate, shifted LJ
+(eps = 1, sigma = 1, cut 2.5), Langevin kT = 1, gamma = 1, dt = 1e-3, float32
+arithmetic with double phases.  Inputs are synthetic and resident on the GPU
+before timing starts.
+
+A timed "step" is one pass of the whole hot path: a fresh batch of P modes,
+structure factors, the Fourier force, the cell list, the real-space + LJ
+force and the Langevin update (rbe_step with nsteps = 1 per step, all launched
+back to back on one stream).  The headline value is N*P*steps / elapsed
+seconds over those full steps.  The JSON line also reports MD steps/s, the
+Fourier-only pair rate (sample + structure factor + force), per-kernel
+durations from HIP events on the library's stream, the ALU roofline of the
+dominant Fourier kernel, and the FP64 CPU oracle timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "k-space particle–mode pairs/s (N·P) + MD steps/s at N=1e5, P=100, 1 GPU"
+
+# Issue cost of the algorithmic operations per particle-mode pair, in FP32
+# VALU issue slots (an FP64 op takes 2, a transcendental op 4), and the chip's
+# FP32 vector peak: 256 CUs x 128 FP32 lanes/clock x 2 flop x 2.4 GHz.
+SLOTS_FORCE = 3 * 2 + 2 * 2 + 2 * 4 + 2 + 3   # phase (3 FP64 FMA), wrap (2 FP64), sin+cos, Im term, 3 FMA
+SLOTS_RHO = 3 * 2 + 2 * 2 + 2 * 4 + 2         # phase, wrap, sin+cos, 2 FMA
+PEAK_FP32_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(s, modes, budget_s):
+    """Time the FP64 oracle's Fourier evaluation (structure factor + force) on
+    the metric workload: whole evaluations at N = 1e5, P = 100 repeated until
+    the budget is spent."""
+    import oracle as O
+    O.build()
+    pos = s.pos.astype(np.float32).astype(np.float64)
+    q = s.q
+    w = O.rbe_weights(s.alpha, s.L, s.p)
+    O.rbe_kspace_force(pos[:, :1000], q[:1000], s.L, s.alpha, modes)  # load + warm
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.kspace_force(pos, q, s.L, modes, w)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or reps >= 1000:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": s.n * s.p * reps / el, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full Fourier evaluations (structure factor + force, FP64) of the N={s.n}, "
+                      f"P={s.p} workload in {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build runs on a "
+              f"single MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2010_01559_amd.rbe as R
+    from paper_2010_01559_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    s = W.metric_system()
+    params = R.params_from_system(s, R.RBE_FP32)
+    ctx = R.rbe_create(params)
+    dt = torch.float32
+    P = torch.as_tensor(s.pos, dtype=dt, device="cuda").contiguous()
+    Q = torch.as_tensor(s.q, dtype=dt, device="cuda").contiguous()
+    V = torch.as_tensor(s.vel, dtype=dt, device="cuda").contiguous()
+    F = torch.zeros_like(P)
+    stream = ctx.stream
+
+    R.rbe_sample_k(ctx, 0)
+    tiles = R.rbe_get_tiles(ctx) if args.no_autotune else R.rbe_autotune(ctx, P, Q, reps=20)
+    R.rbe_kspace_forces(ctx, P, Q, F)
+    R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
+
+    # ---- full MD steps ----
+    for k in range(args.warmup):
+        R.rbe_step(ctx, P, V, Q, F, 1 + k, 1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    base = 1 + args.warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for k in range(args.steps):
+        R.rbe_step(ctx, P, V, Q, F, base + k, 1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = e0.elapsed_time(e1) / args.steps
+    ms_per_step = max(step_ms, 1e3 * wall / args.steps)
+
+    # ---- Fourier-only evaluations: sample + structure factor + force ----
+    nk = max(args.steps, 100)
+    for k in range(10):
+        R.rbe_sample_k(ctx, 10 ** 6 + k)
+        R.rbe_kspace_forces(ctx, P, Q, F)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(nk):
+        R.rbe_sample_k(ctx, 2 * 10 ** 6 + k)
+        R.rbe_kspace_forces(ctx, P, Q, F)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / nk
+
+    # ---- per-kernel durations with HIP events on the library stream ----
+    R.rbe_profile_enable(ctx, True)
+    for k in range(args.steps):
+        R.rbe_step(ctx, P, V, Q, F, base + args.steps + k, 1)
+    prof = R.rbe_profile_read(ctx)
+    R.rbe_profile_enable(ctx, False)
+    kern = {name: {"avg_us": 1e3 * ms / n, "launches": n} for name, (ms, n) in prof.items() if n}
+    step_kernel_us = sum(v["avg_us"] * v["launches"] for v in kern.values()) / args.steps
+    # the Fourier kernels alone (structure factor without the fused
+    # integrator/binning, and the force pass without the scatter)
+    R.rbe_profile_enable(ctx, True)
+    for k in range(nk):
+        R.rbe_sample_k(ctx, 3 * 10 ** 6 + k)
+        R.rbe_kspace_forces(ctx, P, Q, F)
+    kprof = R.rbe_profile_read(ctx)
+    R.rbe_profile_enable(ctx, False)
+    kkern = {name: {"avg_us": 1e3 * ms / n, "launches": n} for name, (ms, n) in kprof.items() if n}
+
+    n, p = s.n, s.p
+    pairs = n * p
+    # dominant Fourier kernel and its ALU roofline
+    kf_us = kkern["kforce"]["avg_us"]
+    rho_us = kkern["stage"]["avg_us"]
+    dom, dom_us, slots = ("kforce", kf_us, SLOTS_FORCE) if kf_us >= rho_us else ("stage", rho_us, SLOTS_RHO)
+    achieved = pairs * slots * 2 / (dom_us * 1e-6) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "slots_per_pair": slots, "avg_launch_us": round(dom_us, 2)}
+
+    cpu = None
+    if not args.no_cpu:
+        m = torch.zeros((3, p), dtype=torch.int32, device="cuda")
+        R.rbe_sample_k(ctx, 0, m)
+        cpu = cpu_baseline(s, m.cpu().numpy(), args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": pairs * 1e3 / ms_per_step,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": s.name, "n": n, "p": p, "box": s.L, "alpha": round(s.alpha, 6),
+                   "r_cut": s.r_cut, "lj": list(s.lj), "dt": s.dt, "precision": "fp32 (fp64 phases)",
+                   "tiles": tiles},
+        "md_steps_per_s": 1e3 / ms_per_step,
+        "kspace_pairs_per_s": pairs * 1e3 / k_ms,
+        "kspace_ms": k_ms,
+        "step_kernel_us": step_kernel_us,
+        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]} for k, v in kern.items()},
+        "kspace_kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
+                           for k, v in kkern.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -22,9 +22,8 @@ namespace {
 
 thread_local std::string g_create_error = "no error";
 
-const char *kKernelNames[K_COUNT] = {"sample",  "rho",    "rho_final", "kforce",     "bin",
-                                     "scan",    "scatter", "cellsort", "real",       "integrate",
-                                     "energy",  "vjp_reduce", "vjp_gather", "vjp_real", "misc"};
+const char *kKernelNames[K_COUNT] = {"sample", "stage",      "mid",        "kforce",   "scatter", "real",
+                                     "energy", "vjp_reduce", "vjp_gather", "vjp_real", "misc"};
 
 std::string fmt(const char *f, ...)
 {
@@ -128,6 +127,7 @@ struct rbe_ctx {
     std::vector<rbe_params> prm;
     std::vector<SysDev> sysh;
     std::vector<int> ntiles_rho;   // per system
+    std::vector<int> real_sys;     // system of each real-space tile
     int64_t ntot = 0;
     int mtot = 0;                  // active modes in total
     int mcap = 0;                  // capacity of the mode arrays
@@ -268,6 +268,24 @@ size_t partial_need(rbe_ctx *c, int chunk)
     return (size_t)run * 2;
 }
 
+// Real-space tiles: runs of RL_PPB cell-sorted slots for systems with at least
+// three cells per side (aux = 0), runs of 256 particles in original order for
+// the all-pairs systems (aux = 1).
+void build_real_tiles(rbe_ctx *c, std::vector<Tile> &out, std::vector<int> &tile_sys)
+{
+    out.clear();
+    tile_sys.clear();
+    for (int r = 0; r < c->R; ++r) {
+        const SysDev &s = c->sysh[r];
+        const int aux = s.nc == 1 ? 1 : 0;
+        const int step = aux ? real_allpairs_per_tile() : real_rows_per_tile();
+        for (int k = 0; k < s.n; k += step) {
+            out.push_back(Tile{r, k, std::min(step, s.n - k), aux});
+            tile_sys.push_back(r);
+        }
+    }
+}
+
 rbe_status upload_rho_tiles(rbe_ctx *c)
 {
     std::vector<Tile> tiles;
@@ -379,7 +397,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     // ---- per-system constants ----
     std::vector<double> cdf;
     int64_t off = 0;
-    int moff = 0, cell_off = 0, max_cells = 0;
+    int moff = 0, cell_off = 0, max_cells = 0, max_table = 0;
     for (int r = 0; r < R; ++r) {
         const rbe_params &p = params[r];
         SysDev s{};
@@ -396,7 +414,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         if (nc < 3) nc = 1;   // fewer than 3 cells along the box: one cell, all pairs
         s.nc = nc;
         s.ncell = nc * nc * nc;
-        s.cell_off = cell_off;
+        s.cell_off = cell_off;   // kept a multiple of 4 for vector loads of the counts
         s.lj_on = p.lj_eps > 0.0 ? 1 : 0;
         s.integrator = p.integrator;
         s.mh_state_off = 3 * r;
@@ -427,8 +445,9 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         if (p.sampler == RBE_SAMPLER_MH) c->any_mh = true;
         off += p.n;
         moff += p.p;
-        cell_off += s.ncell;
+        cell_off += (s.ncell + 3) & ~3;
         max_cells = std::max(max_cells, s.ncell);
+        max_table = std::max(max_table, 2 * s.M + 1);
     }
     c->mcap = moff;
     refresh_cfg_modes(c);
@@ -447,6 +466,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     g.ncell_tot = cell_off;
     g.max_cells = max_cells;
     g.max_p = c->max_p;
+    g.max_table = max_table;
 
     std::vector<Tile> ftiles, ptiles;
     for (int r = 0; r < R; ++r) {
@@ -456,6 +476,9 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     }
     g.n_force_tiles = (int)ftiles.size();
     g.n_part_tiles = (int)ptiles.size();
+    std::vector<Tile> rtiles;
+    build_real_tiles(c, rtiles, c->real_sys);
+    g.n_real_tiles = (int)rtiles.size();
 
     // ---- device memory ----
     const size_t esz = c->prec == RBE_FP64 ? 8 : 4;
@@ -482,6 +505,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     ALLOC(w.rho_tiles, sizeof(Tile) * max_rho_tiles);
     ALLOC(w.force_tiles, sizeof(Tile) * ftiles.size());
     ALLOC(w.part_tiles, sizeof(Tile) * ptiles.size());
+    ALLOC(w.real_tiles, sizeof(Tile) * rtiles.size());
     ALLOC(w.modes, sizeof(int32_t) * 3 * c->mcap);
     ALLOC(w.mode_w, sizeof(double) * c->mcap);
     ALLOC(w.partial, sizeof(double) * c->partial_cap);
@@ -499,10 +523,10 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     ALLOC(w.sorted_idx, sizeof(int32_t) * ntot);
     ALLOC(w.packed, pack_sz * ntot);
     ALLOC(w.sorted, pack_sz * ntot);
-    ALLOC(w.energy_part, sizeof(double) * 8 * ptiles.size());
+    ALLOC(w.energy_part, sizeof(double) * 8 * rtiles.size());
     ALLOC(w.flag, sizeof(int32_t) * 4);
 #undef ALLOC
-    c->epart_h.resize(8 * ptiles.size());
+    c->epart_h.resize(8 * rtiles.size());
 
     auto up = [&](void *dst, const void *src, size_t bytes) -> bool {
         return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
@@ -510,6 +534,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     bool ok = up(w.sys, c->sysh.data(), sizeof(SysDev) * R) &&
               up(w.force_tiles, ftiles.data(), sizeof(Tile) * ftiles.size()) &&
               up(w.part_tiles, ptiles.data(), sizeof(Tile) * ptiles.size()) &&
+              up(w.real_tiles, rtiles.data(), sizeof(Tile) * rtiles.size()) &&
               up(w.cdf, cdf.data(), sizeof(double) * cdf.size()) &&
               hipMemset(w.mh_state, 0, sizeof(int32_t) * 3 * R) == hipSuccess &&
               hipMemset(w.cell_count, 0, sizeof(int32_t) * cell_off) == hipSuccess &&
@@ -643,20 +668,25 @@ rbe_status rbe_set_k(rbe_ctx *c, const int32_t *modes, int32_t nm, const double 
     return RBE_OK;
 }
 
+// Structure factors of pos with the active modes (one staging launch and
+// the reduction), then the force pass when force is given.
 static rbe_status kspace_impl(rbe_ctx *c, const void *pos, const void *q, void *force, int accumulate)
 {
-    RUN(c, K_RHO, launch_rho(c->cfg, c->w, pos, q));
-    RUN(c, K_RHO_FINAL, launch_rho_final(c->cfg, c->w));
-    if (force) RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, accumulate));
+    StageRequest rq{const_cast<void *>(pos), nullptr, nullptr, q, 0, 0, 0, 0, 0, 1};
+    RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
+    RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0));
+    if (force) RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, accumulate, 0));
     return RBE_OK;
 }
 
+// Cell list of pos: bin (staging launch without the structure factor),
+// scan, scatter into cell order.
 static rbe_status cells_impl(rbe_ctx *c, const void *pos, const void *q)
 {
-    RUN(c, K_BIN, launch_bin(c->cfg, c->w, pos, q));
-    RUN(c, K_SCAN, launch_scan(c->cfg, c->w));
+    StageRequest rq{const_cast<void *>(pos), nullptr, nullptr, q, 0, 0, 0, 1, 0, 0};
+    RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
+    RUN(c, K_MID, launch_mid(c->cfg, c->w, 0, 1));
     RUN(c, K_SCATTER, launch_scatter(c->cfg, c->w));
-    RUN(c, K_CELLSORT, launch_cellsort(c->cfg, c->w));
     return RBE_OK;
 }
 
@@ -697,14 +727,20 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
             refresh_cfg_modes(c);
             if ((s = upload_rho_tiles(c)) != RBE_OK) return s;
         }
-    const int mh = c->any_mh ? 1 : 0;
+    // one step = four launches: [integrate + bin + draw modes + structure-factor
+    // partials] -> [totals + cell scan] -> [Fourier force + scatter] ->
+    // [real space + LJ + final half kick]
+    int table_lds = 0, tab_max = 0;
+    const size_t lds = stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max);
+    const bool fuse_sample = !c->any_mh && lds <= 64 * 1024;
     for (int32_t t = 0; t < nsteps; ++t) {
         const uint64_t s = first_step + (uint64_t)t;
-        RUN(c, K_INTEGRATE, launch_integrate(c->cfg, c->w, pos, vel, force, s));
-        RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, andersen ? s + 1 : s, mh));
-        rbe_status st = kspace_impl(c, pos, q, force, 0);
-        if (st != RBE_OK) return st;
-        if ((st = cells_impl(c, pos, q)) != RBE_OK) return st;
+        const uint64_t ks = andersen ? s + 1 : s;
+        if (!fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
+        StageRequest rq{pos, vel, force, q, s, ks, 1, 1, fuse_sample ? 1 : 0, 1};
+        RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
+        RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 1));
+        RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, 0, 1));
         RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, andersen ? nullptr : vel));
     }
     if (nsteps > 0) c->modes_valid = true;
@@ -739,14 +775,9 @@ rbe_status rbe_energy(rbe_ctx *c, const void *pos, const void *q, const void *ve
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, launch_fill_zero(c->stream, c->w.flag, sizeof(int32_t)));
     std::vector<double> acc(8 * (size_t)c->R, 0.0);
-    // part tiles are laid out system after system in creation order
-    {
-        int tile = 0;
-        for (int r = 0; r < c->R; ++r) {
-            const int nt = (c->sysh[r].n + 255) / 256;
-            for (int k = 0; k < nt; ++k, ++tile)
-                for (int j = 0; j < 8; ++j) acc[8 * r + j] += c->epart_h[8 * tile + j];
-        }
+    for (size_t tile = 0; tile < c->real_sys.size(); ++tile) {
+        const int r = c->real_sys[tile];
+        for (int j = 0; j < 8; ++j) acc[8 * r + j] += c->epart_h[8 * tile + j];
     }
     rbe_status ret = RBE_OK;
     for (int r = 0; r < c->R; ++r) {
@@ -839,8 +870,11 @@ rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
         return set_err(c, RBE_ERR_INVALID, "force_split must be 1, 2 or 4");
     if (n.real_split != 1) return set_err(c, RBE_ERR_INVALID, "real_split must be 1");
     // dynamic LDS of the reduction kernels must fit
-    // (the adjoint reduction stages 48 bytes per particle, the structure factor 32)
-    if (48 * (size_t)n.rho_chunk + 16 * (size_t)n.rho_block > 64 * 1024)
+    // the adjoint reduction stages 48 bytes per particle and 16 per thread;
+    // the staging kernel 32 per particle and 28 per thread (plus the table,
+    // which falls back to global memory when it does not fit)
+    if (48 * (size_t)n.rho_chunk + 16 * (size_t)n.rho_block > 64 * 1024 ||
+        32 * (size_t)n.rho_chunk + 28 * (size_t)n.rho_block > 64 * 1024)
         return set_err(c, RBE_ERR_INVALID, "rho_chunk and rho_block need more than 64 KB of LDS");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cfg.rho_chunk = n.rho_chunk;
@@ -886,8 +920,9 @@ rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps
             float ms = 0.f;
             s = timeit(
                 [&]() -> rbe_status {
-                    RUN(c, K_RHO, launch_rho(c->cfg, c->w, pos, q));
-                    RUN(c, K_RHO_FINAL, launch_rho_final(c->cfg, c->w));
+                    StageRequest rq{const_cast<void *>(pos), nullptr, nullptr, q, 0, 0, 0, 0, 0, 1};
+                    RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
+                    RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0));
                     return RBE_OK;
                 },
                 &ms);
@@ -915,7 +950,7 @@ rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps
             float ms = 0.f;
             s = timeit(
                 [&]() -> rbe_status {
-                    RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, fbuf, 0));
+                    RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, fbuf, 0, 0));
                     return RBE_OK;
                 },
                 &ms);

@@ -1,0 +1,171 @@
+// rbe_device.h -- device helpers shared by the kernels of librbe.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rbe_internal.h"
+
+namespace rbe {
+
+// ---------------------------------------------------------------------------
+// Counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror & Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC'11): ten rounds of two
+// 32x32 -> 64-bit products with multipliers 0xD2511F53 and 0xCD9E8D57, a word
+// permutation, and a Weyl key schedule (0x9E3779B9, 0xBB67AE85).
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        U4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Counter (idx, word1, step low, step high) under key `seed`.
+__device__ __forceinline__ U4 draw(uint32_t idx, uint32_t word1, uint64_t seed, uint64_t step)
+{
+    U4 c{idx, word1, (uint32_t)step, (uint32_t)(step >> 32)};
+    return philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// 53-bit uniform in [0,1): 27 high bits of a, 26 of b.
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+// Three standard normals for particle i at step: Box-Muller on
+// u1 = (w0 + 1) 2^-32, u2 = w1 2^-32 (two normals) and on (w2 + 1) 2^-32,
+// w3 2^-32 (cosine branch), in double.
+__device__ __forceinline__ void normals3(uint32_t i, uint64_t seed, uint64_t step, double xi[3])
+{
+    const U4 r = draw(i, kTagLangevin, seed, step);
+    const double k = 1.0 / 4294967296.0;
+    const double u1 = ((double)r.x + 1.0) * k, u2 = (double)r.y * k;
+    const double u3 = ((double)r.z + 1.0) * k, u4 = (double)r.w * k;
+    const double a = sqrt(-2.0 * log(u1)), b = sqrt(-2.0 * log(u3));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    xi[0] = a * c;
+    xi[1] = a * s;
+    xi[2] = b * cospi(2.0 * u4);
+}
+
+// Smallest index k of the cumulative table t[0..K) with u < t[k]; the last
+// entry is 1 and u < 1, so the answer is in range.
+__device__ __forceinline__ int invert_cdf(const double *t, int K, double u)
+{
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u < t[mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// One exact draw from the importance distribution (Sec. 3.1, eq. 3.3): each
+// component inverts the 1-D cumulative table of eq. (3.4); the zero vector
+// is drawn again.  Attempt a of draw l uses counters (l, TAG | 2a, step) and
+// (l, TAG | 2a + 1, step).
+__device__ __forceinline__ void sample_mode(const double *t, int M, uint32_t l, uint64_t seed, uint64_t step,
+                                            int &mx, int &my, int &mz)
+{
+    const int K = 2 * M + 1;
+    mx = my = mz = 0;
+    for (uint32_t a = 0; a < (1u << 22); ++a) {
+        const U4 r0 = draw(l, kTagSample | (2u * a), seed, step);
+        const U4 r1 = draw(l, kTagSample | (2u * a + 1u), seed, step);
+        mx = invert_cdf(t, K, u53(r0.x, r0.y)) - M;
+        my = invert_cdf(t, K, u53(r0.z, r0.w)) - M;
+        mz = invert_cdf(t, K, u53(r1.x, r1.y)) - M;
+        if (mx | my | mz) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Phases and trigonometry.  A phase is m.s in revolutions, formed in double
+// from integer modes and fractional coordinates, wrapped to [-1/2, 1/2].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wrap_rev(double ph) { return ph - rint(ph); }
+
+__device__ __forceinline__ double frac01(double x)
+{
+    const double f = x - floor(x);
+    return f >= 1.0 ? 0.0 : f;
+}
+
+// Single precision: the hardware sine/cosine take revolutions directly
+// (measured absolute error below 1.3e-7 on [-1/2, 1/2]).
+__device__ __forceinline__ void sincos_rev(double r, float *s, float *c)
+{
+    const float rf = (float)r;
+    *s = __builtin_amdgcn_sinf(rf);
+    *c = __builtin_amdgcn_cosf(rf);
+}
+
+__device__ __forceinline__ void sincos_rev(double r, double *s, double *c) { sincospi(2.0 * r, s, c); }
+
+// ---------------------------------------------------------------------------
+// Particle records.
+// PartD: fractional coordinates (double) and charge, for the Fourier passes
+// and the double-precision real space.
+// PackF: 32-bit fixed-point fractions of the box u = floor(s 2^32) and the
+// charge; the unsigned difference of two records, read as signed, is the
+// minimum-image displacement in units of L 2^-32.
+// ---------------------------------------------------------------------------
+struct alignas(16) PartD {
+    double x, y, z, q;
+};
+
+struct alignas(16) PackF {
+    uint32_t x, y, z;
+    float q;
+};
+
+__device__ __forceinline__ uint32_t to_fix(double s)
+{
+    const double v = s * 4294967296.0;
+    return v >= 4294967295.0 ? 4294967295u : (uint32_t)v;
+}
+
+__device__ __forceinline__ int cell_of_fix(uint32_t u, int nc) { return (int)(((uint64_t)u * (uint64_t)nc) >> 32); }
+
+__device__ __forceinline__ int cell_of_frac(double s, int nc)
+{
+    const int c = (int)(s * nc);
+    return c >= nc ? nc - 1 : c;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+}  // namespace rbe

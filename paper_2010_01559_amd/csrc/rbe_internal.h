@@ -26,7 +26,7 @@ struct SysDev {
     int32_t moff;       // first mode in the concatenated mode arrays
     int32_t cdf_off;    // first entry of this system's cumulative table
     int32_t M;          // table covers m = -M..M
-    int32_t nc;         // cells per box side (0 => all-pairs real space)
+    int32_t nc;         // cells per box side (1 => all-pairs real space)
     int32_t cell_off;   // first cell of this system
     int32_t lj_on;
     int32_t integrator;
@@ -86,16 +86,12 @@ struct KVjpD {
 
 // Kernel ids for per-launch event timing.
 enum KernelId {
-    K_SAMPLE = 0,
-    K_RHO,
-    K_RHO_FINAL,
-    K_KFORCE,
-    K_BIN,
-    K_SCAN,
-    K_SCATTER,
-    K_CELLSORT,
-    K_REAL,
-    K_INTEGRATE,
+    K_SAMPLE = 0,   // stand-alone mode sampling
+    K_STAGE,        // [integrate] + [bin] + [sample] + structure-factor partials
+    K_MID,          // structure-factor totals + cell scan
+    K_KFORCE,       // Fourier force [+ scatter]
+    K_SCATTER,      // stand-alone scatter into cell order
+    K_REAL,         // real space [+ kick]
     K_ENERGY,
     K_VJP_REDUCE,
     K_VJP_GATHER,
@@ -108,56 +104,64 @@ enum KernelId {
 struct Workspace {
     SysDev *sys;           // [R]
     Tile *rho_tiles;       // structure-factor tiles
-    Tile *force_tiles;     // force-pass tiles (64 particles per wave slot)
+    Tile *force_tiles;     // force-pass tiles (64 particles)
     Tile *part_tiles;      // 256-particle tiles for elementwise kernels
+    Tile *real_tiles;      // real-space tiles (aux 0: cell-sorted rows, 1: all pairs)
     int32_t *modes;        // [3][Mcap]
     double *mode_w;        // [Mcap] weights (S/p or explicit)
-    double *partial;       // [rho tiles][modes][2] (sized for the maximum over systems)
-    int32_t *partial_off;  // [R] first partial row of each system
+    double *partial;       // structure-factor tile partials
+    int32_t *partial_off;  // [2R]: first partial row of each system, then its tile count
     double *rho;           // [Mcap][2] structure factors
     double *ab;            // [Mcap][2] adjoint reductions (A_l, B_l)
     void *kmode;           // KModeF[Mcap] or KModeD[Mcap]
     void *kvjp;            // KVjpF[Mcap] or KVjpD[Mcap]
     double *cdf;           // concatenated cumulative tables
     int32_t *mh_state;     // [R][3]
-    int32_t *cell_count;   // [ncell_tot]
+    int32_t *cell_count;   // [ncell_tot] (cell offsets padded to multiples of 4)
     int32_t *cell_start;   // [ncell_tot + R]
     int32_t *cellid;       // [Ntot] global cell of each particle
     int32_t *rank;         // [Ntot]
     int32_t *sorted_idx;   // [Ntot] particle at each sorted slot
     void *packed;          // [Ntot] wrapped position + charge, original order
     void *sorted;          // [Ntot] same, sorted by cell
-    double *energy_part;   // [part tiles][8]
-    int32_t *flag;         // [1] non-finite flag
+    double *energy_part;   // [real tiles][8]
+    int32_t *flag;         // [4] bit 0: non-finite force
 };
 
-// ---- launchers implemented in rbe_kernels.hip ----
 struct LaunchCfg {
     hipStream_t stream;
     int R;
     int prec;
     int64_t ntot;
     int mcap;
-    int n_rho_tiles, n_force_tiles, n_part_tiles;
+    int n_rho_tiles, n_force_tiles, n_part_tiles, n_real_tiles;
     int rho_chunk, rho_block, force_split, real_split;
     int ncell_tot;
     int max_cells;   // largest cell count of one system
     int max_p;
+    int max_table;   // largest cumulative table (2M + 1)
 };
 
+// What one launch of the staging kernel does.
+struct StageRequest {
+    void *pos;
+    void *vel;
+    const void *force;
+    const void *q;
+    uint64_t step;         // integrator noise index
+    uint64_t sample_step;  // mode sample index
+    int integrate, bin, sample, rho;
+};
+
+// ---- launchers (rbe_kspace.hip, rbe_real.hip) ----
 hipError_t launch_sample(const LaunchCfg &c, const Workspace &w, uint64_t step, int use_mh);
-hipError_t launch_set_weights(const LaunchCfg &c, const Workspace &w);
-hipError_t launch_rho(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q);
-hipError_t launch_rho_final(const LaunchCfg &c, const Workspace &w);
+hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageRequest &rq);
+size_t stage_lds_bytes(const LaunchCfg &c, int sample_in_kernel, int *table_lds, int *tab_max);
+hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan);
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
-                         int accumulate);
-hipError_t launch_bin(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q);
-hipError_t launch_scan(const LaunchCfg &c, const Workspace &w);
+                         int accumulate, int scatter);
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w);
-hipError_t launch_cellsort(const LaunchCfg &c, const Workspace &w);
 hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick);
-hipError_t launch_integrate(const LaunchCfg &c, const Workspace &w, void *pos, void *vel, const void *force,
-                            uint64_t step);
 hipError_t launch_energy(const LaunchCfg &c, const Workspace &w, const void *q, const void *vel);
 hipError_t launch_vjp_reduce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q,
                              const void *gF);
@@ -167,5 +171,7 @@ hipError_t launch_vjp_gather(const LaunchCfg &c, const Workspace &w, const void 
 hipError_t launch_vjp_real(const LaunchCfg &c, const Workspace &w, const void *gF, void *gpos, void *gq,
                            int accumulate);
 hipError_t launch_fill_zero(hipStream_t s, void *ptr, int64_t nbytes);
+int real_rows_per_tile();
+int real_allpairs_per_tile();
 
 }  // namespace rbe

@@ -1,0 +1,986 @@
+// rbe_kspace.hip -- Fourier-space kernels of librbe (gfx950).
+//
+// Paper: Jin, Li, Xu & Zhao, "A random batch Ewald method for particle
+// systems with Coulomb interactions", arXiv:2010.01559, Sec. 3.1.
+//
+// The random batch force (eq. 3.6) with k = 2 pi m / L reads
+//   F_i = -q_i sum_l a_l (cos th_il S_l - sin th_il C_l),
+//   a_l = coulomb w_l 2 m_l / (L^2 |m_l|^2),  th_il = 2 pi m_l . r_i / L,
+//   rho_l = C_l + i S_l = sum_j q_j exp(i th_jl)       (eq. 2.7)
+// with w_l = S/p for sampled modes.  Only integer modes and one scalar per
+// mode enter; every phase is formed in double and wrapped to [-1/2, 1/2]
+// revolutions before the single-precision sine/cosine.
+//
+// Kernels:
+//   k_sample_exact  draw the modes of every system (standalone call)
+//   k_sample_mh     the paper's Metropolis-Hastings chains
+//   k_stage_rho     [integrate] + [bin] + [draw modes] + structure-factor
+//                   partials per particle chunk  (one launch)
+//   k_mid           structure-factor totals + per-mode force constants, and
+//                   the exclusive scan of the cell counts (one launch)
+//   k_kforce        force pass + [scatter into cell order] (one launch)
+//   k_vjp_*         adjoint of the force at a fixed mode sample
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "rbe_device.h"
+#include "rbe_internal.h"
+
+namespace rbe {
+
+// ---------------------------------------------------------------------------
+// Sampling (Sec. 3.1, eqs. 3.3-3.5)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sample_exact(const SysDev *__restrict__ sys, const double *__restrict__ cdf,
+                                                      int32_t *__restrict__ modes, double *__restrict__ mode_w,
+                                                      int mcap, uint64_t step, int table_lds)
+{
+    extern __shared__ double tab[];
+    const SysDev S = sys[blockIdx.y];
+    const int K = 2 * S.M + 1;
+    const double *t = cdf + S.cdf_off;
+    if (table_lds) {
+        for (int k = threadIdx.x; k < K; k += blockDim.x) tab[k] = t[k];
+        __syncthreads();
+        t = tab;
+    }
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= S.p) return;
+    int mx, my, mz;
+    sample_mode(t, S.M, (uint32_t)l, S.seed, step, mx, my, mz);
+    const int o = S.moff + l;
+    modes[o] = mx;
+    modes[mcap + o] = my;
+    modes[2 * mcap + o] = mz;
+    mode_w[o] = S.S / (double)S.p;
+}
+
+// Proposal mass of eq. (3.5): P(round(x*) = m) for x* ~ N(0, alpha L^2/(2 pi^2)).
+__device__ double mh_qbar(double w, int m)
+{
+    const int am = m < 0 ? -m : m;
+    if (am == 0) return erf(0.5 / w);
+    return 0.5 * (erf((am + 0.5) / w) - erf((am - 0.5) / w));
+}
+
+// One wave per system, lanes 0..2 the three component chains, whose states
+// persist in the context.  Attempt a of draw l: lane d uses Philox block
+// (l, TAG_MH | 4a + d, step) for its Box-Muller proposal and word d of block
+// (l, TAG_MH | 4a + 3, step) as its acceptance uniform; the all-zero vector
+// is discarded.
+__global__ __launch_bounds__(64) void k_sample_mh(const SysDev *__restrict__ sys, int32_t *__restrict__ state,
+                                                  int32_t *__restrict__ modes, double *__restrict__ mode_w,
+                                                  int mcap, uint64_t step)
+{
+    const SysDev S = sys[blockIdx.x];
+    const int d = threadIdx.x;
+    const double a2 = kPi * kPi / (S.alpha * S.L * S.L);
+    const double sd = sqrt(S.alpha * S.L * S.L / (2.0 * kPi * kPi));
+    const double w = sqrt(S.alpha * S.L * S.L / (kPi * kPi));
+    int cur = d < 3 ? state[S.mh_state_off + d] : 1;
+    for (int l = 0; l < S.p; ++l) {
+        for (uint32_t a = 0; a < (1u << 20); ++a) {
+            const U4 acc = draw((uint32_t)l, kTagMH | (4u * a + 3u), S.seed, step);
+            if (d < 3) {
+                const U4 r = draw((uint32_t)l, kTagMH | (4u * a + (uint32_t)d), S.seed, step);
+                const double u1 = 1.0 - u53(r.x, r.y), u2 = u53(r.z, r.w);
+                const double x = sd * sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+                const int ms = x >= 0.0 ? (int)floor(x + 0.5) : -(int)floor(-x + 0.5);
+                const double ratio =
+                    exp(-a2 * ((double)ms * ms - (double)cur * cur)) * mh_qbar(w, cur) / mh_qbar(w, ms);
+                const uint32_t word = d == 0 ? acc.x : (d == 1 ? acc.y : acc.z);
+                if ((double)word * (1.0 / 4294967296.0) < ratio) cur = ms;
+            }
+            if (__ballot(d < 3 && cur != 0)) break;
+        }
+        if (d < 3) modes[d * mcap + S.moff + l] = cur;
+    }
+    if (d < 3) state[S.mh_state_off + d] = cur;
+    if (d == 0)
+        for (int l = 0; l < S.p; ++l) mode_w[S.moff + l] = S.S / (double)S.p;
+}
+
+// ---------------------------------------------------------------------------
+// k_stage_rho: one block per particle chunk of one system.
+//  1. (integrate) BAOA of the Langevin step (reading: BAOAB) or the leapfrog
+//     + Andersen update, positions wrapped into [0, L), arithmetic in double;
+//  2. (bin) cell index, atomic rank within the cell and the packed record;
+//  3. stage fractional coordinates + charge of the chunk in LDS;
+//  4. (sample) draw the system's modes into LDS (the cumulative table is
+//     staged in LDS when small); the first chunk of the system publishes them;
+//  5. structure-factor partials: each thread owns one mode and one residue
+//     class g of the chunk (G = blockDim / P classes); per-thread sums are
+//     blocked in T over runs of 8 particles and folded into double; the G
+//     partials of a mode are combined in LDS in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StageArgs {
+    const SysDev *sys;
+    const Tile *tiles;
+    T *pos;
+    T *vel;
+    const T *F;
+    const T *q;
+    int64_t ntot;
+    const double *cdf;
+    int32_t *modes;
+    double *mode_w;
+    int mcap;
+    double *partial;
+    const int32_t *part_off;
+    int32_t *count;
+    int32_t *cellid;
+    int32_t *rank;
+    void *packed;
+    uint64_t step;         // integrator noise index
+    uint64_t sample_step;  // mode sample index
+    int do_integrate, do_bin, do_sample, table_lds, do_rho;
+    int chunk;
+    int tab_max;           // LDS doubles reserved for the table
+};
+
+template <typename T>
+__device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i, int64_t ntot, T *pos, T *vel,
+                                              const T *F, uint64_t step, double x[3])
+{
+    double xi[3];
+    if (S.integrator == RBE_LANGEVIN_BAOAB) {
+        normals3((uint32_t)il, S.seed, step, xi);
+        const double h = 0.5 * S.dt;
+        for (int d = 0; d < 3; ++d) {
+            const int64_t k = d * ntot + i;
+            double v = (double)vel[k] + h * (double)F[k] / S.mass;  // B
+            double r = (double)pos[k] + h * v;                      // A
+            v = S.c1 * v + S.c2 * xi[d];                            // O
+            r += h * v;                                             // A
+            r -= S.L * floor(r * S.invL);
+            T rs = (T)r;
+            if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
+            pos[k] = rs;
+            vel[k] = (T)v;
+            x[d] = (double)rs;
+        }
+    } else {
+        const U4 w = draw((uint32_t)il, kTagAndersen, S.seed, step);
+        const bool hit = (double)w.x * (1.0 / 4294967296.0) < S.nu_dt;
+        if (hit) normals3((uint32_t)il, S.seed, step, xi);
+        const double sv = sqrt(S.kT / S.mass);
+        for (int d = 0; d < 3; ++d) {
+            const int64_t k = d * ntot + i;
+            const double v = (double)vel[k] + S.dt * (double)F[k] / S.mass;
+            double r = (double)pos[k] + S.dt * v;
+            r -= S.L * floor(r * S.invL);
+            T rs = (T)r;
+            if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
+            pos[k] = rs;
+            vel[k] = (T)(hit ? sv * xi[d] : v);
+            x[d] = (double)rs;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bin_one(const SysDev &S, int64_t i, double sx, double sy, double sz, T qi,
+                                        int32_t *count, int32_t *cellid, int32_t *rank, void *packed)
+{
+    int cx, cy, cz;
+    if constexpr (sizeof(T) == 4) {
+        const PackF v{to_fix(sx), to_fix(sy), to_fix(sz), (float)qi};
+        reinterpret_cast<PackF *>(packed)[i] = v;
+        cx = cell_of_fix(v.x, S.nc);
+        cy = cell_of_fix(v.y, S.nc);
+        cz = cell_of_fix(v.z, S.nc);
+    } else {
+        reinterpret_cast<PartD *>(packed)[i] = PartD{sx, sy, sz, (double)qi};
+        cx = cell_of_frac(sx, S.nc);
+        cy = cell_of_frac(sy, S.nc);
+        cz = cell_of_frac(sz, S.nc);
+    }
+    const int c = S.cell_off + (cz * S.nc + cy) * S.nc + cx;
+    cellid[i] = c;
+    rank[i] = atomicAdd(&count[c], 1);
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = a.tiles[blockIdx.x];
+    const SysDev S = a.sys[t.sys];
+    PartD *sp = reinterpret_cast<PartD *>(smem);
+    double2 *red = reinterpret_cast<double2 *>(smem + sizeof(PartD) * a.chunk);
+    double *tab = reinterpret_cast<double *>(red + BS);
+    int *smode = reinterpret_cast<int *>(tab + a.tab_max);  // [3][BS]
+    const int tid = threadIdx.x;
+    const int count = t.count;
+    const int K = 2 * S.M + 1;
+    if (a.do_sample && a.table_lds)
+        for (int k = tid; k < K; k += BS) tab[k] = a.cdf[S.cdf_off + k];
+    for (int j = tid; j < count; j += BS) {
+        const int il = t.start + j;
+        const int64_t i = S.off + il;
+        double x[3];
+        if (a.do_integrate) {
+            integrate_one<T>(S, il, i, a.ntot, a.pos, a.vel, a.F, a.step, x);
+        } else {
+            x[0] = (double)a.pos[i];
+            x[1] = (double)a.pos[a.ntot + i];
+            x[2] = (double)a.pos[2 * a.ntot + i];
+        }
+        PartD v;
+        v.x = frac01(x[0] * S.invL);
+        v.y = frac01(x[1] * S.invL);
+        v.z = frac01(x[2] * S.invL);
+        const T qi = a.q[i];
+        v.q = (double)qi;
+        sp[j] = v;
+        if (a.do_bin) bin_one<T>(S, i, v.x, v.y, v.z, qi, a.count, a.cellid, a.rank, a.packed);
+    }
+    __syncthreads();
+    if (!a.do_rho) return;
+    const int P = S.p;
+    const int Pt = P < BS ? P : BS;
+    const int G = BS / Pt;
+    const double *tabp = a.table_lds ? tab : a.cdf + S.cdf_off;
+    double *prow = a.partial + 2 * ((int64_t)a.part_off[t.sys] + (int64_t)t.aux * P);
+    for (int m0 = 0; m0 < P; m0 += Pt) {
+        // modes of this tile into LDS: drawn here or read from the mode arrays
+        if (tid < Pt && m0 + tid < P) {
+            const int l = m0 + tid;
+            int mx, my, mz;
+            if (a.do_sample) {
+                sample_mode(tabp, S.M, (uint32_t)l, S.seed, a.sample_step, mx, my, mz);
+                if (t.aux == 0) {
+                    const int o = S.moff + l;
+                    a.modes[o] = mx;
+                    a.modes[a.mcap + o] = my;
+                    a.modes[2 * a.mcap + o] = mz;
+                    a.mode_w[o] = S.S / (double)P;
+                }
+            } else {
+                const int o = S.moff + l;
+                mx = a.modes[o];
+                my = a.modes[a.mcap + o];
+                mz = a.modes[2 * a.mcap + o];
+            }
+            smode[tid] = mx;
+            smode[BS + tid] = my;
+            smode[2 * BS + tid] = mz;
+        }
+        __syncthreads();
+        const int lt = tid % Pt, g = tid / Pt;
+        const int l = m0 + lt;
+        const bool act = g < G && l < P;
+        double C = 0.0, Sn = 0.0;
+        if (act) {
+            const double mx = (double)smode[lt], my = (double)smode[BS + lt], mz = (double)smode[2 * BS + lt];
+            for (int j0 = g; j0 < count; j0 += 8 * G) {
+                T c8 = 0, s8 = 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int j = j0 + u * G;
+                    if (j < count) {
+                        const PartD v = sp[j];
+                        const double ph = wrap_rev(fma(mx, v.x, fma(my, v.y, mz * v.z)));
+                        T sn, cs;
+                        sincos_rev(ph, &sn, &cs);
+                        const T qq = (T)v.q;
+                        c8 = fma(qq, cs, c8);
+                        s8 = fma(qq, sn, s8);
+                    }
+                }
+                C += (double)c8;
+                Sn += (double)s8;
+            }
+        }
+        red[tid] = make_double2(C, Sn);
+        __syncthreads();
+        if (tid < Pt && l < P) {
+            double c = 0.0, s = 0.0;
+            for (int gg = 0; gg < G; ++gg) {
+                const double2 v = red[gg * Pt + lt];
+                c += v.x;
+                s += v.y;
+            }
+            prow[2 * l] = c;
+            prow[2 * l + 1] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_mid: two independent jobs in one launch.
+//  * final structure factors: one wave per (system, mode) adds the tile
+//    partials in a fixed order and fills the per-mode force constants;
+//  * cell scan: one block per system turns the cell counts into global slot
+//    starts (exclusive prefix + S.off) and clears the counts.
+// ---------------------------------------------------------------------------
+template <typename KM>
+struct MidArgs {
+    const SysDev *sys;
+    int R, max_p;
+    int n_final_blocks;   // blocks doing the structure-factor totals
+    const double *partial;
+    const int32_t *part_off;   // [2R]: partial offsets, then tile counts
+    const int32_t *modes;
+    const double *mode_w;
+    int mcap;
+    double *rho;
+    KM *km;
+    int32_t *count;
+    int32_t *start;
+    int do_scan;
+};
+
+template <typename KM>
+__device__ void mid_final(const MidArgs<KM> &a, int gm)
+{
+    const int r = gm / a.max_p, l = gm % a.max_p;
+    if (r >= a.R) return;
+    const SysDev S = a.sys[r];
+    if (l >= S.p) return;
+    const int nt = a.part_off[a.R + r];
+    const double *base = a.partial + 2 * (int64_t)a.part_off[r];
+    const int lane = threadIdx.x & 63;
+    double c = 0.0, s = 0.0;
+    for (int t = lane; t < nt; t += 64) {
+        c += base[2 * ((int64_t)t * S.p + l)];
+        s += base[2 * ((int64_t)t * S.p + l) + 1];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, 64);
+        s += __shfl_down(s, off, 64);
+    }
+    if (lane == 0) {
+        const int o = S.moff + l;
+        a.rho[2 * o] = c;
+        a.rho[2 * o + 1] = s;
+        const double mx = a.modes[o], my = a.modes[a.mcap + o], mz = a.modes[2 * a.mcap + o];
+        const double m2 = mx * mx + my * my + mz * mz;
+        const double f = S.coulomb * a.mode_w[o] * 2.0 / (S.L * S.L * m2);
+        KM k;
+        k.m[0] = mx;
+        k.m[1] = my;
+        k.m[2] = mz;
+        k.a[0] = f * mx;
+        k.a[1] = f * my;
+        k.a[2] = f * mz;
+        k.C = c;
+        k.S = s;
+        if constexpr (sizeof(KM) == sizeof(KModeF)) k.pad = 0.0f;
+        a.km[o] = k;
+    }
+}
+
+// Exclusive scan of one system's cell counts with 1024 threads.  Cells are
+// processed in passes of 8 chunks x 4096; thread t owns cells
+// [base + g*4096 + 4t, +4) of chunk g.  Cell offsets are padded to multiples
+// of 4 so the counts load as int4.
+constexpr int kScanChunks = 8;
+
+__device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
+{
+    __shared__ int wtot[kScanChunks * 16];
+    __shared__ int gpre[kScanChunks * 16 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int32_t *cnt = count + S.cell_off;
+    int32_t *st = start + S.cell_off + r;
+    const int ncell = S.ncell;
+    int carry = 0;
+    for (int base = 0; base < ncell; base += kScanChunks * 4096) {
+        int v[kScanChunks][4];
+        int s[kScanChunks], incl[kScanChunks];
+#pragma unroll
+        for (int g = 0; g < kScanChunks; ++g) {
+            const int idx = base + g * 4096 + 4 * tid;
+            if (idx + 3 < ncell) {
+                const int4 x = *reinterpret_cast<const int4 *>(cnt + idx);
+                v[g][0] = x.x;
+                v[g][1] = x.y;
+                v[g][2] = x.z;
+                v[g][3] = x.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[g][j] = (idx + j < ncell) ? cnt[idx + j] : 0;
+            }
+            s[g] = v[g][0] + v[g][1] + v[g][2] + v[g][3];
+        }
+#pragma unroll
+        for (int g = 0; g < kScanChunks; ++g) {
+            incl[g] = wave_incl_scan(s[g]);
+            if (lane == 63) wtot[g * 16 + wave] = incl[g];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // exclusive prefix of the 128 wave totals in (chunk, wave) order
+            const int x0 = wtot[2 * lane], x1 = wtot[2 * lane + 1];
+            const int inc = wave_incl_scan(x0 + x1);
+            gpre[2 * lane] = inc - x0 - x1;
+            gpre[2 * lane + 1] = inc - x1;
+            if (lane == 63) gpre[kScanChunks * 16] = inc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < kScanChunks; ++g) {
+            const int idx = base + g * 4096 + 4 * tid;
+            int run = S.off + carry + gpre[g * 16 + wave] + incl[g] - s[g];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (idx + j < ncell) {
+                    st[idx + j] = run;
+                    run += v[g][j];
+                    cnt[idx + j] = 0;
+                }
+            }
+        }
+        carry += gpre[kScanChunks * 16];
+        __syncthreads();
+    }
+    if (tid == 0) st[ncell] = S.off + carry;
+}
+
+template <typename KM>
+__global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
+{
+    if ((int)blockIdx.x < a.n_final_blocks) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        mid_final<KM>(a, blockIdx.x * 16 + wave);
+        return;
+    }
+    if (!a.do_scan) return;
+    const int r = blockIdx.x - a.n_final_blocks;
+    mid_scan(a.sys[r], r, a.count, a.start);
+}
+
+// ---------------------------------------------------------------------------
+// k_kforce: one lane per particle; a block holds 4 waves, each group of
+// SPLIT waves shares one 64-particle tile and splits its modes; partial
+// forces are combined in LDS in a fixed order.  Mode constants are
+// wave-uniform scalar loads.  With scatter on, the lane also moves its
+// particle record into cell order (slot = cell start + rank).
+// ---------------------------------------------------------------------------
+template <typename T, typename KM>
+struct ForceArgs {
+    const SysDev *sys;
+    const Tile *tiles;
+    int ntiles;
+    const T *pos;
+    const T *q;
+    int64_t ntot;
+    const KM *km;
+    T *F;
+    int accumulate;
+    int32_t *flag;
+    // scatter
+    int do_scatter;
+    const int32_t *start;
+    const int32_t *cellid;
+    const int32_t *rank;
+    const void *packed;
+    int32_t *sorted_idx;
+    void *sorted;
+};
+
+template <typename T, typename KM, int SPLIT>
+__global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
+{
+    __shared__ T red[4][3][64];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int group = wave / SPLIT, part = wave % SPLIT;
+    const int ti = blockIdx.x * (4 / SPLIT) + group;
+    T fx = 0, fy = 0, fz = 0;
+    int64_t i = -1;
+    T qi = 0;
+    int sysi = 0;
+    if (ti < a.ntiles) {
+        const Tile t = a.tiles[ti];
+        sysi = t.sys;
+        const SysDev S = a.sys[t.sys];
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        if (lane < t.count) {
+            i = S.off + t.start + lane;
+            sx = frac01((double)a.pos[i] * S.invL);
+            sy = frac01((double)a.pos[a.ntot + i] * S.invL);
+            sz = frac01((double)a.pos[2 * a.ntot + i] * S.invL);
+            qi = a.q[i];
+        }
+        const int l0 = (S.p * part) / SPLIT, l1 = (S.p * (part + 1)) / SPLIT;
+        const KM *kk = a.km + S.moff;
+#pragma unroll 4
+        for (int l = l0; l < l1; ++l) {
+            const KM k = kk[l];
+            const double ph = wrap_rev(fma(k.m[0], sx, fma(k.m[1], sy, k.m[2] * sz)));
+            T sn, cs;
+            sincos_rev(ph, &sn, &cs);
+            const T im = cs * (T)k.S - sn * (T)k.C;
+            fx = fma(im, (T)k.a[0], fx);
+            fy = fma(im, (T)k.a[1], fy);
+            fz = fma(im, (T)k.a[2], fz);
+        }
+    }
+    if constexpr (SPLIT > 1) {
+        red[wave][0][lane] = fx;
+        red[wave][1][lane] = fy;
+        red[wave][2][lane] = fz;
+        __syncthreads();
+        if (part != 0) return;
+        for (int s = 1; s < SPLIT; ++s) {
+            fx += red[wave + s][0][lane];
+            fy += red[wave + s][1][lane];
+            fz += red[wave + s][2][lane];
+        }
+    }
+    if (i < 0) return;
+    fx *= -qi;
+    fy *= -qi;
+    fz *= -qi;
+    if (!isfinite(fx + fy + fz)) atomicOr(a.flag, 1);
+    if (a.accumulate) {
+        fx += a.F[i];
+        fy += a.F[a.ntot + i];
+        fz += a.F[2 * a.ntot + i];
+    }
+    a.F[i] = fx;
+    a.F[a.ntot + i] = fy;
+    a.F[2 * a.ntot + i] = fz;
+    if (a.do_scatter) {
+        const int slot = a.start[a.cellid[i] + sysi] + a.rank[i];
+        a.sorted_idx[slot] = (int32_t)i;
+        if constexpr (sizeof(T) == 4)
+            reinterpret_cast<PackF *>(a.sorted)[slot] = reinterpret_cast<const PackF *>(a.packed)[i];
+        else
+            reinterpret_cast<PartD *>(a.sorted)[slot] = reinterpret_cast<const PartD *>(a.packed)[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the force at a fixed mode sample.  With G_i = dLoss/dF_i,
+//   w_il = G_i . a_l,  A_l = sum_i q_i w_il cos th_il,  B_l = sum_i q_i w_il sin th_il,
+//   dLoss/dq_i = -sum_l [w_il (cos th S_l - sin th C_l) + A_l sin th - B_l cos th],
+//   dLoss/dr_i = q_i sum_l k_l [w_il (sin th S_l + cos th C_l) - A_l cos th - B_l sin th],
+// k_l = 2 pi m_l / L.  The (A, B) reduction has the shape of the structure
+// factor and reuses its tiling; the gather has the shape of the force pass.
+// ---------------------------------------------------------------------------
+struct alignas(16) PartG {
+    double x, y, z, gx, gy, gz;   // fractional position and q_i G_i
+};
+
+template <typename T, typename KM, int BS>
+__global__ __launch_bounds__(BS) void k_vjp_reduce(const SysDev *__restrict__ sys, const Tile *__restrict__ tiles,
+                                                   const T *__restrict__ pos, const T *__restrict__ q,
+                                                   const T *__restrict__ gF, int64_t ntot,
+                                                   const KM *__restrict__ km, double *__restrict__ partial,
+                                                   const int32_t *__restrict__ part_off)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const SysDev S = sys[t.sys];
+    PartG *sp = reinterpret_cast<PartG *>(smem);
+    double2 *red = reinterpret_cast<double2 *>(smem + sizeof(PartG) * t.count);
+    const int tid = threadIdx.x;
+    const int count = t.count;
+    for (int j = tid; j < count; j += BS) {
+        const int64_t i = S.off + t.start + j;
+        const double qi = (double)q[i];
+        PartG v;
+        v.x = frac01((double)pos[i] * S.invL);
+        v.y = frac01((double)pos[ntot + i] * S.invL);
+        v.z = frac01((double)pos[2 * ntot + i] * S.invL);
+        v.gx = qi * (double)gF[i];
+        v.gy = qi * (double)gF[ntot + i];
+        v.gz = qi * (double)gF[2 * ntot + i];
+        sp[j] = v;
+    }
+    __syncthreads();
+    const int P = S.p;
+    const int Pt = P < BS ? P : BS;
+    const int G = BS / Pt;
+    double *prow = partial + 2 * ((int64_t)part_off[t.sys] + (int64_t)t.aux * P);
+    for (int m0 = 0; m0 < P; m0 += Pt) {
+        const int lt = tid % Pt, g = tid / Pt;
+        const int l = m0 + lt;
+        const bool act = g < G && l < P;
+        double A = 0.0, B = 0.0;
+        if (act) {
+            const KM k = km[S.moff + l];
+            const T ax = (T)k.a[0], ay = (T)k.a[1], az = (T)k.a[2];
+            for (int j0 = g; j0 < count; j0 += 8 * G) {
+                T a8 = 0, b8 = 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int j = j0 + u * G;
+                    if (j < count) {
+                        const PartG v = sp[j];
+                        const double ph = wrap_rev(fma(k.m[0], v.x, fma(k.m[1], v.y, k.m[2] * v.z)));
+                        T sn, cs;
+                        sincos_rev(ph, &sn, &cs);
+                        const T w = fma((T)v.gx, ax, fma((T)v.gy, ay, (T)v.gz * az));
+                        a8 = fma(w, cs, a8);
+                        b8 = fma(w, sn, b8);
+                    }
+                }
+                A += (double)a8;
+                B += (double)b8;
+            }
+        }
+        red[tid] = make_double2(A, B);
+        __syncthreads();
+        if (tid < Pt && l < P) {
+            double av = 0.0, bv = 0.0;
+            for (int gg = 0; gg < G; ++gg) {
+                const double2 v = red[gg * Pt + lt];
+                av += v.x;
+                bv += v.y;
+            }
+            prow[2 * l] = av;
+            prow[2 * l + 1] = bv;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename KM, typename KV>
+__global__ __launch_bounds__(64) void k_vjp_final(const SysDev *__restrict__ sys, const double *__restrict__ partial,
+                                                  const int32_t *__restrict__ part_off, int R,
+                                                  const KM *__restrict__ km, double *__restrict__ ab,
+                                                  KV *__restrict__ kv)
+{
+    const int r = blockIdx.y;
+    const SysDev S = sys[r];
+    const int l = blockIdx.x;
+    if (l >= S.p) return;
+    const int nt = part_off[R + r];
+    const double *base = partial + 2 * (int64_t)part_off[r];
+    double av = 0.0, bv = 0.0;
+    for (int t = threadIdx.x; t < nt; t += 64) {
+        av += base[2 * ((int64_t)t * S.p + l)];
+        bv += base[2 * ((int64_t)t * S.p + l) + 1];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        av += __shfl_down(av, off, 64);
+        bv += __shfl_down(bv, off, 64);
+    }
+    if (threadIdx.x == 0) {
+        const int o = S.moff + l;
+        ab[2 * o] = av;
+        ab[2 * o + 1] = bv;
+        const KM k = km[o];
+        KV v;
+        const double tp = 2.0 * kPi * S.invL;
+        for (int d = 0; d < 3; ++d) {
+            v.m[d] = k.m[d];
+            v.a[d] = k.a[d];
+            v.k[d] = tp * k.m[d];
+        }
+        v.C = k.C;
+        v.S = k.S;
+        v.A = av;
+        v.B = bv;
+        if constexpr (sizeof(KV) == sizeof(KVjpF)) v.pad[0] = v.pad[1] = v.pad[2] = 0.0f;
+        kv[o] = v;
+    }
+}
+
+template <typename T, typename KV, int SPLIT>
+__global__ __launch_bounds__(256) void k_vjp_gather(const SysDev *__restrict__ sys, const Tile *__restrict__ tiles,
+                                                    int ntiles, const T *__restrict__ pos, const T *__restrict__ q,
+                                                    const T *__restrict__ gF, int64_t ntot,
+                                                    const KV *__restrict__ kv, T *__restrict__ gpos,
+                                                    T *__restrict__ gq)
+{
+    __shared__ T red[4][4][64];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int group = wave / SPLIT, part = wave % SPLIT;
+    const int ti = blockIdx.x * (4 / SPLIT) + group;
+    T dq = 0, rx = 0, ry = 0, rz = 0;
+    int64_t i = -1;
+    T qi = 0;
+    if (ti < ntiles) {
+        const Tile t = tiles[ti];
+        const SysDev S = sys[t.sys];
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        T gx = 0, gy = 0, gz = 0;
+        if (lane < t.count) {
+            i = S.off + t.start + lane;
+            sx = frac01((double)pos[i] * S.invL);
+            sy = frac01((double)pos[ntot + i] * S.invL);
+            sz = frac01((double)pos[2 * ntot + i] * S.invL);
+            qi = q[i];
+            gx = gF[i];
+            gy = gF[ntot + i];
+            gz = gF[2 * ntot + i];
+        }
+        const int l0 = (S.p * part) / SPLIT, l1 = (S.p * (part + 1)) / SPLIT;
+        const KV *kk = kv + S.moff;
+#pragma unroll 2
+        for (int l = l0; l < l1; ++l) {
+            const KV k = kk[l];
+            const double ph = wrap_rev(fma(k.m[0], sx, fma(k.m[1], sy, k.m[2] * sz)));
+            T sn, cs;
+            sincos_rev(ph, &sn, &cs);
+            const T w = fma(gx, (T)k.a[0], fma(gy, (T)k.a[1], gz * (T)k.a[2]));
+            const T Ck = (T)k.C, Sk = (T)k.S, Ak = (T)k.A, Bk = (T)k.B;
+            dq -= fma(w, cs * Sk - sn * Ck, Ak * sn - Bk * cs);
+            const T tt = fma(w, sn * Sk + cs * Ck, -(Ak * cs + Bk * sn));
+            rx = fma(tt, (T)k.k[0], rx);
+            ry = fma(tt, (T)k.k[1], ry);
+            rz = fma(tt, (T)k.k[2], rz);
+        }
+    }
+    if constexpr (SPLIT > 1) {
+        red[wave][0][lane] = dq;
+        red[wave][1][lane] = rx;
+        red[wave][2][lane] = ry;
+        red[wave][3][lane] = rz;
+        __syncthreads();
+        if (part != 0) return;
+        for (int s = 1; s < SPLIT; ++s) {
+            dq += red[wave + s][0][lane];
+            rx += red[wave + s][1][lane];
+            ry += red[wave + s][2][lane];
+            rz += red[wave + s][3][lane];
+        }
+    }
+    if (i < 0) return;
+    gq[i] = dq;
+    gpos[i] = qi * rx;
+    gpos[ntot + i] = qi * ry;
+    gpos[2 * ntot + i] = qi * rz;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_sample(const LaunchCfg &c, const Workspace &w, uint64_t step, int use_mh)
+{
+    if (use_mh) {
+        k_sample_mh<<<dim3(c.R), dim3(64), 0, c.stream>>>(w.sys, w.mh_state, w.modes, w.mode_w, c.mcap, step);
+    } else {
+        const int table_lds = c.max_table <= 8192 ? 1 : 0;
+        const size_t sm = table_lds ? sizeof(double) * c.max_table : 0;
+        dim3 g((c.max_p + 255) / 256, c.R);
+        k_sample_exact<<<g, dim3(256), sm, c.stream>>>(w.sys, w.cdf, w.modes, w.mode_w, c.mcap, step, table_lds);
+    }
+    return hipGetLastError();
+}
+
+size_t stage_lds_bytes(const LaunchCfg &c, int sample_in_kernel, int *table_lds, int *tab_max)
+{
+    size_t base = sizeof(PartD) * c.rho_chunk + sizeof(double2) * c.rho_block + sizeof(int) * 3 * c.rho_block;
+    *table_lds = 0;
+    *tab_max = 0;
+    if (sample_in_kernel && base + sizeof(double) * c.max_table <= 64 * 1024) {
+        *table_lds = 1;
+        *tab_max = c.max_table;
+    }
+    return base + sizeof(double) * (*tab_max);
+}
+
+template <typename T>
+static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const StageRequest &rq)
+{
+    StageArgs<T> a;
+    a.sys = w.sys;
+    a.tiles = w.rho_tiles;
+    a.pos = (T *)rq.pos;
+    a.vel = (T *)rq.vel;
+    a.F = (const T *)rq.force;
+    a.q = (const T *)rq.q;
+    a.ntot = c.ntot;
+    a.cdf = w.cdf;
+    a.modes = w.modes;
+    a.mode_w = w.mode_w;
+    a.mcap = c.mcap;
+    a.partial = w.partial;
+    a.part_off = w.partial_off;
+    a.count = w.cell_count;
+    a.cellid = w.cellid;
+    a.rank = w.rank;
+    a.packed = w.packed;
+    a.step = rq.step;
+    a.sample_step = rq.sample_step;
+    a.do_integrate = rq.integrate;
+    a.do_bin = rq.bin;
+    a.do_sample = rq.sample;
+    a.do_rho = rq.rho;
+    a.chunk = c.rho_chunk;
+    int table_lds, tab_max;
+    const size_t sm = stage_lds_bytes(c, rq.sample, &table_lds, &tab_max);
+    a.table_lds = table_lds;
+    a.tab_max = tab_max;
+    dim3 g(c.n_rho_tiles);
+    switch (c.rho_block) {
+    case 256:
+        k_stage_rho<T, 256><<<g, 256, sm, c.stream>>>(a);
+        break;
+    case 512:
+        k_stage_rho<T, 512><<<g, 512, sm, c.stream>>>(a);
+        break;
+    default:
+        k_stage_rho<T, 1024><<<g, 1024, sm, c.stream>>>(a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageRequest &rq)
+{
+    return c.prec == RBE_FP64 ? stage_dispatch<double>(c, w, rq) : stage_dispatch<float>(c, w, rq);
+}
+
+template <typename KM>
+static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan)
+{
+    MidArgs<KM> a;
+    a.sys = w.sys;
+    a.R = c.R;
+    a.max_p = c.max_p;
+    a.n_final_blocks = do_final ? (c.R * c.max_p + 15) / 16 : 0;
+    a.partial = w.partial;
+    a.part_off = w.partial_off;
+    a.modes = w.modes;
+    a.mode_w = w.mode_w;
+    a.mcap = c.mcap;
+    a.rho = w.rho;
+    a.km = (KM *)w.kmode;
+    a.count = w.cell_count;
+    a.start = w.cell_start;
+    a.do_scan = do_scan;
+    const int nb = a.n_final_blocks + (do_scan ? c.R : 0);
+    if (nb == 0) return hipSuccess;
+    k_mid<KM><<<nb, 1024, 0, c.stream>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan)
+{
+    return c.prec == RBE_FP64 ? mid_dispatch<KModeD>(c, w, do_final, do_scan)
+                              : mid_dispatch<KModeF>(c, w, do_final, do_scan);
+}
+
+template <typename T, typename KM>
+static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *F,
+                                  int acc, int scatter)
+{
+    ForceArgs<T, KM> a;
+    a.sys = w.sys;
+    a.tiles = w.force_tiles;
+    a.ntiles = c.n_force_tiles;
+    a.pos = (const T *)pos;
+    a.q = (const T *)q;
+    a.ntot = c.ntot;
+    a.km = (const KM *)w.kmode;
+    a.F = (T *)F;
+    a.accumulate = acc;
+    a.flag = w.flag;
+    a.do_scatter = scatter;
+    a.start = w.cell_start;
+    a.cellid = w.cellid;
+    a.rank = w.rank;
+    a.packed = w.packed;
+    a.sorted_idx = w.sorted_idx;
+    a.sorted = w.sorted;
+    const int n = c.n_force_tiles;
+    switch (c.force_split) {
+    case 1:
+        k_kforce<T, KM, 1><<<(n + 3) / 4, 256, 0, c.stream>>>(a);
+        break;
+    case 2:
+        k_kforce<T, KM, 2><<<(n + 1) / 2, 256, 0, c.stream>>>(a);
+        break;
+    default:
+        k_kforce<T, KM, 4><<<n, 256, 0, c.stream>>>(a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
+                         int accumulate, int scatter)
+{
+    return c.prec == RBE_FP64 ? kforce_dispatch<double, KModeD>(c, w, pos, q, force, accumulate, scatter)
+                              : kforce_dispatch<float, KModeF>(c, w, pos, q, force, accumulate, scatter);
+}
+
+template <typename T, typename KM>
+static hipError_t vjp_reduce_dispatch(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q,
+                                      const void *gF)
+{
+    const size_t sm = sizeof(PartG) * c.rho_chunk + sizeof(double2) * c.rho_block;
+    const T *p = (const T *)pos, *qq = (const T *)q, *g = (const T *)gF;
+    const KM *km = (const KM *)w.kmode;
+    dim3 gr(c.n_rho_tiles);
+    switch (c.rho_block) {
+    case 256:
+        k_vjp_reduce<T, KM, 256><<<gr, 256, sm, c.stream>>>(w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
+                                                            w.partial_off);
+        break;
+    case 512:
+        k_vjp_reduce<T, KM, 512><<<gr, 512, sm, c.stream>>>(w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
+                                                            w.partial_off);
+        break;
+    default:
+        k_vjp_reduce<T, KM, 1024><<<gr, 1024, sm, c.stream>>>(w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
+                                                              w.partial_off);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_reduce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q,
+                             const void *gF)
+{
+    return c.prec == RBE_FP64 ? vjp_reduce_dispatch<double, KModeD>(c, w, pos, q, gF)
+                              : vjp_reduce_dispatch<float, KModeF>(c, w, pos, q, gF);
+}
+
+hipError_t launch_vjp_final(const LaunchCfg &c, const Workspace &w)
+{
+    dim3 g(c.max_p, c.R);
+    if (c.prec == RBE_FP64)
+        k_vjp_final<KModeD, KVjpD><<<g, 64, 0, c.stream>>>(w.sys, w.partial, w.partial_off, c.R,
+                                                           (const KModeD *)w.kmode, w.ab, (KVjpD *)w.kvjp);
+    else
+        k_vjp_final<KModeF, KVjpF><<<g, 64, 0, c.stream>>>(w.sys, w.partial, w.partial_off, c.R,
+                                                           (const KModeF *)w.kmode, w.ab, (KVjpF *)w.kvjp);
+    return hipGetLastError();
+}
+
+template <typename T, typename KV>
+static hipError_t vjp_gather_dispatch(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q,
+                                      const void *gF, void *gpos, void *gq)
+{
+    const T *p = (const T *)pos, *qq = (const T *)q, *g = (const T *)gF;
+    const KV *kv = (const KV *)w.kvjp;
+    const int n = c.n_force_tiles;
+    switch (c.force_split) {
+    case 1:
+        k_vjp_gather<T, KV, 1><<<(n + 3) / 4, 256, 0, c.stream>>>(w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv,
+                                                                  (T *)gpos, (T *)gq);
+        break;
+    case 2:
+        k_vjp_gather<T, KV, 2><<<(n + 1) / 2, 256, 0, c.stream>>>(w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv,
+                                                                  (T *)gpos, (T *)gq);
+        break;
+    default:
+        k_vjp_gather<T, KV, 4><<<n, 256, 0, c.stream>>>(w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv, (T *)gpos,
+                                                        (T *)gq);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_gather(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q,
+                             const void *gF, void *gpos, void *gq)
+{
+    return c.prec == RBE_FP64 ? vjp_gather_dispatch<double, KVjpD>(c, w, pos, q, gF, gpos, gq)
+                              : vjp_gather_dispatch<float, KVjpF>(c, w, pos, q, gF, gpos, gq);
+}
+
+}  // namespace rbe

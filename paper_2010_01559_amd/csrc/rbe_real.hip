@@ -1,0 +1,692 @@
+// rbe_real.hip -- real-space kernels of librbe (gfx950).
+//
+// Paper: Jin, Li, Xu & Zhao, arXiv:2010.01559: the truncated erfc sum of
+// eq. (2.9) and the second term of eq. (2.11); the shifted Lennard-Jones
+// repulsion of eq. (4.1) with r_off = 0.  The paper leaves the neighbour
+// search open; here it is a cell list with cells of side >= the largest
+// cutoff, rebuilt for every evaluation.
+//
+// Pair force on particle i: phi(r) d with d = r_j - r_i (minimum image),
+//   phi = -coulomb q_i q_j (erfc(beta r)/r + 2 beta exp(-alpha r^2)/sqrt(pi)) / r^2
+//         + 4 eps (6 (sigma/r)^6 - 12 (sigma/r)^12) / r^2        (r < R_c)
+// with beta = sqrt(alpha); the Coulomb part acts for r <= r_c.
+//
+// Work decomposition ("row lanes"): the 27-cell stencil of a particle is
+// nine rows of three x-adjacent cells, and each row is one lane.  A wave
+// holds seven particles x nine rows; the rows are contiguous ranges of the
+// cell-sorted particle array (two ranges where the row wraps in x), read
+// straight from global memory, where the array stays cache-resident.  A lane
+// first marks the partners within the largest cutoff in a 64-bit mask (a
+// cheap distance test, no branches) and then evaluates the pair terms over
+// the set bits, so the expensive terms do not diverge on the cutoff test.
+// Each lane accumulates its FP32 pair terms in double; the nine row sums are
+// added in a fixed order, so the result does not depend on the order of the
+// particles inside a cell (which comes from atomic counters) beyond double
+// rounding.  Systems with fewer than three cells per side use all-pairs tiles.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "rbe_device.h"
+#include "rbe_internal.h"
+
+namespace rbe {
+
+constexpr int RL_BS = 256;                  // threads per block: 4 waves
+constexpr int RL_PPW = 7;                   // particles per wave (9 lanes each)
+constexpr int RL_PPB = 4 * RL_PPW;          // particles per block
+constexpr int RL_ALLPAIRS = 256;            // particles per all-pairs tile
+
+int real_rows_per_tile() { return RL_PPB; }
+int real_allpairs_per_tile() { return RL_ALLPAIRS; }
+
+template <typename T>
+struct RBT;
+template <>
+struct RBT<float> {
+    using Rec = PackF;
+};
+template <>
+struct RBT<double> {
+    using Rec = PartD;
+};
+
+struct PairE {
+    double e_real, e_lj;
+};
+
+// Single-precision constants of one system's pair terms, held in registers.
+struct PairConstF {
+    float rc2, lj_rc2, beta, nalpha_log2e, two_beta_rsqrtpi, coulomb, lj_sig2, eps4, lj_shift;
+    int lj_on;
+};
+
+__device__ __forceinline__ PairConstF pair_const_f(const SysDev &S)
+{
+    PairConstF c;
+    c.rc2 = (float)S.rc2;
+    c.lj_rc2 = (float)S.lj_rc2;
+    c.beta = (float)S.beta;
+    c.nalpha_log2e = (float)(-S.alpha * 1.4426950408889634074);
+    c.two_beta_rsqrtpi = (float)(2.0 * S.beta / 1.7724538509055160273);
+    c.coulomb = (float)S.coulomb;
+    c.lj_sig2 = (float)S.lj_sig2;
+    c.eps4 = (float)(4.0 * S.lj_eps);
+    c.lj_shift = (float)S.lj_shift;
+    c.lj_on = S.lj_on;
+    return c;
+}
+
+// erfc(x) exp(x^2) = t * sum_k c_k t^k with t = 1/(1 + 0.47047 x), x >= 0: the
+// form of Abramowitz & Stegun 7.1.26 refitted to degree 9 for a relative
+// error of erfc below 4e-7 in single precision on [0, 8] (fit_erfc.py).
+__device__ __forceinline__ float erfc_scaled_f32(float x)
+{
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.47047f, x, 1.0f));
+    float s = -4.859511559e-02f;
+    s = fmaf(s, t, 2.750724646e-01f);
+    s = fmaf(s, t, -5.785352996e-01f);
+    s = fmaf(s, t, 4.823851487e-01f);
+    s = fmaf(s, t, -1.365632976e-01f);
+    s = fmaf(s, t, 2.525006764e-01f);
+    s = fmaf(s, t, 2.213245585e-01f);
+    s = fmaf(s, t, 2.670528048e-01f);
+    s = fmaf(s, t, 2.653580831e-01f);
+    return s * t;
+}
+
+// phi(r) of one pair in single precision (r2 = |d|^2 in box units); both
+// terms are evaluated and selected, so a wave does not branch on the
+// per-lane cutoff tests.  With ENERGY, half the pair energies are added to e.
+template <bool ENERGY>
+__device__ __forceinline__ float pair_phi(const PairConstF &c, float qi, float qj, float r2, PairE &e)
+{
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rinv2 = rinv * rinv;
+    const bool in_c = r2 <= c.rc2;
+    const bool in_lj = c.lj_on && r2 < c.lj_rc2;
+    const float r = r2 * rinv;
+    const float ex = __builtin_amdgcn_exp2f(c.nalpha_log2e * r2);   // exp(-alpha r^2)
+    const float ec = erfc_scaled_f32(c.beta * r) * ex;               // erfc(beta r)
+    const float g = fmaf(ec, rinv, c.two_beta_rsqrtpi * ex) * rinv2;
+    const float cq = c.coulomb * qi * qj;
+    const float sr2 = c.lj_sig2 * rinv2;
+    const float sr6 = sr2 * sr2 * sr2;
+    const float plj = c.eps4 * fmaf(-12.0f, sr6, 6.0f) * sr6 * rinv2;
+    if constexpr (ENERGY) {
+        if (in_c) e.e_real += 0.5 * (double)(cq * ec * rinv);
+        if (in_lj) e.e_lj += 0.5 * ((double)c.eps4 * ((double)sr6 * sr6 - sr6) + c.lj_shift);
+    }
+    return (in_c ? -cq * g : 0.0f) + (in_lj ? plj : 0.0f);
+}
+
+// The same in double precision (libm erfc/exp).
+template <bool ENERGY>
+__device__ __forceinline__ double pair_phi(const SysDev &S, double qi, double qj, double r2, PairE &e)
+{
+    double phi = 0.0;
+    if (r2 <= S.rc2) {
+        const double r = sqrt(r2);
+        const double ec = erfc(S.beta * r);
+        const double ex = exp(-S.alpha * r2);
+        const double g = (ec / r + 2.0 / 1.7724538509055160273 * S.beta * ex) / r2;
+        const double cq = S.coulomb * qi * qj;
+        phi = -cq * g;
+        if constexpr (ENERGY) e.e_real += 0.5 * cq * ec / r;
+    }
+    if (S.lj_on && r2 < S.lj_rc2) {
+        const double sr2 = S.lj_sig2 / r2;
+        const double sr6 = sr2 * sr2 * sr2;
+        phi += 4.0 * S.lj_eps * (6.0 * sr6 - 12.0 * sr6 * sr6) / r2;
+        if constexpr (ENERGY) e.e_lj += 0.5 * (4.0 * S.lj_eps * (sr6 * sr6 - sr6) + S.lj_shift);
+    }
+    return phi;
+}
+
+// Displacement between two records.  rmax2 is the largest cutoff squared in
+// the record's own units (fixed-point units for PackF).
+struct Geo {
+    float scale;     // PackF: box length of one fixed-point unit
+    float rmax2u;    // PackF: largest cutoff^2 in fixed-point units
+    double rmax2;    // PartD: largest cutoff^2
+    double L;
+};
+
+template <typename T>
+__device__ __forceinline__ Geo make_geo(const SysDev &S)
+{
+    Geo g;
+    const double rmax2 = S.lj_on ? fmax(S.rc2, S.lj_rc2) : S.rc2;
+    g.scale = (float)(S.L * (1.0 / 4294967296.0));
+    g.rmax2u = (float)(rmax2 / ((double)g.scale * (double)g.scale));
+    g.rmax2 = rmax2;
+    g.L = S.L;
+    return g;
+}
+
+__device__ __forceinline__ bool near_test(const PackF &pa, const PackF &pb, const Geo &g)
+{
+    const float ux = (float)(int32_t)(pb.x - pa.x);
+    const float uy = (float)(int32_t)(pb.y - pa.y);
+    const float uz = (float)(int32_t)(pb.z - pa.z);
+    return fmaf(ux, ux, fmaf(uy, uy, uz * uz)) <= g.rmax2u;
+}
+
+__device__ __forceinline__ void displacement(const PackF &pa, const PackF &pb, const Geo &g, float &dx, float &dy,
+                                             float &dz, float &r2)
+{
+    dx = (float)(int32_t)(pb.x - pa.x) * g.scale;
+    dy = (float)(int32_t)(pb.y - pa.y) * g.scale;
+    dz = (float)(int32_t)(pb.z - pa.z) * g.scale;
+    r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+__device__ __forceinline__ void displacement(const PartD &pa, const PartD &pb, const Geo &g, double &dx, double &dy,
+                                             double &dz, double &r2)
+{
+    double sx = pb.x - pa.x, sy = pb.y - pa.y, sz = pb.z - pa.z;
+    sx -= rint(sx);
+    sy -= rint(sy);
+    sz -= rint(sz);
+    dx = sx * g.L;
+    dy = sy * g.L;
+    dz = sz * g.L;
+    r2 = dx * dx + dy * dy + dz * dz;
+}
+
+__device__ __forceinline__ bool near_test(const PartD &pa, const PartD &pb, const Geo &g)
+{
+    double dx, dy, dz, r2;
+    displacement(pa, pb, g, dx, dy, dz, r2);
+    return r2 <= g.rmax2;
+}
+
+template <typename T>
+__device__ __forceinline__ void cell_coords(const PackF &p, int nc, int &cx, int &cy, int &cz)
+{
+    cx = cell_of_fix(p.x, nc);
+    cy = cell_of_fix(p.y, nc);
+    cz = cell_of_fix(p.z, nc);
+}
+
+template <typename T>
+__device__ __forceinline__ void cell_coords(const PartD &p, int nc, int &cx, int &cy, int &cz)
+{
+    cx = cell_of_frac(p.x, nc);
+    cy = cell_of_frac(p.y, nc);
+    cz = cell_of_frac(p.z, nc);
+}
+
+// Calls f(pb, b) for every record b != self of one stencil row (cells
+// cx-1..cx+1 of row (yy, zz), x taken modulo nc) within the largest cutoff.
+// A row segment of at most 64 records is scanned into a hit mask first;
+// longer segments are visited directly.
+template <typename Rec, typename F>
+__device__ __forceinline__ void visit_row(const Rec &pa, int self, int cx, int yy, int zz, int nc,
+                                          const int32_t *st, const Rec *gs, const Geo &geo, F &&f)
+{
+    const int base = (zz * nc + yy) * nc;
+    int sb[2], se[2], nseg;
+    if (cx >= 1 && cx + 1 < nc) {
+        sb[0] = st[base + cx - 1];
+        se[0] = st[base + cx + 2];
+        nseg = 1;
+    } else if (cx == 0) {
+        sb[0] = st[base];
+        se[0] = st[base + 2];
+        sb[1] = st[base + nc - 1];
+        se[1] = st[base + nc];
+        nseg = 2;
+    } else {
+        sb[0] = st[base + nc - 2];
+        se[0] = st[base + nc];
+        sb[1] = st[base];
+        se[1] = st[base + 1];
+        nseg = 2;
+    }
+    for (int s = 0; s < nseg; ++s) {
+        const int b0 = sb[s], b1 = se[s];
+        if (b1 - b0 <= 64) {
+            uint64_t m = 0;
+            for (int b = b0; b < b1; b += 2) {
+                const int b2 = b + 1 < b1 ? b + 1 : b;
+                const Rec p0 = gs[b];
+                const Rec p1 = gs[b2];
+                const bool h0 = b != self && near_test(pa, p0, geo);
+                const bool h1 = b2 != b && b2 != self && near_test(pa, p1, geo);
+                m |= (uint64_t)(h0 ? 1u : 0u) << (b - b0);
+                m |= (uint64_t)(h1 ? 1u : 0u) << (b2 - b0);
+            }
+            while (m) {
+                const int o = __builtin_ctzll(m);
+                m &= m - 1;
+                f(gs[b0 + o], b0 + o);
+            }
+        } else {
+            for (int b = b0; b < b1; ++b) {
+                if (b == self) continue;
+                const Rec pb = gs[b];
+                if (near_test(pa, pb, geo)) f(pb, b);
+            }
+        }
+    }
+}
+
+template <typename T>
+struct RealArgs {
+    const SysDev *sys;
+    const Tile *tiles;       // aux = 0: row-lane tile of RL_PPB sorted slots; 1: all-pairs tile
+    const int32_t *start;
+    const int32_t *sorted_idx;
+    const void *sorted;
+    const void *packed;      // original order (all-pairs tiles)
+    const T *q;              // energies: charges in original order
+    int64_t ntot;
+    T *F;
+    int accumulate;
+    T *vel;                  // kick target (may be NULL); velocities for kinetic energy when ENERGY
+    int32_t *flag;
+    double *epart;           // ENERGY: [tiles][8]
+};
+
+// Store (or add) the real-space force of particle i and apply the optional
+// half kick; with ENERGY add the one-body sums to ev instead.
+template <typename T, bool ENERGY>
+__device__ __forceinline__ void finish_particle(const RealArgs<T> &a, const SysDev &S, int64_t i, double fxd,
+                                                double fyd, double fzd, double *ev)
+{
+    if constexpr (ENERGY) {
+        if (a.vel) {
+            const double x = a.vel[i], y = a.vel[a.ntot + i], z = a.vel[2 * a.ntot + i];
+            ev[3] += 0.5 * S.mass * (x * x + y * y + z * z);
+        }
+        const double qq = (double)a.q[i];
+        ev[4] += qq * qq;
+        ev[5] += qq;
+        ev[6] += fabs(qq);
+        return;
+    }
+    T fx = (T)fxd, fy = (T)fyd, fz = (T)fzd;
+    if (!isfinite(fx + fy + fz)) atomicOr(a.flag, 1);
+    if (a.accumulate) {
+        fx += a.F[i];
+        fy += a.F[a.ntot + i];
+        fz += a.F[2 * a.ntot + i];
+    }
+    a.F[i] = fx;
+    a.F[a.ntot + i] = fy;
+    a.F[2 * a.ntot + i] = fz;
+    if (a.vel) {
+        const double h = 0.5 * S.dt / S.mass;
+        a.vel[i] = (T)((double)a.vel[i] + h * (double)fx);
+        a.vel[a.ntot + i] = (T)((double)a.vel[a.ntot + i] + h * (double)fy);
+        a.vel[2 * a.ntot + i] = (T)((double)a.vel[2 * a.ntot + i] + h * (double)fz);
+    }
+}
+
+template <typename T>
+struct PairCT {
+    using type = SysDev;
+};
+template <>
+struct PairCT<float> {
+    using type = PairConstF;
+};
+
+template <typename T>
+__device__ __forceinline__ typename PairCT<T>::type pair_consts(const SysDev &S);
+template <>
+__device__ __forceinline__ PairConstF pair_consts<float>(const SysDev &S)
+{
+    return pair_const_f(S);
+}
+template <>
+__device__ __forceinline__ SysDev pair_consts<double>(const SysDev &S)
+{
+    return S;
+}
+
+template <typename T, bool ENERGY>
+__global__ __launch_bounds__(RL_BS) void k_real_rows(RealArgs<T> a)
+{
+    using Rec = typename RBT<T>::Rec;
+    __shared__ double s_red[6][RL_BS];
+    __shared__ double s_blk[8][RL_BS / 64];
+    const Tile t = a.tiles[blockIdx.x];
+    const SysDev S = a.sys[t.sys];
+    const Geo geo = make_geo<T>(S);
+    const auto pc = pair_consts<T>(S);
+    const int tid = threadIdx.x;
+    double ev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (t.aux == 1) {
+        // all pairs: particles [start, start + count) of the system, one per
+        // thread, partners in original index order
+        const Rec *pk = reinterpret_cast<const Rec *>(a.packed) + S.off;
+        if (tid < t.count) {
+            const int il = t.start + tid;
+            const Rec pa = pk[il];
+            double fx = 0, fy = 0, fz = 0;
+            PairE e{0, 0};
+            for (int j = 0; j < S.n; ++j) {
+                if (j == il) continue;
+                const Rec pb = pk[j];
+                if (!near_test(pa, pb, geo)) continue;
+                T dx, dy, dz, r2;
+                displacement(pa, pb, geo, dx, dy, dz, r2);
+                const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
+                fx += (double)(phi * dx);
+                fy += (double)(phi * dy);
+                fz += (double)(phi * dz);
+                if constexpr (ENERGY) ev[2] += 0.5 * (double)(phi * r2);
+            }
+            if constexpr (ENERGY) {
+                ev[0] += e.e_real;
+                ev[1] += e.e_lj;
+            }
+            finish_particle<T, ENERGY>(a, S, S.off + il, fx, fy, fz, ev);
+        }
+    } else {
+        const int wave = tid >> 6, lane = tid & 63;
+        const int p = lane / 9, r = lane - 9 * (lane / 9);
+        const int k = wave * RL_PPW + p;
+        const bool act = lane < 9 * RL_PPW && k < t.count;
+        double fx = 0, fy = 0, fz = 0, vir = 0;
+        PairE e{0, 0};
+        int slot = -1;
+        if (act) {
+            slot = S.off + t.start + k;
+            const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
+            const Rec pa = gs[slot];
+            const int nc = S.nc;
+            int cx, cy, cz;
+            cell_coords<T>(pa, nc, cx, cy, cz);
+            const int zz = (cz + r / 3 - 1 + nc) % nc, yy = (cy + r % 3 - 1 + nc) % nc;
+            const int32_t *st = a.start + S.cell_off + t.sys;
+            visit_row(pa, slot, cx, yy, zz, nc, st, gs, geo, [&](const Rec &pb, int) {
+                T dx, dy, dz, r2;
+                displacement(pa, pb, geo, dx, dy, dz, r2);
+                const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
+                fx += (double)(phi * dx);
+                fy += (double)(phi * dy);
+                fz += (double)(phi * dz);
+                if constexpr (ENERGY) vir += 0.5 * (double)(phi * r2);
+            });
+        }
+        // add the nine row sums of each particle in row order
+        s_red[0][tid] = fx;
+        s_red[1][tid] = fy;
+        s_red[2][tid] = fz;
+        if constexpr (ENERGY) {
+            s_red[3][tid] = e.e_real;
+            s_red[4][tid] = e.e_lj;
+            s_red[5][tid] = vir;
+        }
+        __syncthreads();
+        if (act && r == 0) {
+            double sx = 0, sy = 0, sz = 0;
+            for (int j = 0; j < 9; ++j) {
+                sx += s_red[0][tid + j];
+                sy += s_red[1][tid + j];
+                sz += s_red[2][tid + j];
+            }
+            if constexpr (ENERGY)
+                for (int j = 0; j < 9; ++j) {
+                    ev[0] += s_red[3][tid + j];
+                    ev[1] += s_red[4][tid + j];
+                    ev[2] += s_red[5][tid + j];
+                }
+            finish_particle<T, ENERGY>(a, S, a.sorted_idx[slot], sx, sy, sz, ev);
+        }
+    }
+    if constexpr (ENERGY) {
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int k = 0; k < 8; ++k) {
+            double v = ev[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) s_blk[k][wave] = v;
+        }
+        __syncthreads();
+        if (tid < 8) {
+            double v = 0.0;
+            for (int w = 0; w < RL_BS / 64; ++w) v += s_blk[tid][w];
+            a.epart[8 * blockIdx.x + tid] = v;
+        }
+    }
+}
+
+// Stand-alone scatter into cell order (the force kernel does this inline
+// during a time step).
+template <typename Rec>
+__global__ __launch_bounds__(256) void k_scatter(const SysDev *__restrict__ sys, const Tile *__restrict__ tiles,
+                                                 const int32_t *__restrict__ start, const int32_t *__restrict__ cellid,
+                                                 const int32_t *__restrict__ rank, const Rec *__restrict__ packed,
+                                                 int32_t *__restrict__ sorted_idx, Rec *__restrict__ sorted)
+{
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const int64_t i = sys[t.sys].off + t.start + threadIdx.x;
+    const int slot = start[cellid[i] + t.sys] + rank[i];
+    sorted_idx[slot] = (int32_t)i;
+    sorted[slot] = packed[i];
+}
+
+// ---------------------------------------------------------------------------
+// Real-space and LJ adjoint.  With dG = G_i - G_j and the pair force phi d:
+//   dLoss/dq_i += -coulomb sum_j q_j (G(r)/r) dG.d
+//   dLoss/dr_i += sum_j [ -(phi'(r)/r)(dG.d) d - phi dG ]
+// G(r)/r = erfc(beta r)/r^3 + 2 beta exp(-alpha r^2)/(sqrt(pi) r^2), whose
+// derivative is -3 erfc/r^4 - 6 beta e/(sqrt(pi) r^3) - 4 beta^3 e/(sqrt(pi) r).
+// Same row-lane decomposition as the force.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void vjp_pair(const SysDev &S, T qi, T qj, T dx, T dy, T dz, T r2, T Gx, T Gy, T Gz,
+                                         double &dq, double &rx, double &ry, double &rz)
+{
+    T phi = 0, dphi_r = 0, gq = 0;   // phi, phi'(r)/r, and the charge term
+    const T GD = Gx * dx + Gy * dy + Gz * dz;
+    if (r2 <= (T)S.rc2) {
+        const T r = sqrt(r2);
+        const T beta = (T)S.beta;
+        const T ec = erfc(beta * r);
+        const T ex = exp(-(T)S.alpha * r2);
+        const T isp = (T)(1.0 / 1.7724538509055160273);
+        const T inv_r = (T)1 / r, inv_r2 = inv_r * inv_r;
+        const T g = (ec * inv_r + (T)2 * beta * isp * ex) * inv_r2;
+        const T dg = -(T)3 * ec * inv_r2 * inv_r2 - (T)6 * beta * isp * ex * inv_r2 * inv_r -
+                     (T)4 * beta * beta * beta * isp * ex * inv_r;
+        const T cq = (T)S.coulomb * qi * qj;
+        phi = -cq * g;
+        dphi_r = -cq * dg * inv_r;
+        gq = -(T)S.coulomb * qj * g * GD;
+    }
+    if (S.lj_on && r2 < (T)S.lj_rc2) {
+        const T sr2 = (T)S.lj_sig2 / r2;
+        const T sr6 = sr2 * sr2 * sr2, sr12 = sr6 * sr6;
+        const T eps4 = (T)(4.0 * S.lj_eps);
+        phi += eps4 * ((T)6 * sr6 - (T)12 * sr12) / r2;
+        dphi_r += eps4 * ((T)168 * sr12 - (T)48 * sr6) / (r2 * r2);
+    }
+    dq += (double)gq;
+    rx -= (double)(dphi_r * GD * dx + phi * Gx);
+    ry -= (double)(dphi_r * GD * dy + phi * Gy);
+    rz -= (double)(dphi_r * GD * dz + phi * Gz);
+}
+
+template <typename T>
+__global__ __launch_bounds__(RL_BS) void k_vjp_real(RealArgs<T> a, const T *__restrict__ gF, T *__restrict__ gpos,
+                                                    T *__restrict__ gq, int accumulate)
+{
+    using Rec = typename RBT<T>::Rec;
+    __shared__ double s_red[4][RL_BS];
+    const Tile t = a.tiles[blockIdx.x];
+    const SysDev S = a.sys[t.sys];
+    const Geo geo = make_geo<T>(S);
+    const int tid = threadIdx.x;
+    const int64_t ntot = a.ntot;
+    auto finish = [&](int64_t i, double dq, double rx, double ry, double rz) {
+        if (accumulate) {
+            dq += gq[i];
+            rx += gpos[i];
+            ry += gpos[ntot + i];
+            rz += gpos[2 * ntot + i];
+        }
+        gq[i] = (T)dq;
+        gpos[i] = (T)rx;
+        gpos[ntot + i] = (T)ry;
+        gpos[2 * ntot + i] = (T)rz;
+    };
+    if (t.aux == 1) {
+        const Rec *pk = reinterpret_cast<const Rec *>(a.packed) + S.off;
+        if (tid < t.count) {
+            const int il = t.start + tid;
+            const int64_t i = S.off + il;
+            const Rec pa = pk[il];
+            const T Gix = gF[i], Giy = gF[ntot + i], Giz = gF[2 * ntot + i];
+            double dq = 0, rx = 0, ry = 0, rz = 0;
+            for (int j = 0; j < S.n; ++j) {
+                if (j == il) continue;
+                const Rec pb = pk[j];
+                if (!near_test(pa, pb, geo)) continue;
+                T dx, dy, dz, r2;
+                displacement(pa, pb, geo, dx, dy, dz, r2);
+                const int64_t jj = S.off + j;
+                vjp_pair<T>(S, (T)pa.q, (T)pb.q, dx, dy, dz, r2, Gix - gF[jj], Giy - gF[ntot + jj],
+                            Giz - gF[2 * ntot + jj], dq, rx, ry, rz);
+            }
+            finish(i, dq, rx, ry, rz);
+        }
+        return;
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    const int p = lane / 9, r = lane - 9 * (lane / 9);
+    const int k = wave * RL_PPW + p;
+    const bool act = lane < 9 * RL_PPW && k < t.count;
+    double dq = 0, rx = 0, ry = 0, rz = 0;
+    int slot = -1;
+    if (act) {
+        slot = S.off + t.start + k;
+        const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
+        const Rec pa = gs[slot];
+        const int64_t i = a.sorted_idx[slot];
+        const T Gix = gF[i], Giy = gF[ntot + i], Giz = gF[2 * ntot + i];
+        const int nc = S.nc;
+        int cx, cy, cz;
+        cell_coords<T>(pa, nc, cx, cy, cz);
+        const int zz = (cz + r / 3 - 1 + nc) % nc, yy = (cy + r % 3 - 1 + nc) % nc;
+        const int32_t *st = a.start + S.cell_off + t.sys;
+        visit_row(pa, slot, cx, yy, zz, nc, st, gs, geo, [&](const Rec &pb, int b) {
+            T dx, dy, dz, r2;
+            displacement(pa, pb, geo, dx, dy, dz, r2);
+            const int64_t jj = a.sorted_idx[b];
+            vjp_pair<T>(S, (T)pa.q, (T)pb.q, dx, dy, dz, r2, Gix - gF[jj], Giy - gF[ntot + jj],
+                        Giz - gF[2 * ntot + jj], dq, rx, ry, rz);
+        });
+    }
+    s_red[0][tid] = dq;
+    s_red[1][tid] = rx;
+    s_red[2][tid] = ry;
+    s_red[3][tid] = rz;
+    __syncthreads();
+    if (act && r == 0) {
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int j = 0; j < 9; ++j) {
+            a0 += s_red[0][tid + j];
+            a1 += s_red[1][tid + j];
+            a2 += s_red[2][tid + j];
+            a3 += s_red[3][tid + j];
+        }
+        finish(a.sorted_idx[slot], a0, a1, a2, a3);
+    }
+}
+
+__global__ void k_fill_zero(uint32_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_zero(hipStream_t s, void *ptr, int64_t nbytes)
+{
+    const int64_t n = nbytes / 4;
+    if (n <= 0) return hipSuccess;
+    k_fill_zero<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>((uint32_t *)ptr, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w)
+{
+    if (c.prec == RBE_FP64)
+        k_scatter<PartD><<<c.n_part_tiles, 256, 0, c.stream>>>(w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
+                                                               (const PartD *)w.packed, w.sorted_idx,
+                                                               (PartD *)w.sorted);
+    else
+        k_scatter<PackF><<<c.n_part_tiles, 256, 0, c.stream>>>(w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
+                                                               (const PackF *)w.packed, w.sorted_idx,
+                                                               (PackF *)w.sorted);
+    return hipGetLastError();
+}
+
+template <typename T>
+static RealArgs<T> real_args(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel,
+                             const void *q)
+{
+    RealArgs<T> a;
+    a.sys = w.sys;
+    a.tiles = w.real_tiles;
+    a.start = w.cell_start;
+    a.sorted_idx = w.sorted_idx;
+    a.sorted = w.sorted;
+    a.packed = w.packed;
+    a.q = (const T *)q;
+    a.ntot = c.ntot;
+    a.F = (T *)force;
+    a.accumulate = accumulate;
+    a.vel = (T *)vel;
+    a.flag = w.flag;
+    a.epart = w.energy_part;
+    return a;
+}
+
+hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick)
+{
+    if (c.prec == RBE_FP64)
+        k_real_rows<double, false><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
+            real_args<double>(c, w, force, accumulate, vel_kick, nullptr));
+    else
+        k_real_rows<float, false><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
+            real_args<float>(c, w, force, accumulate, vel_kick, nullptr));
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const LaunchCfg &c, const Workspace &w, const void *q, const void *vel)
+{
+    if (c.prec == RBE_FP64)
+        k_real_rows<double, true><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
+            real_args<double>(c, w, nullptr, 0, (void *)vel, q));
+    else
+        k_real_rows<float, true><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
+            real_args<float>(c, w, nullptr, 0, (void *)vel, q));
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_real(const LaunchCfg &c, const Workspace &w, const void *gF, void *gpos, void *gq,
+                           int accumulate)
+{
+    if (c.prec == RBE_FP64)
+        k_vjp_real<double><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(real_args<double>(c, w, nullptr, 0, nullptr,
+                                                                                     nullptr),
+                                                                   (const double *)gF, (double *)gpos,
+                                                                   (double *)gq, accumulate);
+    else
+        k_vjp_real<float><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(real_args<float>(c, w, nullptr, 0, nullptr,
+                                                                                   nullptr),
+                                                                  (const float *)gF, (float *)gpos, (float *)gq,
+                                                                  accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace rbe

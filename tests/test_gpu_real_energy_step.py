@@ -44,6 +44,25 @@ def test_real_forces_positions_outside_box():
     assert rel_l2(host(F), Fo) <= 1e-11
 
 
+@pytest.mark.parametrize("prec", [R.RBE_FP64, R.RBE_FP32])
+@pytest.mark.parametrize("density", [1.0, 3.0])
+def test_real_forces_dense(prec, density):
+    """Dense boxes: small bricks, and at density 3 a halo larger than the
+    kernel's LDS capacity, which is then read from global memory."""
+    n = 3000
+    rng = np.random.default_rng(int(density * 10))
+    L = W.box_for_density(n, density)
+    pos = W.positions(n, L, rng, 0.3)
+    q = W.electrolyte_charges(n)
+    s = W.System("dense", n, L, 0.8, 3.0, 10, pos, q, np.zeros((3, n)), 5, lj=(1.0, 0.3, 0.75))
+    ctx = make_ctx(s, prec)
+    P, Q, V, F = device_state(ctx, s)
+    pos_r, q_r = rounded(s, prec)
+    R.rbe_real_forces(ctx, P, Q, F)
+    Fo, _, _ = O.real_force(pos_r, q_r, s.L, s.alpha, s.r_cut, s.coulomb, s.lj)
+    assert rel_l2(host(F), Fo) <= (1e-12 if prec == R.RBE_FP64 else 2e-6)
+
+
 def test_real_forces_full_size_sampled():
     s = W.metric_system()
     ctx = make_ctx(s, R.RBE_FP32)
@@ -58,8 +77,9 @@ def test_real_forces_full_size_sampled():
 
 
 @pytest.mark.parametrize("prec", [R.RBE_FP64, R.RBE_FP32])
-def test_energy_components(prec):
-    s = W.langevin_electrolyte()
+@pytest.mark.parametrize("sysfn", [W.small_fp64, W.langevin_electrolyte])
+def test_energy_components(prec, sysfn):
+    s = sysfn()
     ctx = make_ctx(s, prec)
     P, Q, V, F = device_state(ctx, s)
     pos, q = rounded(s, prec)
@@ -181,7 +201,9 @@ def test_forces_vjp(prec, tol, lj):
 def test_batched_systems_match_single_oracle():
     """Several systems of uneven size in one context: each system's forces,
     modes and energies equal the oracle's for that system alone."""
+    # uneven sizes, plus one box too small for a cell list (all pairs)
     systems = W.replica_systems(R=5, nmin=300, nmax=2500, seed=77)
+    systems.insert(2, W.small_fp64(seed=5))
     params = [R.params_from_system(s, R.RBE_FP64) for s in systems]
     ctx = R.rbe_batch_create(params)
     import torch
