@@ -12,14 +12,17 @@ force and the Langevin update (rbe_step with nsteps = 1 per step, all launched
 back to back on one stream).  The headline value is N*P*steps / elapsed
 seconds over those full steps.  The JSON line also reports MD steps/s, the
 Fourier-only pair rate (sample + structure factor + force), per-kernel
-durations from HIP events on the library's stream, the ALU roofline of the
-dominant Fourier kernel, and the FP64 CPU oracle timed on the host.
+durations from HIP events on the library's stream, the ALU roofline of every
+kernel of the step (the longest one as "roofline"), and the FP64 CPU oracle
+timed on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--autotune] [--calibrate-copy]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,12 +35,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "k-space particle–mode pairs/s (N·P) + MD steps/s at N=1e5, P=100, 1 GPU"
 
-# Issue cost of the algorithmic operations per particle-mode pair, in FP32
-# VALU issue slots (an FP64 op takes 2, a transcendental op 4), and the chip's
-# FP32 vector peak: 256 CUs x 128 FP32 lanes/clock x 2 flop x 2.4 GHz.
+# Algorithmic work in FP32 VALU issue slots (an FP64 add/mul/FMA takes 2, a
+# transcendental op 4) and the chip's FP32 vector peak: 256 CUs x 128 FP32
+# lanes/clock x 2 flop x 2.4 GHz.  One slot counts as 2 flop.
+# Per particle-mode pair:
 SLOTS_FORCE = 3 * 2 + 2 * 2 + 2 * 4 + 2 + 3   # phase (3 FP64 FMA), wrap (2 FP64), sin+cos, Im term, 3 FMA
 SLOTS_RHO = 3 * 2 + 2 * 2 + 2 * 4 + 2         # phase, wrap, sin+cos, 2 FMA
+# Real space, per candidate distance test (3 integer differences, 3
+# conversions, |d|^2, compare) and per pair inside the cutoff (displacement,
+# rsqrt, exp, the erfc rational form with its reciprocal, Coulomb and LJ
+# factors, force accumulation); both counted over ordered pairs.
+SLOTS_CHECK = 10
+SLOTS_PAIR = 6 + 3 + 3 * 4 + 3 + 5 + 9 + 4 + 3 + 6 + 6
 PEAK_FP32_TFLOPS = 157.3
+
+# HBM traffic per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch, averaged over the launches of the step),
+# multiplied by the ratio of the true size of a plain copy to what the same
+# counters read for it.  Valid only for the kernel source it was taken on.
+TRAFFIC = {}
 
 
 def parse():
@@ -47,7 +63,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick the Fourier tile shapes by timing")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -74,6 +92,40 @@ def cpu_baseline(s, modes, budget_s):
                       f"P={s.p} workload in {el:.1f} s"}
 
 
+def real_space_counts(s):
+    """Ordered candidate pairs of the 27-cell stencil and ordered pairs within
+    the largest cutoff, for the initial configuration."""
+    from scipy.spatial import cKDTree
+    rmax = max(s.r_cut, s.lj[2] * s.lj[1]) if s.lj[0] > 0 else s.r_cut
+    nc = min(int(np.floor(s.L / rmax)), 128)
+    frac = np.mod(s.pos / s.L, 1.0)
+    c = np.minimum((frac * nc).astype(np.int64), nc - 1)
+    cnt = np.zeros((nc, nc, nc), np.int64)
+    np.add.at(cnt, (c[2], c[1], c[0]), 1)
+    near = sum(np.roll(cnt, (dz, dy, dx), axis=(0, 1, 2))
+               for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    cand = int((cnt * near).sum()) - s.n
+    tree = cKDTree(frac.T * s.L, boxsize=s.L)
+    pairs = 2 * len(tree.query_pairs(rmax, output_type="ndarray"))
+    return cand, pairs
+
+
+def source_sha(name):
+    with open(os.path.join(ROOT, "paper_2010_01559_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+KERNEL_SOURCE = {"stage": "rbe_kspace.hip", "mid": "rbe_kspace.hip", "kforce": "rbe_kspace.hip",
+                 "sample": "rbe_kspace.hip", "real": "rbe_real.hip"}
+
+
+def traffic_for(name):
+    t = TRAFFIC.get(name)
+    if not t or t["src"] != source_sha(KERNEL_SOURCE[name]):
+        return None
+    return round((t["fetch_kib"] + t["write_kib"]) * 1024 * t["scale"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -86,6 +138,12 @@ def main():
     from paper_2010_01559_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     s = W.metric_system()
     params = R.params_from_system(s, R.RBE_FP32)
     ctx = R.rbe_create(params)
@@ -97,7 +155,7 @@ def main():
     stream = ctx.stream
 
     R.rbe_sample_k(ctx, 0)
-    tiles = R.rbe_get_tiles(ctx) if args.no_autotune else R.rbe_autotune(ctx, P, Q, reps=20)
+    tiles = R.rbe_autotune(ctx, P, Q, reps=20) if args.autotune else R.rbe_get_tiles(ctx)
     R.rbe_kspace_forces(ctx, P, Q, F)
     R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
 
@@ -152,14 +210,27 @@ def main():
 
     n, p = s.n, s.p
     pairs = n * p
-    # dominant Fourier kernel and its ALU roofline
-    kf_us = kkern["kforce"]["avg_us"]
-    rho_us = kkern["stage"]["avg_us"]
-    dom, dom_us, slots = ("kforce", kf_us, SLOTS_FORCE) if kf_us >= rho_us else ("stage", rho_us, SLOTS_RHO)
-    achieved = pairs * slots * 2 / (dom_us * 1e-6) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "slots_per_pair": slots, "avg_launch_us": round(dom_us, 2)}
+    cand, nb = real_space_counts(s)
+    work = {"stage": pairs * SLOTS_RHO, "kforce": pairs * SLOTS_FORCE,
+            "real": cand * SLOTS_CHECK + nb * SLOTS_PAIR}
+    rooflines = {}
+    for name, slots in work.items():
+        if name not in kern:
+            continue
+        us = kern[name]["avg_us"]
+        ach = slots * 2 / (us * 1e-6) / 1e12
+        rooflines[name] = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                           "traffic": traffic_for(name), "avg_launch_us": round(us, 2),
+                           "slots_per_launch": int(slots)}
+    dom = max(rooflines, key=lambda k: kern[k]["avg_us"])
+    roofline = dict(rooflines[dom], kernel=dom)
+    fourier = {}
+    for name, slots in (("kforce", pairs * SLOTS_FORCE), ("stage", pairs * SLOTS_RHO)):
+        us = kkern[name]["avg_us"]
+        ach = slots * 2 / (us * 1e-6) / 1e12
+        fourier[name] = {"achieved": round(ach, 3), "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                         "avg_launch_us": round(us, 2)}
 
     cpu = None
     if not args.no_cpu:
@@ -190,7 +261,10 @@ def main():
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]} for k, v in kern.items()},
         "kspace_kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
                            for k, v in kkern.items()},
+        "real_space": {"candidate_pairs": cand, "pairs_in_cutoff": nb},
         "roofline": roofline,
+        "rooflines": rooflines,
+        "fourier_only_rooflines": fourier,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

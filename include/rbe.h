@@ -80,6 +80,14 @@ typedef struct rbe_params {
     double dt;           /* time step [Delta t] */
     double mass;         /* particle mass [m_i], equal for all particles */
     double nu;           /* Andersen collision frequency [nu] (Sec. 3.3) */
+    double skin;         /* neighbour-list skin for rbe_step, >= 0.  With skin > 0 the
+                            real-space pass of a step reads a list of the pairs within
+                            max(r_cut, lj_rcut) + skin, rebuilt on the device whenever a
+                            particle has moved more than skin/2 since the last build; the
+                            cell side is at least cutoff + skin.  0 rebuilds the cell
+                            list at every step.  Either way every pair inside the
+                            cutoffs is counted exactly once (no effect on the result
+                            beyond summation order). */
     uint64_t seed;       /* key of the counter-based generator */
     int32_t precision;   /* RBE_FP32 or RBE_FP64 (all systems of a batch alike) */
     int32_t integrator;  /* RBE_LANGEVIN_BAOAB or RBE_LEAPFROG_ANDERSEN */
@@ -106,7 +114,7 @@ typedef struct rbe_tiles {
     int32_t rho_chunk;     /* particles staged per structure-factor block (<= 2048) */
     int32_t rho_block;     /* threads per structure-factor block: 256, 512 or 1024 */
     int32_t force_split;   /* waves sharing one particle in the force pass: 1, 2 or 4 */
-    int32_t real_split;    /* threads per particle in the real-space pass: 1, 2 or 4 */
+    int32_t real_split;    /* lanes per particle in the neighbour-list pass of rbe_step: 1, 2, 4 or 8 */
 } rbe_tiles;
 
 /* Normaliser of the importance distribution (Sec. 3.1, eqs. 3.1-3.2):
@@ -206,6 +214,12 @@ rbe_status rbe_get_rho(rbe_ctx *ctx, double *rho);
  * eq. 4.1), selected by parts (RBE_PART_*).  Outputs are overwritten. */
 rbe_status rbe_forces_vjp(rbe_ctx *ctx, const void *pos, const void *q, const void *grad_force, void *grad_pos,
                           void *grad_q, int32_t parts);
+
+/* Number of neighbour-list builds made by rbe_step since creation (the first
+ * step after creation, after rbe_real_forces / rbe_energy / rbe_forces_vjp,
+ * and whenever a particle had moved more than skin/2 or a list overflowed),
+ * or -1 when the context does not use the list.  Synchronises the stream. */
+rbe_status rbe_list_builds(rbe_ctx *ctx, int64_t *builds);
 
 /* Tile shapes: read or set (validated; 0 fields keep the current value). */
 rbe_status rbe_get_tiles(const rbe_ctx *ctx, rbe_tiles *tiles);

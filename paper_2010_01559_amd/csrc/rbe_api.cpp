@@ -23,7 +23,7 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 const char *kKernelNames[K_COUNT] = {"sample", "stage",      "mid",        "kforce",   "scatter", "real",
-                                     "energy", "vjp_reduce", "vjp_gather", "vjp_real", "misc"};
+                                     "energy", "vjp_reduce", "vjp_gather", "vjp_real", "scan",    "misc"};
 
 std::string fmt(const char *f, ...)
 {
@@ -103,6 +103,7 @@ rbe_status validate(const rbe_params &p, std::string &err)
     if (!std::isfinite(p.dt) || p.dt < 0.0) return err = "dt must be finite and >= 0", RBE_ERR_INVALID;
     if (!finite_pos(p.mass)) return err = "mass must be finite and > 0", RBE_ERR_INVALID;
     if (!std::isfinite(p.nu) || p.nu < 0.0) return err = "nu must be finite and >= 0", RBE_ERR_INVALID;
+    if (!std::isfinite(p.skin) || p.skin < 0.0) return err = "skin must be finite and >= 0", RBE_ERR_INVALID;
     if (p.precision != RBE_FP32 && p.precision != RBE_FP64) return err = "unknown precision", RBE_ERR_INVALID;
     if (p.integrator != RBE_LANGEVIN_BAOAB && p.integrator != RBE_LEAPFROG_ANDERSEN)
         return err = "unknown integrator", RBE_ERR_INVALID;
@@ -133,6 +134,8 @@ struct rbe_ctx {
     int mcap = 0;                  // capacity of the mode arrays
     int max_p = 0;
     bool modes_valid = false;
+    bool list_valid = false;       // the neighbour list matches the cell order in `sorted`
+    uint64_t list_gen = 0;         // steps taken in list mode (selects the rebuild flag)
     bool any_mh = false;
     LaunchCfg cfg{};
     Workspace w{};
@@ -286,6 +289,29 @@ void build_real_tiles(rbe_ctx *c, std::vector<Tile> &out, std::vector<int> &tile
     }
 }
 
+// List-pass tiles: runs of 256/LPP cell-sorted slots (aux = 2) for list
+// systems, all-pairs runs (aux = 1) for one-cell systems.
+void build_list_tiles(rbe_ctx *c, int lpp, std::vector<Tile> &out)
+{
+    out.clear();
+    for (int r = 0; r < c->R; ++r) {
+        const SysDev &s = c->sysh[r];
+        const int aux = s.nc == 1 ? 1 : 2;
+        const int step = aux == 1 ? real_allpairs_per_tile() : 256 / lpp;
+        for (int k = 0; k < s.n; k += step) out.push_back(Tile{r, k, std::min(step, s.n - k), aux});
+    }
+}
+
+rbe_status upload_list_tiles(rbe_ctx *c)
+{
+    if (!c->cfg.list_on) return RBE_OK;
+    std::vector<Tile> lt;
+    build_list_tiles(c, c->cfg.real_split, lt);
+    c->cfg.n_list_tiles = (int)lt.size();
+    HIPCHK(c, hipMemcpy(c->w.list_tiles, lt.data(), lt.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    return RBE_OK;
+}
+
 rbe_status upload_rho_tiles(rbe_ctx *c)
 {
     std::vector<Tile> tiles;
@@ -398,6 +424,10 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     std::vector<double> cdf;
     int64_t off = 0;
     int moff = 0, cell_off = 0, max_cells = 0, max_table = 0;
+    // the neighbour list is used only when every system of the batch asks for it
+    bool all_skin = true;
+    for (int r = 0; r < R; ++r) all_skin = all_skin && params[r].skin > 0.0;
+    int kmax = 0;
     for (int r = 0; r < R; ++r) {
         const rbe_params &p = params[r];
         SysDev s{};
@@ -409,7 +439,8 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         s.M = table_half_width(p.alpha, p.box);
         build_cdf(p.alpha, p.box, cdf);
         const double rmax = std::max(p.r_cut, p.lj_eps > 0.0 ? p.lj_rcut : 0.0);
-        int nc = (int)std::floor(p.box / rmax);
+        const double rlist = rmax + p.skin;
+        int nc = (int)std::floor(p.box / rlist);
         nc = std::min(nc, 128);
         if (nc < 3) nc = 1;   // fewer than 3 cells along the box: one cell, all pairs
         s.nc = nc;
@@ -441,6 +472,14 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         s.c2 = std::sqrt((1.0 - s.c1 * s.c1) * p.kT / p.mass);
         s.nu_dt = p.nu * p.dt;
         s.seed = p.seed;
+        s.use_list = (all_skin && nc >= 3) ? 1 : 0;
+        s.rlist2 = rlist * rlist;
+        s.half_skin2 = 0.25 * p.skin * p.skin;
+        if (s.use_list) {
+            const double dens = (double)p.n / (p.box * p.box * p.box);
+            const double mean = dens * 4.0 / 3.0 * kPi * rlist * rlist * rlist;
+            kmax = std::max(kmax, (int)std::ceil(1.5 * mean + 32.0));
+        }
         c->sysh.push_back(s);
         if (p.sampler == RBE_SAMPLER_MH) c->any_mh = true;
         off += p.n;
@@ -459,10 +498,13 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     g.prec = c->prec;
     g.ntot = ntot;
     g.mcap = c->mcap;
-    g.rho_chunk = 256;
+    g.rho_chunk = 512;
     g.rho_block = 1024;
     g.force_split = 4;
-    g.real_split = 1;
+    g.real_split = 4;
+    g.kmax = std::min((kmax + 7) & ~7, 1024);
+    g.list_on = 0;
+    for (int r = 0; r < R; ++r) g.list_on |= c->sysh[r].use_list;
     g.ncell_tot = cell_off;
     g.max_cells = max_cells;
     g.max_p = c->max_p;
@@ -525,6 +567,18 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     ALLOC(w.sorted, pack_sz * ntot);
     ALLOC(w.energy_part, sizeof(double) * 8 * rtiles.size());
     ALLOC(w.flag, sizeof(int32_t) * 4);
+    ALLOC(w.lflag, sizeof(int32_t) * 4);
+    {
+        // list-pass tiles: at most one per 32 slots (the 8-lane shape)
+        int64_t nl = 0;
+        for (int r = 0; r < R; ++r) nl += (c->sysh[r].n + 31) / 32;
+        const int64_t nlist = g.list_on ? ntot : 1;
+        ALLOC(w.list_tiles, sizeof(Tile) * (g.list_on ? nl : 1));
+        ALLOC(w.slot_of, sizeof(int32_t) * nlist);
+        ALLOC(w.ref, pack_sz * nlist);
+        ALLOC(w.nbr, sizeof(int32_t) * (g.list_on ? (int64_t)g.kmax * ntot : 1));
+        ALLOC(w.nnb, sizeof(int32_t) * nlist);
+    }
 #undef ALLOC
     c->epart_h.resize(8 * rtiles.size());
 
@@ -539,8 +593,18 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
               hipMemset(w.mh_state, 0, sizeof(int32_t) * 3 * R) == hipSuccess &&
               hipMemset(w.cell_count, 0, sizeof(int32_t) * cell_off) == hipSuccess &&
               hipMemset(w.flag, 0, sizeof(int32_t) * 4) == hipSuccess &&
+              hipMemset(w.lflag, 0, sizeof(int32_t) * 4) == hipSuccess &&
               hipMemset(w.modes, 0, sizeof(int32_t) * 3 * c->mcap) == hipSuccess;
     if (ok) ok = upload_rho_tiles(c) == RBE_OK;
+    if (ok) ok = upload_list_tiles(c) == RBE_OK;
+    if (ok && g.list_on) {
+        // in-bounds slots and zeroed records until the first build replaces them
+        std::vector<int32_t> iota(ntot);
+        for (int64_t i = 0; i < ntot; ++i) iota[i] = (int32_t)i;
+        ok = up(w.slot_of, iota.data(), sizeof(int32_t) * ntot) &&
+             hipMemset(w.ref, 0, pack_sz * ntot) == hipSuccess &&
+             hipMemset(w.nnb, 0, sizeof(int32_t) * ntot) == hipSuccess;
+    }
     if (ok) ok = hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         g_create_error = "uploading the context constants failed";
@@ -683,6 +747,7 @@ static rbe_status kspace_impl(rbe_ctx *c, const void *pos, const void *q, void *
 // scan, scatter into cell order.
 static rbe_status cells_impl(rbe_ctx *c, const void *pos, const void *q)
 {
+    c->list_valid = false;   // the cell order changes under the list
     StageRequest rq{const_cast<void *>(pos), nullptr, nullptr, q, 0, 0, 0, 1, 0, 0};
     RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
     RUN(c, K_MID, launch_mid(c->cfg, c->w, 0, 1));
@@ -729,19 +794,37 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
         }
     // one step = four launches: [integrate + bin + draw modes + structure-factor
     // partials] -> [totals + cell scan] -> [Fourier force + scatter] ->
-    // [real space + LJ + final half kick]
+    // [real space + LJ + final half kick].  In list mode the binning moves to
+    // the force pass and the scan and scatter to launches of their own, and
+    // all three run only on rebuild steps (decided on the device).
     int table_lds = 0, tab_max = 0;
     const size_t lds = stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max);
     const bool fuse_sample = !c->any_mh && lds <= 64 * 1024;
+    const bool list = c->cfg.list_on != 0;
     for (int32_t t = 0; t < nsteps; ++t) {
         const uint64_t s = first_step + (uint64_t)t;
         const uint64_t ks = andersen ? s + 1 : s;
         if (!fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
-        StageRequest rq{pos, vel, force, q, s, ks, 1, 1, fuse_sample ? 1 : 0, 1};
-        RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
-        RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 1));
-        RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, 0, 1));
-        RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, andersen ? nullptr : vel));
+        if (list) {
+            const int par = (int)(c->list_gen & 1);
+            ListStep ls{c->w.lflag + par, c->w.lflag + (1 - par), c->w.lflag + 2, c->w.lflag + 3,
+                        c->list_valid ? 0 : 1};
+            StageRequest rq{pos, vel, force, q, s, ks, 1, 0, fuse_sample ? 1 : 0, 1, &ls};
+            RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
+            RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0));
+            RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, 0, 0, ls.rebuild));
+            RUN(c, K_SCAN, launch_mid(c->cfg, c->w, 0, 1, ls.rebuild));
+            RUN(c, K_SCATTER, launch_scatter(c->cfg, c->w, &ls));
+            RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, andersen ? nullptr : vel));
+            c->list_valid = true;
+            ++c->list_gen;
+        } else {
+            StageRequest rq{pos, vel, force, q, s, ks, 1, 1, fuse_sample ? 1 : 0, 1};
+            RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
+            RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 1));
+            RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, 0, 1));
+            RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, andersen ? nullptr : vel));
+        }
     }
     if (nsteps > 0) c->modes_valid = true;
     return RBE_OK;
@@ -844,6 +927,16 @@ rbe_status rbe_forces_vjp(rbe_ctx *c, const void *pos, const void *q, const void
     return RBE_OK;
 }
 
+rbe_status rbe_list_builds(rbe_ctx *c, int64_t *builds)
+{
+    if (!c || !builds) return RBE_ERR_INVALID;
+    int32_t v = 0;
+    HIPCHK(c, hipMemcpyAsync(&v, c->w.lflag + 3, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *builds = c->cfg.list_on ? (int64_t)v : -1;
+    return RBE_OK;
+}
+
 rbe_status rbe_get_tiles(const rbe_ctx *c, rbe_tiles *t)
 {
     if (!c || !t) return RBE_ERR_INVALID;
@@ -868,7 +961,8 @@ rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
         return set_err(c, RBE_ERR_INVALID, "rho_block must be 256, 512 or 1024");
     if (n.force_split != 1 && n.force_split != 2 && n.force_split != 4)
         return set_err(c, RBE_ERR_INVALID, "force_split must be 1, 2 or 4");
-    if (n.real_split != 1) return set_err(c, RBE_ERR_INVALID, "real_split must be 1");
+    if (n.real_split != 1 && n.real_split != 2 && n.real_split != 4 && n.real_split != 8)
+        return set_err(c, RBE_ERR_INVALID, "real_split must be 1, 2, 4 or 8");
     // dynamic LDS of the reduction kernels must fit
     // the adjoint reduction stages 48 bytes per particle and 16 per thread;
     // the staging kernel 32 per particle and 28 per thread (plus the table,
@@ -881,7 +975,9 @@ rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
     c->cfg.rho_block = n.rho_block;
     c->cfg.force_split = n.force_split;
     c->cfg.real_split = n.real_split;
-    return upload_rho_tiles(c);
+    rbe_status st = upload_rho_tiles(c);
+    if (st != RBE_OK) return st;
+    return upload_list_tiles(c);
 }
 
 rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps, rbe_tiles *best)

@@ -32,6 +32,8 @@ struct SysDev {
     int32_t integrator;
     int32_t mh_state_off;  // three int32 chain states at this offset
     int32_t ncell;         // nc^3
+    int32_t use_list;      // neighbour list in rbe_step (skin > 0 and nc >= 3)
+    int32_t pad0;
     double L, invL;
     double alpha, beta;     // beta = sqrt(alpha)
     double rc2;             // r_cut^2
@@ -41,6 +43,8 @@ struct SysDev {
     double kT, gamma, dt, mass;
     double c1, c2;          // Ornstein-Uhlenbeck factors exp(-gamma dt/m), sqrt((1-c1^2) kT/m)
     double nu_dt;           // Andersen collision probability per step
+    double rlist2;          // (largest cutoff + skin)^2
+    double half_skin2;      // (skin / 2)^2
     uint64_t seed;
 };
 
@@ -96,6 +100,7 @@ enum KernelId {
     K_VJP_REDUCE,
     K_VJP_GATHER,
     K_VJP_REAL,
+    K_SCAN,         // cell scan of a list rebuild (exits at once on other steps)
     K_MISC,
     K_COUNT
 };
@@ -126,6 +131,13 @@ struct Workspace {
     void *sorted;          // [Ntot] same, sorted by cell
     double *energy_part;   // [real tiles][8]
     int32_t *flag;         // [4] bit 0: non-finite force
+    // neighbour list of rbe_step (allocated when some system uses it)
+    Tile *list_tiles;      // list-pass tiles (aux 2: cell-sorted slots, 1: all pairs)
+    int32_t *slot_of;      // [Ntot] sorted slot of each particle at the last build
+    void *ref;             // [Ntot] record of each particle at the last build (original order)
+    int32_t *nbr;          // [kmax][Ntot] partner slots, column k of slot s at k * Ntot + s
+    int32_t *nnb;          // [Ntot] partners of each slot
+    int32_t *lflag;        // [4]: rebuild request for even / odd steps, list overflow, builds
 };
 
 struct LaunchCfg {
@@ -140,6 +152,18 @@ struct LaunchCfg {
     int max_cells;   // largest cell count of one system
     int max_p;
     int max_table;   // largest cumulative table (2M + 1)
+    int list_on;     // some system uses the neighbour list
+    int kmax;        // list capacity per particle
+    int n_list_tiles;
+};
+
+// Device view of the neighbour-list state for one step.
+struct ListStep {
+    int32_t *rebuild;        // request flag of this step (read)
+    int32_t *rebuild_next;   // request flag of the next step (cleared here)
+    int32_t *overflow;
+    int32_t *rebuilds;       // count of list builds
+    int force_rebuild;
 };
 
 // What one launch of the staging kernel does.
@@ -151,16 +175,19 @@ struct StageRequest {
     uint64_t step;         // integrator noise index
     uint64_t sample_step;  // mode sample index
     int integrate, bin, sample, rho;
+    const ListStep *list;  // integrate in list mode: update cell-order records, test displacements
 };
 
 // ---- launchers (rbe_kspace.hip, rbe_real.hip) ----
 hipError_t launch_sample(const LaunchCfg &c, const Workspace &w, uint64_t step, int use_mh);
 hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageRequest &rq);
 size_t stage_lds_bytes(const LaunchCfg &c, int sample_in_kernel, int *table_lds, int *tab_max);
-hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan);
+hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
+                      const int32_t *scan_gate = nullptr);
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
-                         int accumulate, int scatter);
-hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w);
+                         int accumulate, int scatter, const int32_t *bin_gate = nullptr);
+hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);
+hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick);
 hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick);
 hipError_t launch_energy(const LaunchCfg &c, const Workspace &w, const void *q, const void *vel);
 hipError_t launch_vjp_reduce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q,

@@ -138,6 +138,12 @@ struct StageArgs {
     int do_integrate, do_bin, do_sample, table_lds, do_rho;
     int chunk;
     int tab_max;           // LDS doubles reserved for the table
+    // neighbour-list mode of a time step
+    int list_mode;
+    ListStep ls;
+    const int32_t *slot_of;
+    void *sorted;
+    const void *ref;
 };
 
 template <typename T>
@@ -202,6 +208,41 @@ __device__ __forceinline__ void bin_one(const SysDev &S, int64_t i, double sx, d
     rank[i] = atomicAdd(&count[c], 1);
 }
 
+// List mode: store the new record in original and cell order and test the
+// displacement since the last list build against skin/2.
+template <typename T>
+__device__ __forceinline__ bool list_update(const SysDev &S, int64_t i, double sx, double sy, double sz, T qi,
+                                            const StageArgs<T> &a)
+{
+    bool moved = false;
+    if constexpr (sizeof(T) == 4) {
+        const PackF v{to_fix(sx), to_fix(sy), to_fix(sz), (float)qi};
+        reinterpret_cast<PackF *>(a.packed)[i] = v;
+        if (S.use_list) {
+            reinterpret_cast<PackF *>(a.sorted)[a.slot_of[i]] = v;
+            const PackF r = reinterpret_cast<const PackF *>(a.ref)[i];
+            const double u = 1.0 / 4294967296.0 * S.L;
+            const double dx = (double)(int32_t)(v.x - r.x) * u;
+            const double dy = (double)(int32_t)(v.y - r.y) * u;
+            const double dz = (double)(int32_t)(v.z - r.z) * u;
+            moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
+        }
+    } else {
+        const PartD v{sx, sy, sz, (double)qi};
+        reinterpret_cast<PartD *>(a.packed)[i] = v;
+        if (S.use_list) {
+            reinterpret_cast<PartD *>(a.sorted)[a.slot_of[i]] = v;
+            const PartD r = reinterpret_cast<const PartD *>(a.ref)[i];
+            double dx = v.x - r.x, dy = v.y - r.y, dz = v.z - r.z;
+            dx = (dx - rint(dx)) * S.L;
+            dy = (dy - rint(dy)) * S.L;
+            dz = (dz - rint(dz)) * S.L;
+            moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
+        }
+    }
+    return moved;
+}
+
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
 {
@@ -217,6 +258,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
     const int K = 2 * S.M + 1;
     if (a.do_sample && a.table_lds)
         for (int k = tid; k < K; k += BS) tab[k] = a.cdf[S.cdf_off + k];
+    bool moved = false;
     for (int j = tid; j < count; j += BS) {
         const int il = t.start + j;
         const int64_t i = S.off + il;
@@ -236,8 +278,18 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         v.q = (double)qi;
         sp[j] = v;
         if (a.do_bin) bin_one<T>(S, i, v.x, v.y, v.z, qi, a.count, a.cellid, a.rank, a.packed);
+        if (a.list_mode) moved |= list_update<T>(S, i, v.x, v.y, v.z, qi, a);
     }
-    __syncthreads();
+    if (a.list_mode) {
+        // one request per block; block 0 adds the host's and the overflow's
+        const int any = __syncthreads_or(moved ? 1 : 0);
+        if (tid == 0) {
+            const bool req = any || (blockIdx.x == 0 && (a.ls.force_rebuild || *a.ls.overflow != 0));
+            if (req) atomicOr(a.ls.rebuild, 1);
+        }
+    } else {
+        __syncthreads();
+    }
     if (!a.do_rho) return;
     const int P = S.p;
     const int Pt = P < BS ? P : BS;
@@ -332,6 +384,7 @@ struct MidArgs {
     int32_t *count;
     int32_t *start;
     int do_scan;
+    const int32_t *scan_gate;   // when set, the scan runs only if *scan_gate != 0
 };
 
 template <typename KM>
@@ -451,6 +504,7 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
         return;
     }
     if (!a.do_scan) return;
+    if (a.scan_gate && *a.scan_gate == 0) return;
     const int r = blockIdx.x - a.n_final_blocks;
     mid_scan(a.sys[r], r, a.count, a.start);
 }
@@ -482,6 +536,11 @@ struct ForceArgs {
     const void *packed;
     int32_t *sorted_idx;
     void *sorted;
+    // binning of a list rebuild, from the records the staging pass stored
+    const int32_t *bin_gate;
+    int32_t *count;
+    int32_t *bin_cellid;
+    int32_t *bin_rank;
 };
 
 template <typename T, typename KM, int SPLIT>
@@ -547,6 +606,24 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
     a.F[i] = fx;
     a.F[a.ntot + i] = fy;
     a.F[2 * a.ntot + i] = fz;
+    if (a.bin_gate && *a.bin_gate) {
+        const SysDev S = a.sys[sysi];
+        int cx, cy, cz;
+        if constexpr (sizeof(T) == 4) {
+            const PackF v = reinterpret_cast<const PackF *>(a.packed)[i];
+            cx = cell_of_fix(v.x, S.nc);
+            cy = cell_of_fix(v.y, S.nc);
+            cz = cell_of_fix(v.z, S.nc);
+        } else {
+            const PartD v = reinterpret_cast<const PartD *>(a.packed)[i];
+            cx = cell_of_frac(v.x, S.nc);
+            cy = cell_of_frac(v.y, S.nc);
+            cz = cell_of_frac(v.z, S.nc);
+        }
+        const int c = S.cell_off + (cz * S.nc + cy) * S.nc + cx;
+        a.bin_cellid[i] = c;
+        a.bin_rank[i] = atomicAdd(&a.count[c], 1);
+    }
     if (a.do_scatter) {
         const int slot = a.start[a.cellid[i] + sysi] + a.rank[i];
         a.sorted_idx[slot] = (int32_t)i;
@@ -810,6 +887,11 @@ static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const S
     a.do_sample = rq.sample;
     a.do_rho = rq.rho;
     a.chunk = c.rho_chunk;
+    a.list_mode = rq.list ? 1 : 0;
+    if (rq.list) a.ls = *rq.list;
+    a.slot_of = w.slot_of;
+    a.sorted = w.sorted;
+    a.ref = w.ref;
     int table_lds, tab_max;
     const size_t sm = stage_lds_bytes(c, rq.sample, &table_lds, &tab_max);
     a.table_lds = table_lds;
@@ -835,7 +917,8 @@ hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageReque
 }
 
 template <typename KM>
-static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan)
+static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
+                               const int32_t *gate)
 {
     MidArgs<KM> a;
     a.sys = w.sys;
@@ -852,21 +935,22 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.count = w.cell_count;
     a.start = w.cell_start;
     a.do_scan = do_scan;
+    a.scan_gate = gate;
     const int nb = a.n_final_blocks + (do_scan ? c.R : 0);
     if (nb == 0) return hipSuccess;
     k_mid<KM><<<nb, 1024, 0, c.stream>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan)
+hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan, const int32_t *gate)
 {
-    return c.prec == RBE_FP64 ? mid_dispatch<KModeD>(c, w, do_final, do_scan)
-                              : mid_dispatch<KModeF>(c, w, do_final, do_scan);
+    return c.prec == RBE_FP64 ? mid_dispatch<KModeD>(c, w, do_final, do_scan, gate)
+                              : mid_dispatch<KModeF>(c, w, do_final, do_scan, gate);
 }
 
 template <typename T, typename KM>
 static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *F,
-                                  int acc, int scatter)
+                                  int acc, int scatter, const int32_t *bin_gate)
 {
     ForceArgs<T, KM> a;
     a.sys = w.sys;
@@ -886,6 +970,10 @@ static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const 
     a.packed = w.packed;
     a.sorted_idx = w.sorted_idx;
     a.sorted = w.sorted;
+    a.bin_gate = bin_gate;
+    a.count = w.cell_count;
+    a.bin_cellid = w.cellid;
+    a.bin_rank = w.rank;
     const int n = c.n_force_tiles;
     switch (c.force_split) {
     case 1:
@@ -902,10 +990,10 @@ static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const 
 }
 
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
-                         int accumulate, int scatter)
+                         int accumulate, int scatter, const int32_t *bin_gate)
 {
-    return c.prec == RBE_FP64 ? kforce_dispatch<double, KModeD>(c, w, pos, q, force, accumulate, scatter)
-                              : kforce_dispatch<float, KModeF>(c, w, pos, q, force, accumulate, scatter);
+    return c.prec == RBE_FP64 ? kforce_dispatch<double, KModeD>(c, w, pos, q, force, accumulate, scatter, bin_gate)
+                              : kforce_dispatch<float, KModeF>(c, w, pos, q, force, accumulate, scatter, bin_gate);
 }
 
 template <typename T, typename KM>

@@ -4,7 +4,11 @@
 // eq. (2.9) and the second term of eq. (2.11); the shifted Lennard-Jones
 // repulsion of eq. (4.1) with r_off = 0.  The paper leaves the neighbour
 // search open; here it is a cell list with cells of side >= the largest
-// cutoff, rebuilt for every evaluation.
+// cutoff (+ skin), rebuilt for every stand-alone evaluation, and inside
+// rbe_step a Verlet list of the pairs within cutoff + skin, rebuilt on the
+// device whenever some particle has moved more than skin/2 since the last
+// build (the rebuild step evaluates the forces on the cell list and writes
+// the list in the same pass).
 //
 // Pair force on particle i: phi(r) d with d = r_j - r_i (minimum image),
 //   phi = -coulomb q_i q_j (erfc(beta r)/r + 2 beta exp(-alpha r^2)/sqrt(pi)) / r^2
@@ -23,6 +27,9 @@
 // added in a fixed order, so the result does not depend on the order of the
 // particles inside a cell (which comes from atomic counters) beyond double
 // rounding.  Systems with fewer than three cells per side use all-pairs tiles.
+//
+// List pass: LPP lanes per particle walk its list in strides of LPP; the
+// LPP partial sums are combined by a fixed butterfly.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -147,8 +154,8 @@ __device__ __forceinline__ double pair_phi(const SysDev &S, double qi, double qj
 // the record's own units (fixed-point units for PackF).
 struct Geo {
     float scale;     // PackF: box length of one fixed-point unit
-    float rmax2u;    // PackF: largest cutoff^2 in fixed-point units
-    double rmax2;    // PartD: largest cutoff^2
+    float rmax2u;    // PackF: search radius^2 in fixed-point units
+    double rmax2;    // PartD: search radius^2
     double L;
 };
 
@@ -160,6 +167,17 @@ __device__ __forceinline__ Geo make_geo(const SysDev &S)
     g.scale = (float)(S.L * (1.0 / 4294967296.0));
     g.rmax2u = (float)(rmax2 / ((double)g.scale * (double)g.scale));
     g.rmax2 = rmax2;
+    g.L = S.L;
+    return g;
+}
+
+// The same with the list radius (cutoff + skin) as search radius.
+__device__ __forceinline__ Geo list_geo(const SysDev &S)
+{
+    Geo g;
+    g.scale = (float)(S.L * (1.0 / 4294967296.0));
+    g.rmax2u = (float)(S.rlist2 / ((double)g.scale * (double)g.scale));
+    g.rmax2 = S.rlist2;
     g.L = S.L;
     return g;
 }
@@ -217,37 +235,44 @@ __device__ __forceinline__ void cell_coords(const PartD &p, int nc, int &cx, int
     cz = cell_of_frac(p.z, nc);
 }
 
-// Calls f(pb, b) for every record b != self of one stencil row (cells
-// cx-1..cx+1 of row (yy, zz), x taken modulo nc) within the largest cutoff.
-// A row segment of at most 64 records is scanned into a hit mask first;
-// longer segments are visited directly.
-template <typename Rec, typename F>
-__device__ __forceinline__ void visit_row(const Rec &pa, int self, int cx, int yy, int zz, int nc,
-                                          const int32_t *st, const Rec *gs, const Geo &geo, F &&f)
+// One stencil row of a particle: cells cx-1..cx+1 of row (yy, zz), x taken
+// modulo nc, as one or two contiguous ranges of cell-sorted slots.  Ranges of
+// at most 64 slots are scanned into hit masks (records within the search
+// radius, self excluded); longer ranges are left for a direct walk.
+struct RowScan {
+    int b0[2], b1[2];
+    uint64_t m[2];
+    int nseg;
+    bool walk;   // some range exceeds 64 slots
+};
+
+template <typename Rec>
+__device__ __forceinline__ void row_scan(const Rec &pa, int self, int cx, int yy, int zz, int nc,
+                                         const int32_t *st, const Rec *gs, const Geo &geo, RowScan &rs)
 {
     const int base = (zz * nc + yy) * nc;
-    int sb[2], se[2], nseg;
     if (cx >= 1 && cx + 1 < nc) {
-        sb[0] = st[base + cx - 1];
-        se[0] = st[base + cx + 2];
-        nseg = 1;
+        rs.b0[0] = st[base + cx - 1];
+        rs.b1[0] = st[base + cx + 2];
+        rs.nseg = 1;
     } else if (cx == 0) {
-        sb[0] = st[base];
-        se[0] = st[base + 2];
-        sb[1] = st[base + nc - 1];
-        se[1] = st[base + nc];
-        nseg = 2;
+        rs.b0[0] = st[base];
+        rs.b1[0] = st[base + 2];
+        rs.b0[1] = st[base + nc - 1];
+        rs.b1[1] = st[base + nc];
+        rs.nseg = 2;
     } else {
-        sb[0] = st[base + nc - 2];
-        se[0] = st[base + nc];
-        sb[1] = st[base];
-        se[1] = st[base + 1];
-        nseg = 2;
+        rs.b0[0] = st[base + nc - 2];
+        rs.b1[0] = st[base + nc];
+        rs.b0[1] = st[base];
+        rs.b1[1] = st[base + 1];
+        rs.nseg = 2;
     }
-    for (int s = 0; s < nseg; ++s) {
-        const int b0 = sb[s], b1 = se[s];
+    rs.walk = false;
+    for (int s = 0; s < rs.nseg; ++s) {
+        const int b0 = rs.b0[s], b1 = rs.b1[s];
+        uint64_t m = 0;
         if (b1 - b0 <= 64) {
-            uint64_t m = 0;
             for (int b = b0; b < b1; b += 2) {
                 const int b2 = b + 1 < b1 ? b + 1 : b;
                 const Rec p0 = gs[b];
@@ -257,6 +282,22 @@ __device__ __forceinline__ void visit_row(const Rec &pa, int self, int cx, int y
                 m |= (uint64_t)(h0 ? 1u : 0u) << (b - b0);
                 m |= (uint64_t)(h1 ? 1u : 0u) << (b2 - b0);
             }
+        } else {
+            rs.walk = true;
+        }
+        rs.m[s] = m;
+    }
+}
+
+// Calls f(pb, b) for every hit of a scanned row (masks, then direct walks).
+template <typename Rec, typename F>
+__device__ __forceinline__ void row_visit(const Rec &pa, int self, const RowScan &rs, const Rec *gs, const Geo &geo,
+                                          F &&f)
+{
+    for (int s = 0; s < rs.nseg; ++s) {
+        const int b0 = rs.b0[s], b1 = rs.b1[s];
+        if (b1 - b0 <= 64) {
+            uint64_t m = rs.m[s];
             while (m) {
                 const int o = __builtin_ctzll(m);
                 m &= m - 1;
@@ -287,6 +328,16 @@ struct RealArgs {
     T *vel;                  // kick target (may be NULL); velocities for kinetic energy when ENERGY
     int32_t *flag;
     double *epart;           // ENERGY: [tiles][8]
+};
+
+// Neighbour-list state seen by the real-space pass of a step.
+struct ListArgs {
+    ListStep ls;
+    const Tile *list_tiles;
+    int n_rows, n_list;      // tiles of the cell pass and of the list pass
+    int32_t *nbr;
+    int32_t *nnb;
+    int kmax;
 };
 
 // Store (or add) the real-space force of particle i and apply the optional
@@ -346,129 +397,265 @@ __device__ __forceinline__ SysDev pair_consts<double>(const SysDev &S)
     return S;
 }
 
+// All-pairs tile: particles [start, start + count) of a one-cell system, one
+// per thread, partners in original index order.
+template <typename T, bool ENERGY>
+__device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &t, const SysDev &S, double *ev)
+{
+    using Rec = typename RBT<T>::Rec;
+    const Geo geo = make_geo<T>(S);
+    const auto pc = pair_consts<T>(S);
+    const Rec *pk = reinterpret_cast<const Rec *>(a.packed) + S.off;
+    if ((int)threadIdx.x >= t.count) return;
+    const int il = t.start + threadIdx.x;
+    const Rec pa = pk[il];
+    double fx = 0, fy = 0, fz = 0;
+    PairE e{0, 0};
+    for (int j = 0; j < S.n; ++j) {
+        if (j == il) continue;
+        const Rec pb = pk[j];
+        if (!near_test(pa, pb, geo)) continue;
+        T dx, dy, dz, r2;
+        displacement(pa, pb, geo, dx, dy, dz, r2);
+        const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
+        fx += (double)(phi * dx);
+        fy += (double)(phi * dy);
+        fz += (double)(phi * dz);
+        if constexpr (ENERGY) ev[2] += 0.5 * (double)(phi * r2);
+    }
+    if constexpr (ENERGY) {
+        ev[0] += e.e_real;
+        ev[1] += e.e_lj;
+    }
+    finish_particle<T, ENERGY>(a, S, S.off + il, fx, fy, fz, ev);
+}
+
+// Row-lane tile on the cell list.  With BUILD the rows are scanned with the
+// list radius and every hit is also written to the particle's list: the nine
+// row counts are prefixed in LDS so that the list keeps row order.
+template <typename T, bool ENERGY, bool BUILD>
+__device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *la, const Tile &t, const SysDev &S,
+                                          double *ev)
+{
+    using Rec = typename RBT<T>::Rec;
+    __shared__ double s_red[ENERGY ? 6 : 3][RL_BS];
+    __shared__ int s_cnt[BUILD ? RL_BS : 1];
+    const Geo geo = BUILD ? list_geo(S) : make_geo<T>(S);
+    const auto pc = pair_consts<T>(S);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int p = lane / 9, r = lane - 9 * (lane / 9);
+    const int k = wave * RL_PPW + p;
+    const bool act = lane < 9 * RL_PPW && k < t.count;
+    double fx = 0, fy = 0, fz = 0, vir = 0;
+    PairE e{0, 0};
+    int slot = -1;
+    const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
+    Rec pa{};
+    RowScan rs;
+    rs.nseg = 0;
+    rs.walk = false;
+    if (act) {
+        slot = S.off + t.start + k;
+        pa = gs[slot];
+        const int nc = S.nc;
+        int cx, cy, cz;
+        cell_coords<T>(pa, nc, cx, cy, cz);
+        const int zz = (cz + r / 3 - 1 + nc) % nc, yy = (cy + r % 3 - 1 + nc) % nc;
+        const int32_t *st = a.start + S.cell_off + t.sys;
+        row_scan(pa, slot, cx, yy, zz, nc, st, gs, geo, rs);
+    }
+    int pos = 0, total = 0;
+    if constexpr (BUILD) {
+        int cnt = 0;
+        for (int s = 0; s < rs.nseg; ++s) cnt += __builtin_popcountll(rs.m[s]);
+        s_cnt[tid] = cnt + (rs.walk ? (1 << 20) : 0);   // a walked row cannot be listed
+        __syncthreads();
+        if (act) {
+            const int first = tid - r;
+            for (int j = 0; j < 9; ++j) {
+                const int v = s_cnt[first + j];
+                if (j < r) pos += v;
+                total += v;
+            }
+        }
+    }
+    if (act) {
+        row_visit(pa, slot, rs, gs, geo, [&](const Rec &pb, int b) {
+            T dx, dy, dz, r2;
+            displacement(pa, pb, geo, dx, dy, dz, r2);
+            const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
+            fx += (double)(phi * dx);
+            fy += (double)(phi * dy);
+            fz += (double)(phi * dz);
+            if constexpr (ENERGY) vir += 0.5 * (double)(phi * r2);
+            if constexpr (BUILD) {
+                if (pos < la->kmax) la->nbr[(int64_t)pos * a.ntot + slot] = b;
+                ++pos;
+            }
+        });
+    }
+    // add the nine row sums of each particle in row order
+    s_red[0][tid] = fx;
+    s_red[1][tid] = fy;
+    s_red[2][tid] = fz;
+    if constexpr (ENERGY) {
+        s_red[3][tid] = e.e_real;
+        s_red[4][tid] = e.e_lj;
+        s_red[5][tid] = vir;
+    }
+    __syncthreads();
+    if (act && r == 0) {
+        double sx = 0, sy = 0, sz = 0;
+        for (int j = 0; j < 9; ++j) {
+            sx += s_red[0][tid + j];
+            sy += s_red[1][tid + j];
+            sz += s_red[2][tid + j];
+        }
+        if constexpr (ENERGY)
+            for (int j = 0; j < 9; ++j) {
+                ev[0] += s_red[3][tid + j];
+                ev[1] += s_red[4][tid + j];
+                ev[2] += s_red[5][tid + j];
+            }
+        if constexpr (BUILD) {
+            // an overflowing list is never read (the next step rebuilds)
+            la->nnb[slot] = total <= la->kmax ? total : 0;
+            if (total > la->kmax) atomicOr(la->ls.overflow, 1);
+        }
+        finish_particle<T, ENERGY>(a, S, a.sorted_idx[slot], sx, sy, sz, ev);
+    }
+}
+
+// Block partials of the energy sums.
+__device__ __forceinline__ void energy_block(double *ev, double *out)
+{
+    __shared__ double s_blk[8][RL_BS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int k = 0; k < 8; ++k) {
+        double v = ev[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) s_blk[k][wave] = v;
+    }
+    __syncthreads();
+    if (tid < 8) {
+        double v = 0.0;
+        for (int w = 0; w < RL_BS / 64; ++w) v += s_blk[tid][w];
+        out[tid] = v;
+    }
+}
+
 template <typename T, bool ENERGY>
 __global__ __launch_bounds__(RL_BS) void k_real_rows(RealArgs<T> a)
 {
-    using Rec = typename RBT<T>::Rec;
-    __shared__ double s_red[6][RL_BS];
-    __shared__ double s_blk[8][RL_BS / 64];
     const Tile t = a.tiles[blockIdx.x];
     const SysDev S = a.sys[t.sys];
+    double ev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (t.aux == 1)
+        allpairs_body<T, ENERGY>(a, t, S, ev);
+    else
+        rows_body<T, ENERGY, false>(a, nullptr, t, S, ev);
+    if constexpr (ENERGY) energy_block(ev, a.epart + 8 * blockIdx.x);
+}
+
+// List tile: LPP lanes per cell-sorted slot.
+template <typename T, int LPP>
+__device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &la, const Tile &t, const SysDev &S)
+{
+    using Rec = typename RBT<T>::Rec;
     const Geo geo = make_geo<T>(S);
     const auto pc = pair_consts<T>(S);
     const int tid = threadIdx.x;
-    double ev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (t.aux == 1) {
-        // all pairs: particles [start, start + count) of the system, one per
-        // thread, partners in original index order
-        const Rec *pk = reinterpret_cast<const Rec *>(a.packed) + S.off;
-        if (tid < t.count) {
-            const int il = t.start + tid;
-            const Rec pa = pk[il];
-            double fx = 0, fy = 0, fz = 0;
-            PairE e{0, 0};
-            for (int j = 0; j < S.n; ++j) {
-                if (j == il) continue;
-                const Rec pb = pk[j];
-                if (!near_test(pa, pb, geo)) continue;
-                T dx, dy, dz, r2;
-                displacement(pa, pb, geo, dx, dy, dz, r2);
-                const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
-                fx += (double)(phi * dx);
-                fy += (double)(phi * dy);
-                fz += (double)(phi * dz);
-                if constexpr (ENERGY) ev[2] += 0.5 * (double)(phi * r2);
-            }
-            if constexpr (ENERGY) {
-                ev[0] += e.e_real;
-                ev[1] += e.e_lj;
-            }
-            finish_particle<T, ENERGY>(a, S, S.off + il, fx, fy, fz, ev);
-        }
-    } else {
-        const int wave = tid >> 6, lane = tid & 63;
-        const int p = lane / 9, r = lane - 9 * (lane / 9);
-        const int k = wave * RL_PPW + p;
-        const bool act = lane < 9 * RL_PPW && k < t.count;
-        double fx = 0, fy = 0, fz = 0, vir = 0;
+    const int k = tid / LPP, sub = tid % LPP;
+    const bool act = k < t.count;
+    double fx = 0, fy = 0, fz = 0;
+    int slot = 0;
+    if (act) {
+        slot = S.off + t.start + k;
+        const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
+        const Rec pa = gs[slot];
+        const int n = la.nnb[slot];
+        const int32_t *nb = la.nbr + slot;
         PairE e{0, 0};
-        int slot = -1;
-        if (act) {
-            slot = S.off + t.start + k;
-            const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
-            const Rec pa = gs[slot];
-            const int nc = S.nc;
-            int cx, cy, cz;
-            cell_coords<T>(pa, nc, cx, cy, cz);
-            const int zz = (cz + r / 3 - 1 + nc) % nc, yy = (cy + r % 3 - 1 + nc) % nc;
-            const int32_t *st = a.start + S.cell_off + t.sys;
-            visit_row(pa, slot, cx, yy, zz, nc, st, gs, geo, [&](const Rec &pb, int) {
-                T dx, dy, dz, r2;
-                displacement(pa, pb, geo, dx, dy, dz, r2);
-                const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
-                fx += (double)(phi * dx);
-                fy += (double)(phi * dy);
-                fz += (double)(phi * dz);
-                if constexpr (ENERGY) vir += 0.5 * (double)(phi * r2);
-            });
-        }
-        // add the nine row sums of each particle in row order
-        s_red[0][tid] = fx;
-        s_red[1][tid] = fy;
-        s_red[2][tid] = fz;
-        if constexpr (ENERGY) {
-            s_red[3][tid] = e.e_real;
-            s_red[4][tid] = e.e_lj;
-            s_red[5][tid] = vir;
-        }
-        __syncthreads();
-        if (act && r == 0) {
-            double sx = 0, sy = 0, sz = 0;
-            for (int j = 0; j < 9; ++j) {
-                sx += s_red[0][tid + j];
-                sy += s_red[1][tid + j];
-                sz += s_red[2][tid + j];
-            }
-            if constexpr (ENERGY)
-                for (int j = 0; j < 9; ++j) {
-                    ev[0] += s_red[3][tid + j];
-                    ev[1] += s_red[4][tid + j];
-                    ev[2] += s_red[5][tid + j];
-                }
-            finish_particle<T, ENERGY>(a, S, a.sorted_idx[slot], sx, sy, sz, ev);
+        for (int j = sub; j < n; j += LPP) {
+            const int b = nb[(int64_t)j * a.ntot];
+            const Rec pb = gs[b];
+            T dx, dy, dz, r2;
+            displacement(pa, pb, geo, dx, dy, dz, r2);
+            const T phi = pair_phi<false>(pc, (T)pa.q, (T)pb.q, r2, e);
+            fx += (double)(phi * dx);
+            fy += (double)(phi * dy);
+            fz += (double)(phi * dz);
         }
     }
-    if constexpr (ENERGY) {
-        const int lane = tid & 63, wave = tid >> 6;
-        for (int k = 0; k < 8; ++k) {
-            double v = ev[k];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-            if (lane == 0) s_blk[k][wave] = v;
-        }
-        __syncthreads();
-        if (tid < 8) {
-            double v = 0.0;
-            for (int w = 0; w < RL_BS / 64; ++w) v += s_blk[tid][w];
-            a.epart[8 * blockIdx.x + tid] = v;
-        }
+    for (int o = 1; o < LPP; o <<= 1) {
+        fx += __shfl_xor(fx, o, 64);
+        fy += __shfl_xor(fy, o, 64);
+        fz += __shfl_xor(fz, o, 64);
+    }
+    if (act && sub == 0) finish_particle<T, false>(a, S, a.sorted_idx[slot], fx, fy, fz, nullptr);
+}
+
+// Real-space pass of one time step: the cell pass with list build when the
+// step's rebuild flag is set, else the list pass.  Block 0 clears the next
+// step's flag (nothing else touches it during this launch).
+template <typename T, int LPP>
+__global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
+{
+    const int rebuild = *la.ls.rebuild;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *la.ls.rebuild_next = 0;
+    if (rebuild) {
+        if ((int)blockIdx.x >= la.n_rows) return;
+        const Tile t = a.tiles[blockIdx.x];
+        const SysDev S = a.sys[t.sys];
+        if (t.aux == 1)
+            allpairs_body<T, false>(a, t, S, nullptr);
+        else
+            rows_body<T, false, true>(a, &la, t, S, nullptr);
+    } else {
+        if ((int)blockIdx.x >= la.n_list) return;
+        const Tile t = la.list_tiles[blockIdx.x];
+        const SysDev S = a.sys[t.sys];
+        if (t.aux == 1)
+            allpairs_body<T, false>(a, t, S, nullptr);
+        else
+            list_body<T, LPP>(a, la, t, S);
     }
 }
 
 // Stand-alone scatter into cell order (the force kernel does this inline
 // during a time step).
+// With a list step (gate), it runs only on rebuild steps and also records
+// each particle's slot and reference record, clears the overflow flag and
+// counts the build.
 template <typename Rec>
 __global__ __launch_bounds__(256) void k_scatter(const SysDev *__restrict__ sys, const Tile *__restrict__ tiles,
                                                  const int32_t *__restrict__ start, const int32_t *__restrict__ cellid,
                                                  const int32_t *__restrict__ rank, const Rec *__restrict__ packed,
-                                                 int32_t *__restrict__ sorted_idx, Rec *__restrict__ sorted)
+                                                 int32_t *__restrict__ sorted_idx, Rec *__restrict__ sorted,
+                                                 const int32_t *gate, int32_t *overflow, int32_t *builds,
+                                                 int32_t *slot_of, Rec *ref)
 {
+    if (gate) {
+        if (*gate == 0) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *overflow = 0;
+            *builds += 1;
+        }
+    }
     const Tile t = tiles[blockIdx.x];
     if ((int)threadIdx.x >= t.count) return;
     const int64_t i = sys[t.sys].off + t.start + threadIdx.x;
     const int slot = start[cellid[i] + t.sys] + rank[i];
+    const Rec v = packed[i];
     sorted_idx[slot] = (int32_t)i;
-    sorted[slot] = packed[i];
+    sorted[slot] = v;
+    if (gate) {
+        slot_of[i] = slot;
+        ref[i] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -575,7 +762,9 @@ __global__ __launch_bounds__(RL_BS) void k_vjp_real(RealArgs<T> a, const T *__re
         cell_coords<T>(pa, nc, cx, cy, cz);
         const int zz = (cz + r / 3 - 1 + nc) % nc, yy = (cy + r % 3 - 1 + nc) % nc;
         const int32_t *st = a.start + S.cell_off + t.sys;
-        visit_row(pa, slot, cx, yy, zz, nc, st, gs, geo, [&](const Rec &pb, int b) {
+        RowScan rs;
+        row_scan(pa, slot, cx, yy, zz, nc, st, gs, geo, rs);
+        row_visit(pa, slot, rs, gs, geo, [&](const Rec &pb, int b) {
             T dx, dy, dz, r2;
             displacement(pa, pb, geo, dx, dy, dz, r2);
             const int64_t jj = a.sorted_idx[b];
@@ -617,16 +806,21 @@ hipError_t launch_fill_zero(hipStream_t s, void *ptr, int64_t nbytes)
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w)
+hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls)
 {
+    const int32_t *gate = ls ? ls->rebuild : nullptr;
+    int32_t *ovf = ls ? ls->overflow : nullptr;
+    int32_t *nb = ls ? ls->rebuilds : nullptr;
     if (c.prec == RBE_FP64)
         k_scatter<PartD><<<c.n_part_tiles, 256, 0, c.stream>>>(w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
                                                                (const PartD *)w.packed, w.sorted_idx,
-                                                               (PartD *)w.sorted);
+                                                               (PartD *)w.sorted, gate, ovf, nb, w.slot_of,
+                                                               (PartD *)w.ref);
     else
         k_scatter<PackF><<<c.n_part_tiles, 256, 0, c.stream>>>(w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
                                                                (const PackF *)w.packed, w.sorted_idx,
-                                                               (PackF *)w.sorted);
+                                                               (PackF *)w.sorted, gate, ovf, nb, w.slot_of,
+                                                               (PackF *)w.ref);
     return hipGetLastError();
 }
 
@@ -659,6 +853,49 @@ hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int 
     else
         k_real_rows<float, false><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
             real_args<float>(c, w, force, accumulate, vel_kick, nullptr));
+    return hipGetLastError();
+}
+
+template <typename T, int LPP>
+static void real_step_launch(const LaunchCfg &c, const RealArgs<T> &a, const ListArgs &la)
+{
+    const int nb = la.n_rows > la.n_list ? la.n_rows : la.n_list;
+    k_real_step<T, LPP><<<nb, RL_BS, 0, c.stream>>>(a, la);
+}
+
+template <typename T>
+static void real_step_dispatch(const LaunchCfg &c, const RealArgs<T> &a, const ListArgs &la)
+{
+    switch (c.real_split) {
+    case 1:
+        real_step_launch<T, 1>(c, a, la);
+        break;
+    case 2:
+        real_step_launch<T, 2>(c, a, la);
+        break;
+    case 8:
+        real_step_launch<T, 8>(c, a, la);
+        break;
+    default:
+        real_step_launch<T, 4>(c, a, la);
+        break;
+    }
+}
+
+hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick)
+{
+    ListArgs la;
+    la.ls = ls;
+    la.list_tiles = w.list_tiles;
+    la.n_rows = c.n_real_tiles;
+    la.n_list = c.n_list_tiles;
+    la.nbr = w.nbr;
+    la.nnb = w.nnb;
+    la.kmax = c.kmax;
+    if (c.prec == RBE_FP64)
+        real_step_dispatch<double>(c, real_args<double>(c, w, force, 1, vel_kick, nullptr), la);
+    else
+        real_step_dispatch<float>(c, real_args<float>(c, w, force, 1, vel_kick, nullptr), la);
     return hipGetLastError();
 }
 

@@ -43,8 +43,9 @@ STATUS_NAMES = {0: "RBE_OK", -1: "RBE_ERR_INVALID", -2: "RBE_ERR_NOT_NEUTRAL", -
 EXPORTED = ["rbe_normalizer", "rbe_create", "rbe_batch_create", "rbe_destroy", "rbe_last_error",
             "rbe_num_systems", "rbe_num_particles", "rbe_num_modes", "rbe_sample_k", "rbe_set_k",
             "rbe_reserve_modes", "rbe_kspace_forces", "rbe_real_forces", "rbe_step", "rbe_batch_step",
-            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_get_tiles", "rbe_set_tiles", "rbe_autotune",
-            "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name", "rbe_profile_count"]
+            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_get_tiles",
+            "rbe_set_tiles", "rbe_autotune", "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name",
+            "rbe_profile_count"]
 
 
 class RBEError(RuntimeError):
@@ -57,7 +58,7 @@ class rbe_params(C.Structure):
     _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("box", C.c_double), ("alpha", C.c_double),
                 ("r_cut", C.c_double), ("coulomb", C.c_double), ("lj_eps", C.c_double), ("lj_sigma", C.c_double),
                 ("lj_rcut", C.c_double), ("kT", C.c_double), ("gamma", C.c_double), ("dt", C.c_double),
-                ("mass", C.c_double), ("nu", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
+                ("mass", C.c_double), ("nu", C.c_double), ("skin", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
                 ("integrator", C.c_int32), ("sampler", C.c_int32), ("flags", C.c_int32)]
 
 
@@ -107,6 +108,7 @@ def lib():
     L.rbe_energy.argtypes = [vp, vp, vp, vp, C.POINTER(rbe_energy_t)]
     L.rbe_get_rho.argtypes = [vp, vp]
     L.rbe_forces_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32]
+    L.rbe_list_builds.argtypes = [vp, C.POINTER(i64)]
     L.rbe_get_tiles.argtypes = [vp, C.POINTER(rbe_tiles)]
     L.rbe_set_tiles.argtypes = [vp, C.POINTER(rbe_tiles)]
     L.rbe_autotune.argtypes = [vp, vp, vp, i32, C.POINTER(rbe_tiles)]
@@ -147,6 +149,7 @@ class Params:
     dt: float = 1e-3
     mass: float = 1.0
     nu: float = 0.0
+    skin: float = 0.0
     seed: int = 0
     precision: int = RBE_FP32
     integrator: int = RBE_LANGEVIN_BAOAB
@@ -156,14 +159,19 @@ class Params:
     def to_c(self):
         return rbe_params(self.n, self.p, self.box, self.alpha, self.r_cut, self.coulomb, self.lj_eps,
                           self.lj_sigma, self.lj_rcut, self.kT, self.gamma, self.dt, self.mass, self.nu,
-                          self.seed, self.precision, self.integrator, self.sampler, self.flags)
+                          self.skin, self.seed, self.precision, self.integrator, self.sampler, self.flags)
+
+
+DEFAULT_SKIN_FRACTION = 0.1
 
 
 def params_from_system(s, precision=RBE_FP32, **over):
-    """Params for a workloads.System."""
+    """Params for a workloads.System; the neighbour-list skin defaults to a
+    tenth of the largest cutoff."""
+    rmax = max(s.r_cut, s.lj[2] if s.lj[0] > 0 else 0.0)
     kw = dict(n=s.n, p=s.p, box=s.L, alpha=s.alpha, r_cut=s.r_cut, coulomb=s.coulomb, lj_eps=s.lj[0],
               lj_sigma=s.lj[1], lj_rcut=s.lj[2], kT=s.kT, gamma=s.gamma, dt=s.dt, mass=s.mass, seed=s.seed,
-              precision=precision)
+              skin=DEFAULT_SKIN_FRACTION * rmax, precision=precision)
     kw.update(over)
     return Params(**kw)
 
@@ -330,6 +338,13 @@ def rbe_forces_vjp(ctx, pos, q, grad_force, grad_pos, grad_q, parts=RBE_PART_ALL
     _check(lib().rbe_forces_vjp(ctx.handle, _vec3(ctx, pos, "pos"), _scal(ctx, q, "q"),
                                 _vec3(ctx, grad_force, "grad_force"), _vec3(ctx, grad_pos, "grad_pos"),
                                 _scal(ctx, grad_q, "grad_q"), parts), ctx.handle)
+
+
+def rbe_list_builds(ctx):
+    """Neighbour-list builds made by rbe_step so far (-1: no list)."""
+    v = C.c_int64()
+    _check(lib().rbe_list_builds(ctx.handle, C.byref(v)), ctx.handle)
+    return v.value
 
 
 def rbe_get_tiles(ctx):

@@ -1,0 +1,174 @@
+"""GPU parity of the time step on the neighbour list (rbe_params.skin > 0)
+against the FP64 oracle: list rebuilds triggered by motion, by the caller
+moving particles, and by overflow; batched systems; every list-pass shape.
+
+Paper: Sec. 3.1 (Algorithm 1), Sec. 3.3 (Langevin equation), eq. (2.11)
+second term and eq. (4.1) for the pair forces.  The list is an
+implementation device: every pair inside the cutoffs must be counted once,
+so the oracle (which searches all pairs) is the reference.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2010_01559_amd.rbe as R
+from paper_2010_01559_amd import workloads as W
+from gpu_util import device_state, host, make_ctx, rel_l2, rounded
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_sys(s, **over):
+    kw = dict(kT=s.kT, gamma=s.gamma, dt=s.dt)
+    kw.update(over)
+    return O.make_sys(s.n, s.p, s.L, s.alpha, s.r_cut, s.coulomb, s.lj, kw["kT"], kw["gamma"], kw["dt"], s.mass,
+                      s.seed)
+
+
+def initial_force(ctx, P, Q, F, step=0):
+    R.rbe_sample_k(ctx, step)
+    R.rbe_kspace_forces(ctx, P, Q, F)
+    R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
+
+
+def pos_err(P, po, L):
+    dp = host(P) - po
+    dp -= L * np.round(dp / L)
+    return float(np.linalg.norm(dp) / np.linalg.norm(po))
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBE_FP64, 1e-10), (R.RBE_FP32, 2e-4)])
+def test_motion_triggers_rebuilds(prec, tol):
+    """A thin skin and a long time step force a rebuild every few steps; the
+    trajectory still follows the oracle."""
+    s = W.langevin_electrolyte()
+    dt = 0.005
+    ctx = make_ctx(s, prec, skin=0.1, dt=dt)
+    P, Q, V, F = device_state(ctx, s)
+    pos, q = rounded(s, prec)
+    vel = s.vel.astype(np.float32).astype(np.float64) if prec == R.RBE_FP32 else s.vel.copy()
+    initial_force(ctx, P, Q, F)
+    sysd = oracle_sys(s, dt=dt)
+    po, vo = pos.copy(), vel.copy()
+    Fo = O.total_force(sysd, po, q, 0)
+    nsteps = 30
+    R.rbe_step(ctx, P, V, Q, F, 1, nsteps)
+    for k in range(1, nsteps + 1):
+        O.baoab_step(sysd, po, vo, q, Fo, k)
+    builds = R.rbe_list_builds(ctx)
+    assert 4 <= builds < nsteps, builds
+    assert pos_err(P, po, s.L) <= tol
+    assert rel_l2(host(V), vo) <= tol
+    assert rel_l2(host(F), Fo) <= 50 * tol
+
+
+def test_slow_motion_keeps_the_list():
+    """At the default skin a few small steps reuse the first list."""
+    s = W.langevin_electrolyte()
+    ctx = make_ctx(s, R.RBE_FP64)
+    P, Q, V, F = device_state(ctx, s)
+    initial_force(ctx, P, Q, F)
+    R.rbe_step(ctx, P, V, Q, F, 1, 6)
+    assert R.rbe_list_builds(ctx) == 1
+
+
+def test_caller_moving_particles_forces_a_rebuild():
+    """Positions replaced by the caller between calls (without any library
+    call that would invalidate the list) are caught by the displacement test."""
+    a = W.langevin_electrolyte()
+    b = W.electrolyte_system("electrolyte-n3000-b", a.n, 0.1, a.alpha, a.r_cut, a.p, a.seed + 99, L=a.L)
+    b.seed = a.seed
+    ctx = make_ctx(a, R.RBE_FP64)
+    P, Q, V, F = device_state(ctx, a)
+    initial_force(ctx, P, Q, F)
+    R.rbe_step(ctx, P, V, Q, F, 1, 3)
+    n0 = R.rbe_list_builds(ctx)
+    # new configuration and its force, written straight into the buffers
+    import torch
+    sysd = oracle_sys(b)
+    po, vo = b.pos.copy(), b.vel.copy()
+    Fo = O.total_force(sysd, po, b.q, 10)
+    P.copy_(torch.as_tensor(po, device="cuda"))
+    V.copy_(torch.as_tensor(vo, device="cuda"))
+    F.copy_(torch.as_tensor(Fo, device="cuda"))
+    R.rbe_step(ctx, P, V, Q, F, 11, 4)
+    for k in range(11, 15):
+        O.baoab_step(sysd, po, vo, b.q, Fo, k)
+    assert R.rbe_list_builds(ctx) > n0
+    assert pos_err(P, po, b.L) <= 1e-10
+    assert rel_l2(host(V), vo) <= 1e-10
+    assert rel_l2(host(F), Fo) <= 1e-9
+
+
+def test_overflow_falls_back_to_the_cell_pass():
+    """A dense cluster in a dilute box overflows the list (sized for the mean
+    density) and has cell rows longer than one hit mask: every step rebuilds
+    and the forces stay exact."""
+    L, side, a = 40.0, 12, 0.6
+    g = (np.arange(side) + 0.5) * a
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    rng = np.random.default_rng(5)
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()]) + rng.uniform(-0.05, 0.05, (3, side ** 3)) + 3.0
+    n = pos.shape[1]
+    q = np.where((np.arange(n) % 2) == 0, 1.0, -1.0)
+    s = W.System("cluster-n1728", n, L, 0.6, 3.5, 50, pos, q, W.velocities(n, rng), 4242, lj=(0.0, 1.0, 2.5))
+    ctx = make_ctx(s, R.RBE_FP64)
+    P, Q, V, F = device_state(ctx, s)
+    initial_force(ctx, P, Q, F)
+    sysd = oracle_sys(s)
+    po, vo = s.pos.copy(), s.vel.copy()
+    Fo = O.total_force(sysd, po, s.q, 0)
+    assert rel_l2(host(F), Fo) <= 1e-12
+    R.rbe_step(ctx, P, V, Q, F, 1, 4)
+    for k in range(1, 5):
+        O.baoab_step(sysd, po, vo, s.q, Fo, k)
+    assert R.rbe_list_builds(ctx) == 4
+    assert pos_err(P, po, L) <= 1e-10
+    assert rel_l2(host(F), Fo) <= 1e-9
+
+
+@pytest.mark.parametrize("lpp", [1, 2, 4, 8])
+def test_every_list_shape(lpp):
+    s = W.langevin_electrolyte()
+    ctx = make_ctx(s, R.RBE_FP64)
+    R.rbe_set_tiles(ctx, real_split=lpp)
+    assert R.rbe_get_tiles(ctx)["real_split"] == lpp
+    P, Q, V, F = device_state(ctx, s)
+    initial_force(ctx, P, Q, F)
+    sysd = oracle_sys(s)
+    po, vo = s.pos.copy(), s.vel.copy()
+    Fo = O.total_force(sysd, po, s.q, 0)
+    R.rbe_step(ctx, P, V, Q, F, 1, 3)
+    for k in range(1, 4):
+        O.baoab_step(sysd, po, vo, s.q, Fo, k)
+    assert rel_l2(host(F), Fo) <= 1e-10
+
+
+def test_batched_step_matches_each_system():
+    """Systems of uneven size (one of them all-pairs) stepped together on the
+    list: each follows its own oracle trajectory."""
+    systems = W.replica_systems(R=4, nmin=400, nmax=2500, seed=78)
+    systems.insert(1, W.small_fp64(seed=6))
+    params = [R.params_from_system(s, R.RBE_FP64) for s in systems]
+    ctx = R.rbe_batch_create(params)
+    import torch
+    cat = lambda k: np.concatenate([getattr(s, k) for s in systems], -1)
+    P = torch.as_tensor(cat("pos"), device="cuda").contiguous()
+    V = torch.as_tensor(cat("vel"), device="cuda").contiguous()
+    Q = torch.as_tensor(cat("q"), device="cuda").contiguous()
+    F = torch.zeros_like(P)
+    initial_force(ctx, P, Q, F)
+    R.rbe_batch_step(ctx, P, V, Q, F, 1, 6)
+    p, v = host(P), host(V)
+    off = 0
+    for r, s in enumerate(systems):
+        sysd = oracle_sys(s)
+        po, vo = s.pos.copy(), s.vel.copy()
+        Fo = O.total_force(sysd, po, s.q, 0)
+        for k in range(1, 7):
+            O.baoab_step(sysd, po, vo, s.q, Fo, k)
+        dp = p[:, off:off + s.n] - po
+        dp -= s.L * np.round(dp / s.L)
+        assert np.linalg.norm(dp) / np.linalg.norm(po) <= 1e-10, r
+        assert rel_l2(v[:, off:off + s.n], vo) <= 1e-10, r
+        off += s.n

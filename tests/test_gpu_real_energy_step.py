@@ -111,10 +111,12 @@ def test_energy_flags_non_neutral():
 
 
 @pytest.mark.parametrize("prec,tol", [(R.RBE_FP64, 1e-10), (R.RBE_FP32, 2e-4)])
-def test_langevin_trajectory_parity(prec, tol):
-    """Ten BAOAB steps with identical modes and noise: GPU against oracle."""
+@pytest.mark.parametrize("skin", [None, 0.0])
+def test_langevin_trajectory_parity(prec, tol, skin):
+    """Ten BAOAB steps with identical modes and noise: GPU against oracle,
+    on the neighbour list (default skin) and on the cell list of every step."""
     s = W.langevin_electrolyte()
-    ctx = make_ctx(s, prec)
+    ctx = make_ctx(s, prec) if skin is None else make_ctx(s, prec, skin=skin)
     P, Q, V, F = device_state(ctx, s)
     pos, q = rounded(s, prec)
     vel = s.vel.astype(np.float32).astype(np.float64) if prec == R.RBE_FP32 else s.vel.copy()
@@ -136,9 +138,11 @@ def test_langevin_trajectory_parity(prec, tol):
     assert rel_l2(host(F), Fo) <= 50 * tol
 
 
-def test_leapfrog_andersen_parity():
+@pytest.mark.parametrize("skin", [None, 0.0])
+def test_leapfrog_andersen_parity(skin):
     s = W.langevin_electrolyte()
-    ctx = make_ctx(s, R.RBE_FP64, integrator=R.RBE_LEAPFROG_ANDERSEN, nu=3.0, dt=0.002)
+    kw = {} if skin is None else {"skin": skin}
+    ctx = make_ctx(s, R.RBE_FP64, integrator=R.RBE_LEAPFROG_ANDERSEN, nu=3.0, dt=0.002, **kw)
     P, Q, V, F = device_state(ctx, s)
     R.rbe_sample_k(ctx, 0)
     R.rbe_kspace_forces(ctx, P, Q, F)
