@@ -115,6 +115,10 @@ rbe_status validate(const rbe_params &p, std::string &err)
                          p.alpha * p.box * p.box),
                RBE_ERR_INVALID;
     if (table_half_width(p.alpha, p.box) > (1 << 20)) return err = "alpha L^2 too large for the mode table", RBE_ERR_INVALID;
+    if (p.precision == RBE_FP32 && table_half_width(p.alpha, p.box) > 4095)
+        return err = fmt("alpha L^2 = %.3g needs modes beyond |m| = 8191, past the single-precision phase "
+                         "split; use RBE_FP64", p.alpha * p.box * p.box),
+               RBE_ERR_INVALID;
     return RBE_OK;
 }
 
@@ -472,6 +476,14 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         s.c2 = std::sqrt((1.0 - s.c1 * s.c1) * p.kT / p.mass);
         s.nu_dt = p.nu * p.dt;
         s.seed = p.seed;
+        // split of FP32 phases: |m| <= 2M must satisfy |m| < 2^(22 - hi_bits)
+        {
+            int bm = 0;
+            while ((1 << bm) <= 2 * s.M) ++bm;
+            s.hi_bits = std::min(14, 22 - bm);
+            s.hi_scale = std::ldexp(1.0f, s.hi_bits);
+            s.hi_inv = std::ldexp(1.0f, -s.hi_bits);
+        }
         s.use_list = (all_skin && nc >= 3) ? 1 : 0;
         s.rlist2 = rlist * rlist;
         s.half_skin2 = 0.25 * p.skin * p.skin;
@@ -794,9 +806,11 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
         }
     // one step = four launches: [integrate + bin + draw modes + structure-factor
     // partials] -> [totals + cell scan] -> [Fourier force + scatter] ->
-    // [real space + LJ + final half kick].  In list mode the binning moves to
-    // the force pass and the scan and scatter to launches of their own, and
-    // all three run only on rebuild steps (decided on the device).
+    // [real space + LJ + final half kick].  In list mode: [integrate + list
+    // bookkeeping + draw modes + partials] -> [totals + binning] -> [scan] ->
+    // [scatter] -> [Fourier + real space + LJ + final half kick], where the
+    // binning, scan and scatter do work only on rebuild steps (decided on the
+    // device).
     int table_lds = 0, tab_max = 0;
     const size_t lds = stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max);
     const bool fuse_sample = !c->any_mh && lds <= 64 * 1024;
@@ -811,8 +825,7 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
                         c->list_valid ? 0 : 1};
             StageRequest rq{pos, vel, force, q, s, ks, 1, 0, fuse_sample ? 1 : 0, 1, &ls};
             RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
-            RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0));
-            RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, 0, 0, ls.rebuild));
+            RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild));
             RUN(c, K_SCAN, launch_mid(c->cfg, c->w, 0, 1, ls.rebuild));
             RUN(c, K_SCATTER, launch_scatter(c->cfg, c->w, &ls));
             RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, andersen ? nullptr : vel));
@@ -965,10 +978,11 @@ rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
         return set_err(c, RBE_ERR_INVALID, "real_split must be 1, 2, 4 or 8");
     // dynamic LDS of the reduction kernels must fit
     // the adjoint reduction stages 48 bytes per particle and 16 per thread;
-    // the staging kernel 32 per particle and 28 per thread (plus the table,
+    // the staging kernel 32 per particle (plus 256 padding records) and 28
+    // per thread (plus the table,
     // which falls back to global memory when it does not fit)
     if (48 * (size_t)n.rho_chunk + 16 * (size_t)n.rho_block > 64 * 1024 ||
-        32 * (size_t)n.rho_chunk + 28 * (size_t)n.rho_block > 64 * 1024)
+        32 * ((size_t)n.rho_chunk + 256) + 28 * (size_t)n.rho_block > 64 * 1024)
         return set_err(c, RBE_ERR_INVALID, "rho_chunk and rho_block need more than 64 KB of LDS");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cfg.rho_chunk = n.rho_chunk;
@@ -1011,8 +1025,8 @@ rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps
     rbe_status s = RBE_OK;
     for (int ch : chunks)
         for (int bl : blocks) {
-            rbe_tiles t{ch, bl, cur.force_split, 1};
-            if ((s = rbe_set_tiles(c, &t)) != RBE_OK) continue;
+            rbe_tiles t{ch, bl, cur.force_split, 0};
+            if (rbe_set_tiles(c, &t) != RBE_OK) continue;   // shape does not fit
             float ms = 0.f;
             s = timeit(
                 [&]() -> rbe_status {
@@ -1037,8 +1051,10 @@ rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps
     if (s == RBE_OK) {
         const size_t esz = c->prec == RBE_FP64 ? 8 : 4;
         // the force pass needs an output: borrow the sorted workspace, which
-        // is large enough (16 or 32 bytes per particle >= 3 elements)
+        // is large enough (16 or 32 bytes per particle >= 3 elements); the
+        // neighbour list reads that workspace, so it must be rebuilt
         fbuf = c->w.sorted;
+        c->list_valid = false;
         (void)esz;
         for (int sp : {1, 2, 4}) {
             rbe_tiles t{0, 0, sp, 0};

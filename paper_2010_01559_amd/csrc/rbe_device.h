@@ -156,6 +156,69 @@ __device__ __forceinline__ int cell_of_frac(double s, int nc)
     return c >= nc ? nc - 1 : c;
 }
 
+// ---------------------------------------------------------------------------
+// Single-precision phases without loss: a box fraction s in [0, 1) is split
+// as s = hi + lo with hi a multiple of 2^-b (b = SysDev::hi_bits) and
+// 0 <= lo < 2^-b.  For integer modes with |m| < 2^(22-b) the three products
+// m_d hi_d and their sum are exact in float, so frac(m . hi) is exact; m . lo
+// is small and carries only float rounding.  The phase in revolutions is
+// frac(m . hi) + m . lo (range (-0.01, 1.01) at most, fine for the hardware
+// sine, which takes revolutions).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split_frac(double s, const SysDev &S, float &hi, float &lo)
+{
+    const double h = floor(s * (double)S.hi_scale) * (double)S.hi_inv;
+    hi = (float)h;
+    lo = (float)(s - h);
+}
+
+__device__ __forceinline__ void split_fix(uint32_t u, const SysDev &S, float &hi, float &lo)
+{
+    const int sh = 32 - S.hi_bits;
+    hi = (float)(u >> sh) * S.hi_inv;
+    lo = (float)(u & ((1u << sh) - 1u)) * (1.0f / 4294967296.0f);
+}
+
+__device__ __forceinline__ float phase_split(float mx, float my, float mz, float hx, float hy, float hz, float lx,
+                                             float ly, float lz)
+{
+    const float hi = fmaf(mx, hx, fmaf(my, hy, mz * hz));
+    const float lo = fmaf(mx, lx, fmaf(my, ly, mz * lz));
+    return __builtin_amdgcn_fractf(hi) + lo;
+}
+
+// Fourier force of the modes [l0, l1) of one system on one particle, summed
+// in mode order (eq. 3.6 without the factor -q_i).  kk is wave-uniform.
+__device__ __forceinline__ void fourier_range(const KModeF *kk, int l0, int l1, const float h[3], const float lo[3],
+                                              float f[3])
+{
+#pragma unroll 4
+    for (int l = l0; l < l1; ++l) {
+        const KModeF k = kk[l];
+        const float rf = phase_split(k.m[0], k.m[1], k.m[2], h[0], h[1], h[2], lo[0], lo[1], lo[2]);
+        const float sn = __builtin_amdgcn_sinf(rf), cs = __builtin_amdgcn_cosf(rf);
+        const float im = cs * k.S - sn * k.C;
+        f[0] = fmaf(im, k.a[0], f[0]);
+        f[1] = fmaf(im, k.a[1], f[1]);
+        f[2] = fmaf(im, k.a[2], f[2]);
+    }
+}
+
+__device__ __forceinline__ void fourier_range(const KModeD *kk, int l0, int l1, const double s[3], double f[3])
+{
+#pragma unroll 2
+    for (int l = l0; l < l1; ++l) {
+        const KModeD k = kk[l];
+        const double ph = wrap_rev(fma(k.m[0], s[0], fma(k.m[1], s[1], k.m[2] * s[2])));
+        double sn, cs;
+        sincospi(2.0 * ph, &sn, &cs);
+        const double im = cs * k.S - sn * k.C;
+        f[0] = fma(im, k.a[0], f[0]);
+        f[1] = fma(im, k.a[1], f[1]);
+        f[2] = fma(im, k.a[2], f[2]);
+    }
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave.
 __device__ __forceinline__ int wave_incl_scan(int v)
 {

@@ -33,7 +33,8 @@ struct SysDev {
     int32_t mh_state_off;  // three int32 chain states at this offset
     int32_t ncell;         // nc^3
     int32_t use_list;      // neighbour list in rbe_step (skin > 0 and nc >= 3)
-    int32_t pad0;
+    int32_t hi_bits;       // FP32 phases: box fractions split as hi (multiple of 2^-hi_bits) + lo
+    float hi_scale, hi_inv;  // 2^hi_bits, 2^-hi_bits
     double L, invL;
     double alpha, beta;     // beta = sqrt(alpha)
     double rc2;             // r_cut^2
@@ -56,14 +57,13 @@ struct Tile {
     int32_t aux;     // structure-factor tiles: index of this tile within its system
 };
 
-// Per-mode constants for the force pass (single precision path).  The phase
-// uses the mode in double; the force coefficients a = w 2 m/(L^2 |m|^2) and
-// the structure factor (C, S) are in float.
+// Per-mode constants for the force pass (single precision path): the mode
+// (small integers, exact in float), the force coefficients
+// a = w 2 m/(L^2 |m|^2) and the structure factor (C, S).
 struct KModeF {
-    double m[3];
+    float m[3];
     float a[3];
     float C, S;
-    float pad;
 };
 
 struct KModeD {
@@ -183,7 +183,7 @@ hipError_t launch_sample(const LaunchCfg &c, const Workspace &w, uint64_t step, 
 hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageRequest &rq);
 size_t stage_lds_bytes(const LaunchCfg &c, int sample_in_kernel, int *table_lds, int *tab_max);
 hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
-                      const int32_t *scan_gate = nullptr);
+                      const int32_t *scan_gate = nullptr, const int32_t *bin_gate = nullptr);
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
                          int accumulate, int scatter, const int32_t *bin_gate = nullptr);
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);

@@ -243,14 +243,72 @@ __device__ __forceinline__ bool list_update(const SysDev &S, int64_t i, double s
     return moved;
 }
 
+// LDS record of the structure-factor pass: fractional coordinates in double
+// and the charge in the working precision.
+template <typename T>
+struct RhoRec;
+template <>
+struct RhoRec<float> {
+    struct type {
+        float hx, hy, hz, lx, ly, lz, q, pad;   // split box fractions, charge
+    };
+};
+template <>
+struct RhoRec<double> {
+    using type = PartD;
+};
+
+__device__ __forceinline__ void rho_record(const SysDev &S, double sx, double sy, double sz, float q,
+                                           RhoRec<float>::type &v)
+{
+    split_frac(sx, S, v.hx, v.lx);
+    split_frac(sy, S, v.hy, v.ly);
+    split_frac(sz, S, v.hz, v.lz);
+    v.q = q;
+    v.pad = 0.0f;
+}
+
+__device__ __forceinline__ void rho_record(const SysDev &, double sx, double sy, double sz, double q, PartD &v)
+{
+    v.x = sx;
+    v.y = sy;
+    v.z = sz;
+    v.q = q;
+}
+
+// One particle-mode term of the structure factor, added to (c, s).
+__device__ __forceinline__ void rho_term(const RhoRec<float>::type &v, float mx, float my, float mz, float &c,
+                                         float &s)
+{
+    const float rf = phase_split(mx, my, mz, v.hx, v.hy, v.hz, v.lx, v.ly, v.lz);
+    const float sn = __builtin_amdgcn_sinf(rf), cs = __builtin_amdgcn_cosf(rf);
+    c = fmaf(v.q, cs, c);
+    s = fmaf(v.q, sn, s);
+}
+
+__device__ __forceinline__ void rho_term(const PartD &v, double mx, double my, double mz, double &c, double &s)
+{
+    const double ph = wrap_rev(fma(mx, v.x, fma(my, v.y, mz * v.z)));
+    double sn, cs;
+    sincospi(2.0 * ph, &sn, &cs);
+    c = fma(v.q, cs, c);
+    s = fma(v.q, sn, s);
+}
+
+// Particle groups per block are capped so that the zero-charge padding of a
+// chunk (up to 8 records per group) stays small.
+constexpr int kRhoGroupsMax = 32;
+constexpr int kRhoUnroll = 8;
+
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = a.tiles[blockIdx.x];
     const SysDev S = a.sys[t.sys];
-    PartD *sp = reinterpret_cast<PartD *>(smem);
-    double2 *red = reinterpret_cast<double2 *>(smem + sizeof(PartD) * a.chunk);
+    using RR = typename RhoRec<T>::type;
+    RR *sp = reinterpret_cast<RR *>(smem);
+    double2 *red = reinterpret_cast<double2 *>(smem + sizeof(RR) * (a.chunk + kRhoUnroll * kRhoGroupsMax));
     double *tab = reinterpret_cast<double *>(red + BS);
     int *smode = reinterpret_cast<int *>(tab + a.tab_max);  // [3][BS]
     const int tid = threadIdx.x;
@@ -270,15 +328,13 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
             x[1] = (double)a.pos[a.ntot + i];
             x[2] = (double)a.pos[2 * a.ntot + i];
         }
-        PartD v;
-        v.x = frac01(x[0] * S.invL);
-        v.y = frac01(x[1] * S.invL);
-        v.z = frac01(x[2] * S.invL);
+        const double sx = frac01(x[0] * S.invL), sy = frac01(x[1] * S.invL), sz = frac01(x[2] * S.invL);
         const T qi = a.q[i];
-        v.q = (double)qi;
+        RR v;
+        rho_record(S, sx, sy, sz, qi, v);
         sp[j] = v;
-        if (a.do_bin) bin_one<T>(S, i, v.x, v.y, v.z, qi, a.count, a.cellid, a.rank, a.packed);
-        if (a.list_mode) moved |= list_update<T>(S, i, v.x, v.y, v.z, qi, a);
+        if (a.do_bin) bin_one<T>(S, i, sx, sy, sz, qi, a.count, a.cellid, a.rank, a.packed);
+        if (a.list_mode) moved |= list_update<T>(S, i, sx, sy, sz, qi, a);
     }
     if (a.list_mode) {
         // one request per block; block 0 adds the host's and the overflow's
@@ -293,7 +349,14 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
     if (!a.do_rho) return;
     const int P = S.p;
     const int Pt = P < BS ? P : BS;
-    const int G = BS / Pt;
+    const int G = BS / Pt < kRhoGroupsMax ? BS / Pt : kRhoGroupsMax;
+    // zero-charge records up to a multiple of 8 G, so the unrolled loop
+    // below needs no bounds tests
+    const int cpad = (count + kRhoUnroll * G - 1) / (kRhoUnroll * G) * (kRhoUnroll * G);
+    for (int j = count + tid; j < cpad; j += BS) {
+        RR z{};
+        sp[j] = z;
+    }
     const double *tabp = a.table_lds ? tab : a.cdf + S.cdf_off;
     double *prow = a.partial + 2 * ((int64_t)a.part_off[t.sys] + (int64_t)t.aux * P);
     for (int m0 = 0; m0 < P; m0 += Pt) {
@@ -326,22 +389,11 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         const bool act = g < G && l < P;
         double C = 0.0, Sn = 0.0;
         if (act) {
-            const double mx = (double)smode[lt], my = (double)smode[BS + lt], mz = (double)smode[2 * BS + lt];
-            for (int j0 = g; j0 < count; j0 += 8 * G) {
+            const T mx = (T)smode[lt], my = (T)smode[BS + lt], mz = (T)smode[2 * BS + lt];
+            for (int j0 = g; j0 < cpad; j0 += kRhoUnroll * G) {
                 T c8 = 0, s8 = 0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int j = j0 + u * G;
-                    if (j < count) {
-                        const PartD v = sp[j];
-                        const double ph = wrap_rev(fma(mx, v.x, fma(my, v.y, mz * v.z)));
-                        T sn, cs;
-                        sincos_rev(ph, &sn, &cs);
-                        const T qq = (T)v.q;
-                        c8 = fma(qq, cs, c8);
-                        s8 = fma(qq, sn, s8);
-                    }
-                }
+                for (int u = 0; u < kRhoUnroll; ++u) rho_term(sp[j0 + u * G], mx, my, mz, c8, s8);
                 C += (double)c8;
                 Sn += (double)s8;
             }
@@ -363,9 +415,10 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
 }
 
 // ---------------------------------------------------------------------------
-// k_mid: two independent jobs in one launch.
+// k_mid: independent jobs in one launch.
 //  * final structure factors: one wave per (system, mode) adds the tile
 //    partials in a fixed order and fills the per-mode force constants;
+//  * (gated) binning of a neighbour-list rebuild from the stored records;
 //  * cell scan: one block per system turns the cell counts into global slot
 //    starts (exclusive prefix + S.off) and clears the counts.
 // ---------------------------------------------------------------------------
@@ -385,7 +438,43 @@ struct MidArgs {
     int32_t *start;
     int do_scan;
     const int32_t *scan_gate;   // when set, the scan runs only if *scan_gate != 0
+    // binning of a list rebuild (blocks after the totals), only if *bin_gate != 0
+    const int32_t *bin_gate;
+    int n_bin_blocks;
+    const Tile *part_tiles;
+    int n_part_tiles;
+    const void *packed;
+    int32_t *cellid;
+    int32_t *rank;
 };
+
+// Cell of a stored record and its atomic rank within the cell.
+template <typename KM>
+__device__ void mid_bin(const MidArgs<KM> &a, int b)
+{
+    const int ti = 4 * b + (int)(threadIdx.x >> 8);
+    if (ti >= a.n_part_tiles) return;
+    const Tile t = a.part_tiles[ti];
+    const int k = threadIdx.x & 255;
+    if (k >= t.count) return;
+    const SysDev S = a.sys[t.sys];
+    const int64_t i = S.off + t.start + k;
+    int cx, cy, cz;
+    if constexpr (sizeof(KM) == sizeof(KModeF)) {
+        const PackF v = reinterpret_cast<const PackF *>(a.packed)[i];
+        cx = cell_of_fix(v.x, S.nc);
+        cy = cell_of_fix(v.y, S.nc);
+        cz = cell_of_fix(v.z, S.nc);
+    } else {
+        const PartD v = reinterpret_cast<const PartD *>(a.packed)[i];
+        cx = cell_of_frac(v.x, S.nc);
+        cy = cell_of_frac(v.y, S.nc);
+        cz = cell_of_frac(v.z, S.nc);
+    }
+    const int c = S.cell_off + (cz * S.nc + cy) * S.nc + cx;
+    a.cellid[i] = c;
+    a.rank[i] = atomicAdd(&a.count[c], 1);
+}
 
 template <typename KM>
 __device__ void mid_final(const MidArgs<KM> &a, int gm)
@@ -423,7 +512,6 @@ __device__ void mid_final(const MidArgs<KM> &a, int gm)
         k.a[2] = f * mz;
         k.C = c;
         k.S = s;
-        if constexpr (sizeof(KM) == sizeof(KModeF)) k.pad = 0.0f;
         a.km[o] = k;
     }
 }
@@ -503,9 +591,14 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
         mid_final<KM>(a, blockIdx.x * 16 + wave);
         return;
     }
+    const int b = blockIdx.x - a.n_final_blocks;
+    if (b < a.n_bin_blocks) {
+        if (*a.bin_gate != 0) mid_bin<KM>(a, b);
+        return;
+    }
     if (!a.do_scan) return;
     if (a.scan_gate && *a.scan_gate == 0) return;
-    const int r = blockIdx.x - a.n_final_blocks;
+    const int r = b - a.n_bin_blocks;
     mid_scan(a.sys[r], r, a.count, a.start);
 }
 
@@ -559,27 +652,25 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
         const Tile t = a.tiles[ti];
         sysi = t.sys;
         const SysDev S = a.sys[t.sys];
-        double sx = 0.0, sy = 0.0, sz = 0.0;
+        double s3[3] = {0.0, 0.0, 0.0};
         if (lane < t.count) {
             i = S.off + t.start + lane;
-            sx = frac01((double)a.pos[i] * S.invL);
-            sy = frac01((double)a.pos[a.ntot + i] * S.invL);
-            sz = frac01((double)a.pos[2 * a.ntot + i] * S.invL);
+            for (int d = 0; d < 3; ++d) s3[d] = frac01((double)a.pos[d * a.ntot + i] * S.invL);
             qi = a.q[i];
         }
         const int l0 = (S.p * part) / SPLIT, l1 = (S.p * (part + 1)) / SPLIT;
         const KM *kk = a.km + S.moff;
-#pragma unroll 4
-        for (int l = l0; l < l1; ++l) {
-            const KM k = kk[l];
-            const double ph = wrap_rev(fma(k.m[0], sx, fma(k.m[1], sy, k.m[2] * sz)));
-            T sn, cs;
-            sincos_rev(ph, &sn, &cs);
-            const T im = cs * (T)k.S - sn * (T)k.C;
-            fx = fma(im, (T)k.a[0], fx);
-            fy = fma(im, (T)k.a[1], fy);
-            fz = fma(im, (T)k.a[2], fz);
+        T f[3] = {0, 0, 0};
+        if constexpr (sizeof(T) == 4) {
+            float h[3], lo[3];
+            for (int d = 0; d < 3; ++d) split_frac(s3[d], S, h[d], lo[d]);
+            fourier_range(kk, l0, l1, h, lo, f);
+        } else {
+            fourier_range(kk, l0, l1, s3, f);
         }
+        fx = f[0];
+        fy = f[1];
+        fz = f[2];
     }
     if constexpr (SPLIT > 1) {
         red[wave][0][lane] = fx;
@@ -849,7 +940,8 @@ hipError_t launch_sample(const LaunchCfg &c, const Workspace &w, uint64_t step, 
 
 size_t stage_lds_bytes(const LaunchCfg &c, int sample_in_kernel, int *table_lds, int *tab_max)
 {
-    size_t base = sizeof(PartD) * c.rho_chunk + sizeof(double2) * c.rho_block + sizeof(int) * 3 * c.rho_block;
+    size_t base = sizeof(PartD) * (c.rho_chunk + kRhoUnroll * kRhoGroupsMax) + sizeof(double2) * c.rho_block +
+                  sizeof(int) * 3 * c.rho_block;
     *table_lds = 0;
     *tab_max = 0;
     if (sample_in_kernel && base + sizeof(double) * c.max_table <= 64 * 1024) {
@@ -918,7 +1010,7 @@ hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageReque
 
 template <typename KM>
 static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
-                               const int32_t *gate)
+                               const int32_t *gate, const int32_t *bin_gate)
 {
     MidArgs<KM> a;
     a.sys = w.sys;
@@ -936,16 +1028,24 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.start = w.cell_start;
     a.do_scan = do_scan;
     a.scan_gate = gate;
-    const int nb = a.n_final_blocks + (do_scan ? c.R : 0);
+    a.bin_gate = bin_gate;
+    a.n_bin_blocks = bin_gate ? (c.n_part_tiles + 3) / 4 : 0;
+    a.part_tiles = w.part_tiles;
+    a.n_part_tiles = c.n_part_tiles;
+    a.packed = w.packed;
+    a.cellid = w.cellid;
+    a.rank = w.rank;
+    const int nb = a.n_final_blocks + a.n_bin_blocks + (do_scan ? c.R : 0);
     if (nb == 0) return hipSuccess;
     k_mid<KM><<<nb, 1024, 0, c.stream>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan, const int32_t *gate)
+hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan, const int32_t *gate,
+                      const int32_t *bin_gate)
 {
-    return c.prec == RBE_FP64 ? mid_dispatch<KModeD>(c, w, do_final, do_scan, gate)
-                              : mid_dispatch<KModeF>(c, w, do_final, do_scan, gate);
+    return c.prec == RBE_FP64 ? mid_dispatch<KModeD>(c, w, do_final, do_scan, gate, bin_gate)
+                              : mid_dispatch<KModeF>(c, w, do_final, do_scan, gate, bin_gate);
 }
 
 template <typename T, typename KM>

@@ -269,7 +269,10 @@ __device__ __forceinline__ void row_scan(const Rec &pa, int self, int cx, int yy
         rs.nseg = 2;
     }
     rs.walk = false;
-    for (int s = 0; s < rs.nseg; ++s) {
+    rs.m[0] = rs.m[1] = 0;
+    if (rs.nseg == 1) rs.b0[1] = rs.b1[1] = 0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
         const int b0 = rs.b0[s], b1 = rs.b1[s];
         uint64_t m = 0;
         if (b1 - b0 <= 64) {
@@ -294,7 +297,8 @@ template <typename Rec, typename F>
 __device__ __forceinline__ void row_visit(const Rec &pa, int self, const RowScan &rs, const Rec *gs, const Geo &geo,
                                           F &&f)
 {
-    for (int s = 0; s < rs.nseg; ++s) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
         const int b0 = rs.b0[s], b1 = rs.b1[s];
         if (b1 - b0 <= 64) {
             uint64_t m = rs.m[s];
@@ -328,6 +332,7 @@ struct RealArgs {
     T *vel;                  // kick target (may be NULL); velocities for kinetic energy when ENERGY
     int32_t *flag;
     double *epart;           // ENERGY: [tiles][8]
+    const void *km;          // per-mode force constants (KModeF / KModeD) for the fused Fourier force
 };
 
 // Neighbour-list state seen by the real-space pass of a step.
@@ -335,7 +340,7 @@ struct ListArgs {
     ListStep ls;
     const Tile *list_tiles;
     int n_rows, n_list;      // tiles of the cell pass and of the list pass
-    int32_t *nbr;
+    int32_t *nbr;            // [kmax][Ntot] partner slots, column k of slot s at k * Ntot + s
     int32_t *nnb;
     int kmax;
 };
@@ -397,10 +402,80 @@ __device__ __forceinline__ SysDev pair_consts<double>(const SysDev &S)
     return S;
 }
 
+// ---------------------------------------------------------------------------
+// Fourier force fused into the real-space pass of a step (eq. 3.6).  Wave w of
+// the block sums the modes of quarter w, [w P/4, (w+1) P/4), in mode order for
+// every particle of the tile (64 per pass, one per lane; the mode constants are
+// wave-uniform), and leaves the partial sum in LDS; the particle's lane adds
+// the quarters in a fixed order when it finishes the particle.  The decomposition
+// is the same on every tile shape, so the Fourier force of a particle does not
+// depend on the real-space path.
+// ---------------------------------------------------------------------------
+constexpr int FT_MAX = 256;   // particles per tile, any shape
+
+template <typename T>
+struct KMT;
+template <>
+struct KMT<float> {
+    using type = KModeF;
+};
+template <>
+struct KMT<double> {
+    using type = KModeD;
+};
+
+template <typename T>
+using Four = T (*)[FT_MAX][3];
+
+template <typename T>
+__device__ __forceinline__ void fourier_tile(const RealArgs<T> &a, const SysDev &S, const void *recs, int first,
+                                             int count, Four<T> s4)
+{
+    using Rec = typename RBT<T>::Rec;
+    using KM = typename KMT<T>::type;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int l0 = (S.p * wave) / 4, l1 = (S.p * (wave + 1)) / 4;
+    const KM *kk = reinterpret_cast<const KM *>(a.km) + S.moff;
+    const Rec *rp = reinterpret_cast<const Rec *>(recs) + first;
+    for (int p0 = 0; p0 < count; p0 += 64) {
+        const int p = p0 + lane;
+        T f[3] = {0, 0, 0};
+        if (p < count) {
+            const Rec r = rp[p];
+            if constexpr (sizeof(T) == 4) {
+                float h[3], lo[3];
+                split_fix(r.x, S, h[0], lo[0]);
+                split_fix(r.y, S, h[1], lo[1]);
+                split_fix(r.z, S, h[2], lo[2]);
+                fourier_range(kk, l0, l1, h, lo, f);
+            } else {
+                const double s3[3] = {r.x, r.y, r.z};
+                fourier_range(kk, l0, l1, s3, f);
+            }
+            s4[wave][p][0] = f[0];
+            s4[wave][p][1] = f[1];
+            s4[wave][p][2] = f[2];
+        }
+    }
+}
+
+// Adds the Fourier force of tile particle k (charge qi) to (fx, fy, fz).
+template <typename T>
+__device__ __forceinline__ void add_fourier(Four<T> s4, int k, T qi, double &fx, double &fy, double &fz)
+{
+    if (!s4) return;
+    T g[3];
+    for (int d = 0; d < 3; ++d) g[d] = ((s4[0][k][d] + s4[1][k][d]) + s4[2][k][d]) + s4[3][k][d];
+    fx += (double)(-qi * g[0]);
+    fy += (double)(-qi * g[1]);
+    fz += (double)(-qi * g[2]);
+}
+
 // All-pairs tile: particles [start, start + count) of a one-cell system, one
 // per thread, partners in original index order.
 template <typename T, bool ENERGY>
-__device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &t, const SysDev &S, double *ev)
+__device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &t, const SysDev &S, double *ev,
+                                              Four<T> s4 = nullptr)
 {
     using Rec = typename RBT<T>::Rec;
     const Geo geo = make_geo<T>(S);
@@ -427,6 +502,7 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
         ev[0] += e.e_real;
         ev[1] += e.e_lj;
     }
+    add_fourier<T>(s4, (int)threadIdx.x, (T)pa.q, fx, fy, fz);
     finish_particle<T, ENERGY>(a, S, S.off + il, fx, fy, fz, ev);
 }
 
@@ -435,7 +511,7 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
 // row counts are prefixed in LDS so that the list keeps row order.
 template <typename T, bool ENERGY, bool BUILD>
 __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *la, const Tile &t, const SysDev &S,
-                                          double *ev)
+                                          double *ev, Four<T> s4 = nullptr)
 {
     using Rec = typename RBT<T>::Rec;
     __shared__ double s_red[ENERGY ? 6 : 3][RL_BS];
@@ -455,6 +531,8 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
     RowScan rs;
     rs.nseg = 0;
     rs.walk = false;
+    rs.b0[0] = rs.b0[1] = rs.b1[0] = rs.b1[1] = 0;
+    rs.m[0] = rs.m[1] = 0;
     if (act) {
         slot = S.off + t.start + k;
         pa = gs[slot];
@@ -467,8 +545,7 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
     }
     int pos = 0, total = 0;
     if constexpr (BUILD) {
-        int cnt = 0;
-        for (int s = 0; s < rs.nseg; ++s) cnt += __builtin_popcountll(rs.m[s]);
+        const int cnt = __builtin_popcountll(rs.m[0]) + __builtin_popcountll(rs.m[1]);
         s_cnt[tid] = cnt + (rs.walk ? (1 << 20) : 0);   // a walked row cannot be listed
         __syncthreads();
         if (act) {
@@ -520,9 +597,11 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
             }
         if constexpr (BUILD) {
             // an overflowing list is never read (the next step rebuilds)
-            la->nnb[slot] = total <= la->kmax ? total : 0;
-            if (total > la->kmax) atomicOr(la->ls.overflow, 1);
+            const bool ok = total <= la->kmax;
+            la->nnb[slot] = ok ? total : 0;
+            if (!ok) atomicOr(la->ls.overflow, 1);
         }
+        add_fourier<T>(s4, k, (T)pa.q, sx, sy, sz);
         finish_particle<T, ENERGY>(a, S, a.sorted_idx[slot], sx, sy, sz, ev);
     }
 }
@@ -561,7 +640,8 @@ __global__ __launch_bounds__(RL_BS) void k_real_rows(RealArgs<T> a)
 
 // List tile: LPP lanes per cell-sorted slot.
 template <typename T, int LPP>
-__device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &la, const Tile &t, const SysDev &S)
+__device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &la, const Tile &t, const SysDev &S,
+                                          Four<T> s4 = nullptr)
 {
     using Rec = typename RBT<T>::Rec;
     const Geo geo = make_geo<T>(S);
@@ -571,22 +651,39 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
     const bool act = k < t.count;
     double fx = 0, fy = 0, fz = 0;
     int slot = 0;
+    T qi = 0;
     if (act) {
         slot = S.off + t.start + k;
         const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
         const Rec pa = gs[slot];
+        qi = (T)pa.q;
         const int n = la.nnb[slot];
         const int32_t *nb = la.nbr + slot;
         PairE e{0, 0};
-        for (int j = sub; j < n; j += LPP) {
-            const int b = nb[(int64_t)j * a.ntot];
-            const Rec pb = gs[b];
-            T dx, dy, dz, r2;
-            displacement(pa, pb, geo, dx, dy, dz, r2);
-            const T phi = pair_phi<false>(pc, (T)pa.q, (T)pb.q, r2, e);
-            fx += (double)(phi * dx);
-            fy += (double)(phi * dy);
-            fz += (double)(phi * dz);
+        // four partners per round: their indices, then their records, are
+        // loaded together so that the gathers overlap
+        constexpr int U = 4;
+        for (int j = sub; j < n; j += U * LPP) {
+            int b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jj = j + u * LPP;
+                b[u] = jj < n ? nb[(int64_t)jj * a.ntot] : slot;
+            }
+            Rec pb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) pb[u] = gs[b[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (j + u * LPP < n) {
+                    T dx, dy, dz, r2;
+                    displacement(pa, pb[u], geo, dx, dy, dz, r2);
+                    const T phi = pair_phi<false>(pc, (T)pa.q, (T)pb[u].q, r2, e);
+                    fx += (double)(phi * dx);
+                    fy += (double)(phi * dy);
+                    fz += (double)(phi * dz);
+                }
+            }
         }
     }
 #pragma unroll
@@ -595,34 +692,35 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
         fy += __shfl_xor(fy, o, 64);
         fz += __shfl_xor(fz, o, 64);
     }
-    if (act && sub == 0) finish_particle<T, false>(a, S, a.sorted_idx[slot], fx, fy, fz, nullptr);
+    if (act && sub == 0) {
+        add_fourier<T>(s4, k, qi, fx, fy, fz);
+        finish_particle<T, false>(a, S, a.sorted_idx[slot], fx, fy, fz, nullptr);
+    }
 }
 
-// Real-space pass of one time step: the cell pass with list build when the
-// step's rebuild flag is set, else the list pass.  Block 0 clears the next
-// step's flag (nothing else touches it during this launch).
+// Force pass of one time step: the Fourier force plus the real-space force,
+// on the cell list with list build when the step's rebuild flag is set, else
+// on the list; then the final half kick.  Block 0 clears the next step's flag
+// (nothing else touches it during this launch).
 template <typename T, int LPP>
 __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
 {
+    __shared__ T s4[4][FT_MAX][3];
     const int rebuild = *la.ls.rebuild;
     if (blockIdx.x == 0 && threadIdx.x == 0) *la.ls.rebuild_next = 0;
-    if (rebuild) {
-        if ((int)blockIdx.x >= la.n_rows) return;
-        const Tile t = a.tiles[blockIdx.x];
-        const SysDev S = a.sys[t.sys];
-        if (t.aux == 1)
-            allpairs_body<T, false>(a, t, S, nullptr);
-        else
-            rows_body<T, false, true>(a, &la, t, S, nullptr);
-    } else {
-        if ((int)blockIdx.x >= la.n_list) return;
-        const Tile t = la.list_tiles[blockIdx.x];
-        const SysDev S = a.sys[t.sys];
-        if (t.aux == 1)
-            allpairs_body<T, false>(a, t, S, nullptr);
-        else
-            list_body<T, LPP>(a, la, t, S);
-    }
+    const int nb = rebuild ? la.n_rows : la.n_list;
+    if ((int)blockIdx.x >= nb) return;
+    const Tile t = rebuild ? a.tiles[blockIdx.x] : la.list_tiles[blockIdx.x];
+    const SysDev S = a.sys[t.sys];
+    const bool allpairs = t.aux == 1;
+    fourier_tile<T>(a, S, allpairs ? a.packed : a.sorted, S.off + t.start, t.count, s4);
+    __syncthreads();
+    if (allpairs)
+        allpairs_body<T, false>(a, t, S, nullptr, s4);
+    else if (rebuild)
+        rows_body<T, false, true>(a, &la, t, S, nullptr, s4);
+    else
+        list_body<T, LPP>(a, la, t, S, s4);
 }
 
 // Stand-alone scatter into cell order (the force kernel does this inline
@@ -842,6 +940,7 @@ static RealArgs<T> real_args(const LaunchCfg &c, const Workspace &w, void *force
     a.vel = (T *)vel;
     a.flag = w.flag;
     a.epart = w.energy_part;
+    a.km = w.kmode;
     return a;
 }
 
@@ -893,9 +992,9 @@ hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListSt
     la.nnb = w.nnb;
     la.kmax = c.kmax;
     if (c.prec == RBE_FP64)
-        real_step_dispatch<double>(c, real_args<double>(c, w, force, 1, vel_kick, nullptr), la);
+        real_step_dispatch<double>(c, real_args<double>(c, w, force, 0, vel_kick, nullptr), la);
     else
-        real_step_dispatch<float>(c, real_args<float>(c, w, force, 1, vel_kick, nullptr), la);
+        real_step_dispatch<float>(c, real_args<float>(c, w, force, 0, vel_kick, nullptr), la);
     return hipGetLastError();
 }
 
