@@ -7,10 +7,10 @@ arithmetic with double phases.  Inputs are synthetic and resident on the GPU
 before timing starts.
 
 A timed "step" is one pass of the whole hot path: a fresh batch of P modes,
-structure factors, the Fourier force, the cell list, the real-space + LJ
-force and the Langevin update (rbe_step with nsteps = 1 per step, all launched
-back to back on one stream).  The headline value is N*P*steps / elapsed
-seconds over those full steps.  The JSON line also reports MD steps/s, the
+structure factors, the Fourier force, the neighbour list (rebuilt on the
+device when particles have moved far enough), the real-space + LJ force and
+the Langevin update; the K timed steps are one rbe_step call.  The headline
+value is N*P*steps / elapsed seconds over those full steps.  The JSON line also reports MD steps/s, the
 Fourier-only pair rate (sample + structure factor + force), per-kernel
 durations from HIP events on the library's stream, the ALU roofline of every
 kernel of the step (the longest one as "roofline"), and the FP64 CPU oracle
@@ -159,17 +159,15 @@ def main():
     R.rbe_kspace_forces(ctx, P, Q, F)
     R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
 
-    # ---- full MD steps ----
-    for k in range(args.warmup):
-        R.rbe_step(ctx, P, V, Q, F, 1 + k, 1)
+    # ---- full MD steps (one rbe_step call advances all K steps) ----
+    R.rbe_step(ctx, P, V, Q, F, 1, args.warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     base = 1 + args.warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for k in range(args.steps):
-        R.rbe_step(ctx, P, V, Q, F, base + k, 1)
+    R.rbe_step(ctx, P, V, Q, F, base, args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -192,8 +190,7 @@ def main():
 
     # ---- per-kernel durations with HIP events on the library stream ----
     R.rbe_profile_enable(ctx, True)
-    for k in range(args.steps):
-        R.rbe_step(ctx, P, V, Q, F, base + args.steps + k, 1)
+    R.rbe_step(ctx, P, V, Q, F, base + args.steps, args.steps)
     prof = R.rbe_profile_read(ctx)
     R.rbe_profile_enable(ctx, False)
     kern = {name: {"avg_us": 1e3 * ms / n, "launches": n} for name, (ms, n) in prof.items() if n}

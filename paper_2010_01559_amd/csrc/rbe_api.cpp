@@ -577,6 +577,8 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     ALLOC(w.sorted_idx, sizeof(int32_t) * ntot);
     ALLOC(w.packed, pack_sz * ntot);
     ALLOC(w.sorted, pack_sz * ntot);
+    ALLOC(w.modes_alt, sizeof(int32_t) * 3 * c->mcap);
+    ALLOC(w.mode_w_alt, sizeof(double) * c->mcap);
     ALLOC(w.energy_part, sizeof(double) * 8 * rtiles.size());
     ALLOC(w.flag, sizeof(int32_t) * 4);
     ALLOC(w.lflag, sizeof(int32_t) * 4);
@@ -672,6 +674,8 @@ rbe_status rbe_reserve_modes(rbe_ctx *c, int32_t cap)
     rbe_status s;
     if ((s = swap_alloc((void **)&c->w.modes, sizeof(int32_t) * 3 * cap)) != RBE_OK ||
         (s = swap_alloc((void **)&c->w.mode_w, sizeof(double) * cap)) != RBE_OK ||
+        (s = swap_alloc((void **)&c->w.modes_alt, sizeof(int32_t) * 3 * cap)) != RBE_OK ||
+        (s = swap_alloc((void **)&c->w.mode_w_alt, sizeof(double) * cap)) != RBE_OK ||
         (s = swap_alloc((void **)&c->w.rho, sizeof(double) * 2 * cap)) != RBE_OK ||
         (s = swap_alloc((void **)&c->w.ab, sizeof(double) * 2 * cap)) != RBE_OK ||
         (s = swap_alloc(&c->w.kmode, km_sz * cap)) != RBE_OK || (s = swap_alloc(&c->w.kvjp, kv_sz * cap)) != RBE_OK) {
@@ -818,20 +822,32 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
     for (int32_t t = 0; t < nsteps; ++t) {
         const uint64_t s = first_step + (uint64_t)t;
         const uint64_t ks = andersen ? s + 1 : s;
-        if (!fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
         if (list) {
+            // the staging launch integrates (in particle order); the modes of
+            // every step after the first of a call were drawn by the totals
+            // launch of the step before (exact sampler)
+            const bool first = t == 0, last = t == nsteps - 1;
             const int par = (int)(c->list_gen & 1);
             ListStep ls{c->w.lflag + par, c->w.lflag + (1 - par), c->w.lflag + 2, c->w.lflag + 3,
                         c->list_valid ? 0 : 1};
-            StageRequest rq{pos, vel, force, q, s, ks, 1, 0, fuse_sample ? 1 : 0, 1, &ls};
+            const bool drawn = !first && !c->any_mh;
+            if (!drawn && !fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
+            StageRequest rq{pos, vel, force, q, s, ks, 1, 0, (!drawn && fuse_sample) ? 1 : 0, 1, &ls};
             RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
-            RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild));
+            const bool draw_next = !c->any_mh && !last;
+            RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild, ls.rebuild_next, draw_next ? 1 : 0,
+                                     ks + 1));
             RUN(c, K_SCAN, launch_mid(c->cfg, c->w, 0, 1, ls.rebuild));
             RUN(c, K_SCATTER, launch_scatter(c->cfg, c->w, &ls));
             RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, andersen ? nullptr : vel));
             c->list_valid = true;
             ++c->list_gen;
+            if (draw_next) {
+                std::swap(c->w.modes, c->w.modes_alt);
+                std::swap(c->w.mode_w, c->w.mode_w_alt);
+            }
         } else {
+            if (!fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
             StageRequest rq{pos, vel, force, q, s, ks, 1, 1, fuse_sample ? 1 : 0, 1};
             RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
             RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 1));

@@ -54,18 +54,42 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b)
 // Three standard normals for particle i at step: Box-Muller on
 // u1 = (w0 + 1) 2^-32, u2 = w1 2^-32 (two normals) and on (w2 + 1) 2^-32,
 // w3 2^-32 (cosine branch), in double.
-__device__ __forceinline__ void normals3(uint32_t i, uint64_t seed, uint64_t step, double xi[3])
+// Component d of those normals.
+__device__ __forceinline__ double normal_comp(uint32_t i, uint64_t seed, uint64_t step, int d)
 {
     const U4 r = draw(i, kTagLangevin, seed, step);
     const double k = 1.0 / 4294967296.0;
-    const double u1 = ((double)r.x + 1.0) * k, u2 = (double)r.y * k;
+    if (d < 2) {
+        const double u1 = ((double)r.x + 1.0) * k, u2 = (double)r.y * k;
+        const double a = sqrt(-2.0 * log(u1));
+        double s, c;
+        sincospi(2.0 * u2, &s, &c);
+        return d == 0 ? a * c : a * s;
+    }
     const double u3 = ((double)r.z + 1.0) * k, u4 = (double)r.w * k;
-    const double a = sqrt(-2.0 * log(u1)), b = sqrt(-2.0 * log(u3));
-    double s, c;
-    sincospi(2.0 * u2, &s, &c);
-    xi[0] = a * c;
-    xi[1] = a * s;
-    xi[2] = b * cospi(2.0 * u4);
+    const double b = sqrt(-2.0 * log(u3));
+    return b * cospi(2.0 * u4);
+}
+
+// The same normals in single precision (hardware log2, sqrt and sine/cosine
+// of revolutions), for single-precision systems: relative error ~1e-7.
+__device__ __forceinline__ float normal_comp_f32(uint32_t i, uint64_t seed, uint64_t step, int d)
+{
+    const U4 r = draw(i, kTagLangevin, seed, step);
+    const float k = 1.0f / 4294967296.0f;
+    const uint32_t wa = d < 2 ? r.x : r.z, wb = d < 2 ? r.y : r.w;
+    const float u1 = ((float)wa + 1.0f) * k, u2 = (float)wb * k;
+    const float a = __builtin_amdgcn_sqrtf(-2.0f * 0.693147180559945309f * __builtin_amdgcn_logf(u1));
+    return d == 1 ? a * __builtin_amdgcn_sinf(u2) : a * __builtin_amdgcn_cosf(u2);
+}
+
+template <typename T>
+__device__ __forceinline__ double normal_t(uint32_t i, uint64_t seed, uint64_t step, int d)
+{
+    if constexpr (sizeof(T) == 4)
+        return (double)normal_comp_f32(i, seed, step, d);
+    else
+        return normal_comp(i, seed, step, d);
 }
 
 // Smallest index k of the cumulative table t[0..K) with u < t[k]; the last
@@ -217,6 +241,98 @@ __device__ __forceinline__ void fourier_range(const KModeD *kk, int l0, int l1, 
         f[1] = fma(im, k.a[1], f[1]);
         f[2] = fma(im, k.a[2], f[2]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// One particle's position/velocity update up to the force evaluation, in
+// double from the stored values: BAOA of the BAOAB Langevin step (half kick,
+// half drift, exact Ornstein-Uhlenbeck velocity update with the normals of
+// (particle il, step), half drift), or the leapfrog + Andersen update; the
+// position is wrapped into [0, L).  x receives the new position.
+// ---------------------------------------------------------------------------
+// Component d of that update; xi is the component's normal (Langevin) or,
+// for Andersen, the normal used when the particle collides (`hit`).
+template <typename T>
+__device__ __forceinline__ double integrate_comp(const SysDev &S, int d, int64_t i, int64_t ntot, T *pos, T *vel,
+                                                 const T *F, double xi, bool hit)
+{
+    const int64_t k = d * ntot + i;
+    if (S.integrator == RBE_LANGEVIN_BAOAB) {
+        const double h = 0.5 * S.dt;
+        double v = (double)vel[k] + h * (double)F[k] / S.mass;  // B
+        double r = (double)pos[k] + h * v;                      // A
+        v = S.c1 * v + S.c2 * xi;                               // O
+        r += h * v;                                             // A
+        r -= S.L * floor(r * S.invL);
+        T rs = (T)r;
+        if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
+        pos[k] = rs;
+        vel[k] = (T)v;
+        return (double)rs;
+    }
+    const double sv = sqrt(S.kT / S.mass);
+    const double v = (double)vel[k] + S.dt * (double)F[k] / S.mass;
+    double r = (double)pos[k] + S.dt * v;
+    r -= S.L * floor(r * S.invL);
+    T rs = (T)r;
+    if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
+    pos[k] = rs;
+    vel[k] = (T)(hit ? sv * xi : v);
+    return (double)rs;
+}
+
+// Andersen collision of particle il at step.
+__device__ __forceinline__ bool andersen_hit(const SysDev &S, int il, uint64_t step)
+{
+    const U4 w = draw((uint32_t)il, kTagAndersen, S.seed, step);
+    return (double)w.x * (1.0 / 4294967296.0) < S.nu_dt;
+}
+
+template <typename T>
+__device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i, int64_t ntot, T *pos, T *vel,
+                                              const T *F, uint64_t step, double x[3])
+{
+    const bool hit = S.integrator == RBE_LANGEVIN_BAOAB ? false : andersen_hit(S, il, step);
+    const bool noise = S.integrator == RBE_LANGEVIN_BAOAB || hit;
+    for (int d = 0; d < 3; ++d) {
+        const double xi = noise ? normal_t<T>((uint32_t)il, S.seed, step, d) : 0.0;
+        x[d] = integrate_comp<T>(S, d, i, ntot, pos, vel, F, xi, hit);
+    }
+}
+
+// Stored record of a particle (original order, and cell order for list
+// systems) and the displacement test against skin/2 since the last build.
+template <typename T>
+__device__ __forceinline__ bool record_update(const SysDev &S, int64_t i, double sx, double sy, double sz, T qi,
+                                              void *packed, void *sorted, const int32_t *slot_of, const void *ref)
+{
+    bool moved = false;
+    if constexpr (sizeof(T) == 4) {
+        const PackF v{to_fix(sx), to_fix(sy), to_fix(sz), (float)qi};
+        reinterpret_cast<PackF *>(packed)[i] = v;
+        if (S.use_list) {
+            reinterpret_cast<PackF *>(sorted)[slot_of[i]] = v;
+            const PackF r = reinterpret_cast<const PackF *>(ref)[i];
+            const double u = 1.0 / 4294967296.0 * S.L;
+            const double dx = (double)(int32_t)(v.x - r.x) * u;
+            const double dy = (double)(int32_t)(v.y - r.y) * u;
+            const double dz = (double)(int32_t)(v.z - r.z) * u;
+            moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
+        }
+    } else {
+        const PartD v{sx, sy, sz, (double)qi};
+        reinterpret_cast<PartD *>(packed)[i] = v;
+        if (S.use_list) {
+            reinterpret_cast<PartD *>(sorted)[slot_of[i]] = v;
+            const PartD r = reinterpret_cast<const PartD *>(ref)[i];
+            double dx = v.x - r.x, dy = v.y - r.y, dz = v.z - r.z;
+            dx = (dx - rint(dx)) * S.L;
+            dy = (dy - rint(dy)) * S.L;
+            dz = (dz - rint(dz)) * S.L;
+            moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
+        }
+    }
+    return moved;
 }
 
 // Inclusive prefix sum across the 64 lanes of a wave.

@@ -129,6 +129,8 @@ struct Workspace {
     int32_t *sorted_idx;   // [Ntot] particle at each sorted slot
     void *packed;          // [Ntot] wrapped position + charge, original order
     void *sorted;          // [Ntot] same, sorted by cell
+    int32_t *modes_alt;    // the next step's modes and weights when the totals launch draws them
+    double *mode_w_alt;
     double *energy_part;   // [real tiles][8]
     int32_t *flag;         // [4] bit 0: non-finite force
     // neighbour list of rbe_step (allocated when some system uses it)
@@ -160,7 +162,7 @@ struct LaunchCfg {
 // Device view of the neighbour-list state for one step.
 struct ListStep {
     int32_t *rebuild;        // request flag of this step (read)
-    int32_t *rebuild_next;   // request flag of the next step (cleared here)
+    int32_t *rebuild_next;   // request flag of the next step
     int32_t *overflow;
     int32_t *rebuilds;       // count of list builds
     int force_rebuild;
@@ -183,7 +185,8 @@ hipError_t launch_sample(const LaunchCfg &c, const Workspace &w, uint64_t step, 
 hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageRequest &rq);
 size_t stage_lds_bytes(const LaunchCfg &c, int sample_in_kernel, int *table_lds, int *tab_max);
 hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
-                      const int32_t *scan_gate = nullptr, const int32_t *bin_gate = nullptr);
+                      const int32_t *scan_gate = nullptr, const int32_t *bin_gate = nullptr,
+                      int32_t *clear_flag = nullptr, int sample_next = 0, uint64_t sample_step = 0);
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
                          int accumulate, int scatter, const int32_t *bin_gate = nullptr);
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);

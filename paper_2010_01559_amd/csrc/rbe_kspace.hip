@@ -147,46 +147,6 @@ struct StageArgs {
 };
 
 template <typename T>
-__device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i, int64_t ntot, T *pos, T *vel,
-                                              const T *F, uint64_t step, double x[3])
-{
-    double xi[3];
-    if (S.integrator == RBE_LANGEVIN_BAOAB) {
-        normals3((uint32_t)il, S.seed, step, xi);
-        const double h = 0.5 * S.dt;
-        for (int d = 0; d < 3; ++d) {
-            const int64_t k = d * ntot + i;
-            double v = (double)vel[k] + h * (double)F[k] / S.mass;  // B
-            double r = (double)pos[k] + h * v;                      // A
-            v = S.c1 * v + S.c2 * xi[d];                            // O
-            r += h * v;                                             // A
-            r -= S.L * floor(r * S.invL);
-            T rs = (T)r;
-            if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
-            pos[k] = rs;
-            vel[k] = (T)v;
-            x[d] = (double)rs;
-        }
-    } else {
-        const U4 w = draw((uint32_t)il, kTagAndersen, S.seed, step);
-        const bool hit = (double)w.x * (1.0 / 4294967296.0) < S.nu_dt;
-        if (hit) normals3((uint32_t)il, S.seed, step, xi);
-        const double sv = sqrt(S.kT / S.mass);
-        for (int d = 0; d < 3; ++d) {
-            const int64_t k = d * ntot + i;
-            const double v = (double)vel[k] + S.dt * (double)F[k] / S.mass;
-            double r = (double)pos[k] + S.dt * v;
-            r -= S.L * floor(r * S.invL);
-            T rs = (T)r;
-            if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
-            pos[k] = rs;
-            vel[k] = (T)(hit ? sv * xi[d] : v);
-            x[d] = (double)rs;
-        }
-    }
-}
-
-template <typename T>
 __device__ __forceinline__ void bin_one(const SysDev &S, int64_t i, double sx, double sy, double sz, T qi,
                                         int32_t *count, int32_t *cellid, int32_t *rank, void *packed)
 {
@@ -214,33 +174,7 @@ template <typename T>
 __device__ __forceinline__ bool list_update(const SysDev &S, int64_t i, double sx, double sy, double sz, T qi,
                                             const StageArgs<T> &a)
 {
-    bool moved = false;
-    if constexpr (sizeof(T) == 4) {
-        const PackF v{to_fix(sx), to_fix(sy), to_fix(sz), (float)qi};
-        reinterpret_cast<PackF *>(a.packed)[i] = v;
-        if (S.use_list) {
-            reinterpret_cast<PackF *>(a.sorted)[a.slot_of[i]] = v;
-            const PackF r = reinterpret_cast<const PackF *>(a.ref)[i];
-            const double u = 1.0 / 4294967296.0 * S.L;
-            const double dx = (double)(int32_t)(v.x - r.x) * u;
-            const double dy = (double)(int32_t)(v.y - r.y) * u;
-            const double dz = (double)(int32_t)(v.z - r.z) * u;
-            moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
-        }
-    } else {
-        const PartD v{sx, sy, sz, (double)qi};
-        reinterpret_cast<PartD *>(a.packed)[i] = v;
-        if (S.use_list) {
-            reinterpret_cast<PartD *>(a.sorted)[a.slot_of[i]] = v;
-            const PartD r = reinterpret_cast<const PartD *>(a.ref)[i];
-            double dx = v.x - r.x, dy = v.y - r.y, dz = v.z - r.z;
-            dx = (dx - rint(dx)) * S.L;
-            dy = (dy - rint(dy)) * S.L;
-            dz = (dz - rint(dz)) * S.L;
-            moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
-        }
-    }
-    return moved;
+    return record_update<T>(S, i, sx, sy, sz, qi, a.packed, a.sorted, a.slot_of, a.ref);
 }
 
 // LDS record of the structure-factor pass: fractional coordinates in double
@@ -331,7 +265,21 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         const double sx = frac01(x[0] * S.invL), sy = frac01(x[1] * S.invL), sz = frac01(x[2] * S.invL);
         const T qi = a.q[i];
         RR v;
-        rho_record(S, sx, sy, sz, qi, v);
+        if constexpr (sizeof(T) == 4) {
+            if (a.list_mode) {
+                // the force pass reads the stored 32-bit records: take the
+                // phases of the structure factor from the same fractions
+                split_fix(to_fix(sx), S, v.hx, v.lx);
+                split_fix(to_fix(sy), S, v.hy, v.ly);
+                split_fix(to_fix(sz), S, v.hz, v.lz);
+                v.q = qi;
+                v.pad = 0.0f;
+            } else {
+                rho_record(S, sx, sy, sz, qi, v);
+            }
+        } else {
+            rho_record(S, sx, sy, sz, qi, v);
+        }
         sp[j] = v;
         if (a.do_bin) bin_one<T>(S, i, sx, sy, sz, qi, a.count, a.cellid, a.rank, a.packed);
         if (a.list_mode) moved |= list_update<T>(S, i, sx, sy, sz, qi, a);
@@ -446,6 +394,14 @@ struct MidArgs {
     const void *packed;
     int32_t *cellid;
     int32_t *rank;
+    // the next step's modes (one block per system), and a flag to clear
+    int n_sample_blocks;
+    uint64_t sample_step;
+    const double *cdf;
+    int table_lds;
+    int32_t *modes_next;
+    double *mode_w_next;
+    int32_t *clear_flag;
 };
 
 // Cell of a stored record and its atomic rank within the cell.
@@ -586,6 +542,8 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
 template <typename KM>
 __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
 {
+    extern __shared__ double mid_tab[];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.clear_flag) *a.clear_flag = 0;
     if ((int)blockIdx.x < a.n_final_blocks) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         mid_final<KM>(a, blockIdx.x * 16 + wave);
@@ -596,9 +554,30 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
         if (*a.bin_gate != 0) mid_bin<KM>(a, b);
         return;
     }
+    const int b2 = b - a.n_bin_blocks;
+    if (b2 < a.n_sample_blocks) {
+        // draw the next step's modes of system b2 (exact sampler)
+        const SysDev S = a.sys[b2];
+        const double *t = a.cdf + S.cdf_off;
+        if (a.table_lds) {
+            for (int k = threadIdx.x; k < 2 * S.M + 1; k += blockDim.x) mid_tab[k] = t[k];
+            __syncthreads();
+            t = mid_tab;
+        }
+        for (int l = threadIdx.x; l < S.p; l += blockDim.x) {
+            int mx, my, mz;
+            sample_mode(t, S.M, (uint32_t)l, S.seed, a.sample_step, mx, my, mz);
+            const int o = S.moff + l;
+            a.modes_next[o] = mx;
+            a.modes_next[a.mcap + o] = my;
+            a.modes_next[2 * a.mcap + o] = mz;
+            a.mode_w_next[o] = S.S / (double)S.p;
+        }
+        return;
+    }
     if (!a.do_scan) return;
     if (a.scan_gate && *a.scan_gate == 0) return;
-    const int r = b - a.n_bin_blocks;
+    const int r = b2 - a.n_sample_blocks;
     mid_scan(a.sys[r], r, a.count, a.start);
 }
 
@@ -1010,7 +989,8 @@ hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageReque
 
 template <typename KM>
 static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
-                               const int32_t *gate, const int32_t *bin_gate)
+                               const int32_t *gate, const int32_t *bin_gate, int32_t *clear_flag, int sample_next,
+                               uint64_t sample_step)
 {
     MidArgs<KM> a;
     a.sys = w.sys;
@@ -1035,17 +1015,26 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.packed = w.packed;
     a.cellid = w.cellid;
     a.rank = w.rank;
-    const int nb = a.n_final_blocks + a.n_bin_blocks + (do_scan ? c.R : 0);
+    a.n_sample_blocks = sample_next ? c.R : 0;
+    a.sample_step = sample_step;
+    a.cdf = w.cdf;
+    a.table_lds = sample_next && c.max_table <= 6144 ? 1 : 0;
+    a.modes_next = w.modes_alt;
+    a.mode_w_next = w.mode_w_alt;
+    a.clear_flag = clear_flag;
+    const size_t sm = a.table_lds ? sizeof(double) * c.max_table : 0;
+    const int nb = a.n_final_blocks + a.n_bin_blocks + a.n_sample_blocks + (do_scan ? c.R : 0);
     if (nb == 0) return hipSuccess;
-    k_mid<KM><<<nb, 1024, 0, c.stream>>>(a);
+    k_mid<KM><<<nb, 1024, sm, c.stream>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan, const int32_t *gate,
-                      const int32_t *bin_gate)
+                      const int32_t *bin_gate, int32_t *clear_flag, int sample_next, uint64_t sample_step)
 {
-    return c.prec == RBE_FP64 ? mid_dispatch<KModeD>(c, w, do_final, do_scan, gate, bin_gate)
-                              : mid_dispatch<KModeF>(c, w, do_final, do_scan, gate, bin_gate);
+    return c.prec == RBE_FP64
+               ? mid_dispatch<KModeD>(c, w, do_final, do_scan, gate, bin_gate, clear_flag, sample_next, sample_step)
+               : mid_dispatch<KModeF>(c, w, do_final, do_scan, gate, bin_gate, clear_flag, sample_next, sample_step);
 }
 
 template <typename T, typename KM>

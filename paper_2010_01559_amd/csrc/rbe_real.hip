@@ -23,10 +23,10 @@
 // first marks the partners within the largest cutoff in a 64-bit mask (a
 // cheap distance test, no branches) and then evaluates the pair terms over
 // the set bits, so the expensive terms do not diverge on the cutoff test.
-// Each lane accumulates its FP32 pair terms in double; the nine row sums are
-// added in a fixed order, so the result does not depend on the order of the
-// particles inside a cell (which comes from atomic counters) beyond double
-// rounding.  Systems with fewer than three cells per side use all-pairs tiles.
+// Each lane accumulates its FP32 pair terms exactly (on a fixed grid, see
+// qterm); the nine row sums are added in a fixed order, so the result does not
+// depend on the order of the particles inside a cell (which comes from atomic
+// counters) nor on the path (cell or list pass).  Systems with fewer than three cells per side use all-pairs tiles.
 //
 // List pass: LPP lanes per particle walk its list in strides of LPP; the
 // LPP partial sums are combined by a fixed butterfly.
@@ -61,6 +61,21 @@ struct RBT<double> {
 struct PairE {
     double e_real, e_lj;
 };
+
+// Single-precision pair terms are added on a fixed grid of 2^-40 (as integers
+// held in double): every partial sum is exact, so a particle's real-space
+// force does not depend on the order in which its partners are visited (cell
+// ranks come from atomic counters; list and cell passes order partners
+// differently).  This holds while partial sums stay below 2^13 in magnitude,
+// far above the pair forces of these systems; the grid is far below
+// single-precision rounding.
+__device__ __forceinline__ double qterm(float v) { return rint((double)v * 0x1p40); }
+__device__ __forceinline__ double qterm(double v) { return v; }
+template <typename T>
+__device__ __forceinline__ double qscale()
+{
+    return sizeof(T) == 4 ? 0x1p-40 : 1.0;
+}
 
 // Single-precision constants of one system's pair terms, held in registers.
 struct PairConstF {
@@ -493,15 +508,18 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
         T dx, dy, dz, r2;
         displacement(pa, pb, geo, dx, dy, dz, r2);
         const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
-        fx += (double)(phi * dx);
-        fy += (double)(phi * dy);
-        fz += (double)(phi * dz);
+        fx += qterm(phi * dx);
+        fy += qterm(phi * dy);
+        fz += qterm(phi * dz);
         if constexpr (ENERGY) ev[2] += 0.5 * (double)(phi * r2);
     }
     if constexpr (ENERGY) {
         ev[0] += e.e_real;
         ev[1] += e.e_lj;
     }
+    fx *= qscale<T>();
+    fy *= qscale<T>();
+    fz *= qscale<T>();
     add_fourier<T>(s4, (int)threadIdx.x, (T)pa.q, fx, fy, fz);
     finish_particle<T, ENERGY>(a, S, S.off + il, fx, fy, fz, ev);
 }
@@ -562,9 +580,9 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
             T dx, dy, dz, r2;
             displacement(pa, pb, geo, dx, dy, dz, r2);
             const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
-            fx += (double)(phi * dx);
-            fy += (double)(phi * dy);
-            fz += (double)(phi * dz);
+            fx += qterm(phi * dx);
+            fy += qterm(phi * dy);
+            fz += qterm(phi * dz);
             if constexpr (ENERGY) vir += 0.5 * (double)(phi * r2);
             if constexpr (BUILD) {
                 if (pos < la->kmax) la->nbr[(int64_t)pos * a.ntot + slot] = b;
@@ -601,6 +619,9 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
             la->nnb[slot] = ok ? total : 0;
             if (!ok) atomicOr(la->ls.overflow, 1);
         }
+        sx *= qscale<T>();
+        sy *= qscale<T>();
+        sz *= qscale<T>();
         add_fourier<T>(s4, k, (T)pa.q, sx, sy, sz);
         finish_particle<T, ENERGY>(a, S, a.sorted_idx[slot], sx, sy, sz, ev);
     }
@@ -679,9 +700,9 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
                     T dx, dy, dz, r2;
                     displacement(pa, pb[u], geo, dx, dy, dz, r2);
                     const T phi = pair_phi<false>(pc, (T)pa.q, (T)pb[u].q, r2, e);
-                    fx += (double)(phi * dx);
-                    fy += (double)(phi * dy);
-                    fz += (double)(phi * dz);
+                    fx += qterm(phi * dx);
+                    fy += qterm(phi * dy);
+                    fz += qterm(phi * dz);
                 }
             }
         }
@@ -693,6 +714,9 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
         fz += __shfl_xor(fz, o, 64);
     }
     if (act && sub == 0) {
+        fx *= qscale<T>();
+        fy *= qscale<T>();
+        fz *= qscale<T>();
         add_fourier<T>(s4, k, qi, fx, fy, fz);
         finish_particle<T, false>(a, S, a.sorted_idx[slot], fx, fy, fz, nullptr);
     }
@@ -700,14 +724,12 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
 
 // Force pass of one time step: the Fourier force plus the real-space force,
 // on the cell list with list build when the step's rebuild flag is set, else
-// on the list; then the final half kick.  Block 0 clears the next step's flag
-// (nothing else touches it during this launch).
+// on the list; then the final half kick.
 template <typename T, int LPP>
 __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
 {
     __shared__ T s4[4][FT_MAX][3];
     const int rebuild = *la.ls.rebuild;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *la.ls.rebuild_next = 0;
     const int nb = rebuild ? la.n_rows : la.n_list;
     if ((int)blockIdx.x >= nb) return;
     const Tile t = rebuild ? a.tiles[blockIdx.x] : la.list_tiles[blockIdx.x];

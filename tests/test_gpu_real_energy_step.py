@@ -159,20 +159,26 @@ def test_leapfrog_andersen_parity(skin):
     assert rel_l2(host(V), vo) <= 1e-10
 
 
-def test_step_restart_is_bitwise():
-    """2n steps equal n steps + copy of the state + n steps (counter-based RNG)."""
+@pytest.mark.parametrize("skin", [None, 0.0])
+def test_step_restart_is_bitwise(skin):
+    """8 steps in one call, 4 + 4, and 8 single-step calls give bitwise the
+    same positions, velocities and forces (counter-based noise; forces that do
+    not depend on the order of partners or on where a call starts)."""
     s = W.langevin_electrolyte()
-    ctx = make_ctx(s, R.RBE_FP32)
+    ctx = make_ctx(s, R.RBE_FP32) if skin is None else make_ctx(s, R.RBE_FP32, skin=skin)
     P, Q, V, F = device_state(ctx, s)
     R.rbe_sample_k(ctx, 0)
     R.rbe_kspace_forces(ctx, P, Q, F)
     R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
     P2, V2, F2 = P.clone(), V.clone(), F.clone()
+    P3, V3, F3 = P.clone(), V.clone(), F.clone()
     R.rbe_step(ctx, P, V, Q, F, 1, 8)
     R.rbe_step(ctx, P2, V2, Q, F2, 1, 4)
-    P3, V3, F3 = P2.clone(), V2.clone(), F2.clone()
-    R.rbe_step(ctx, P3, V3, Q, F3, 5, 4)
-    assert np.array_equal(host(P), host(P3)) and np.array_equal(host(V), host(V3))
+    R.rbe_step(ctx, P2, V2, Q, F2, 5, 4)
+    for k in range(1, 9):
+        R.rbe_step(ctx, P3, V3, Q, F3, k, 1)
+    for a, b, c in ((P, P2, P3), (V, V2, V3), (F, F2, F3)):
+        assert np.array_equal(host(a), host(b)) and np.array_equal(host(a), host(c))
 
 
 @pytest.mark.parametrize("prec,tol", [(R.RBE_FP64, 1e-10), (R.RBE_FP32, 1e-5)])
