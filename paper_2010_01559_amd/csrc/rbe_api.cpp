@@ -581,7 +581,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     ALLOC(w.mode_w_alt, sizeof(double) * c->mcap);
     ALLOC(w.energy_part, sizeof(double) * 8 * rtiles.size());
     ALLOC(w.flag, sizeof(int32_t) * 4);
-    ALLOC(w.lflag, sizeof(int32_t) * 4);
+    ALLOC(w.lflag, sizeof(int32_t) * 8);
     {
         // list-pass tiles: at most one per 32 slots (the 8-lane shape)
         int64_t nl = 0;
@@ -607,7 +607,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
               hipMemset(w.mh_state, 0, sizeof(int32_t) * 3 * R) == hipSuccess &&
               hipMemset(w.cell_count, 0, sizeof(int32_t) * cell_off) == hipSuccess &&
               hipMemset(w.flag, 0, sizeof(int32_t) * 4) == hipSuccess &&
-              hipMemset(w.lflag, 0, sizeof(int32_t) * 4) == hipSuccess &&
+              hipMemset(w.lflag, 0, sizeof(int32_t) * 8) == hipSuccess &&
               hipMemset(w.modes, 0, sizeof(int32_t) * 3 * c->mcap) == hipSuccess;
     if (ok) ok = upload_rho_tiles(c) == RBE_OK;
     if (ok) ok = upload_list_tiles(c) == RBE_OK;
@@ -811,10 +811,10 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
     // one step = four launches: [integrate + bin + draw modes + structure-factor
     // partials] -> [totals + cell scan] -> [Fourier force + scatter] ->
     // [real space + LJ + final half kick].  In list mode: [integrate + list
-    // bookkeeping + draw modes + partials] -> [totals + binning] -> [scan] ->
-    // [scatter] -> [Fourier + real space + LJ + final half kick], where the
-    // binning, scan and scatter do work only on rebuild steps (decided on the
-    // device).
+    // bookkeeping + partials] -> [totals + next step's modes + binning] ->
+    // [cell scan + scatter] -> [Fourier + real space + LJ + final half kick],
+    // where binning, scan and scatter do work only on rebuild steps (decided
+    // on the device).
     int table_lds = 0, tab_max = 0;
     const size_t lds = stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max);
     const bool fuse_sample = !c->any_mh && lds <= 64 * 1024;
@@ -828,7 +828,7 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
             // launch of the step before (exact sampler)
             const bool first = t == 0, last = t == nsteps - 1;
             const int par = (int)(c->list_gen & 1);
-            ListStep ls{c->w.lflag + par, c->w.lflag + (1 - par), c->w.lflag + 2, c->w.lflag + 3,
+            ListStep ls{c->w.lflag + par, c->w.lflag + (1 - par), c->w.lflag + 2, c->w.lflag + 3, c->w.lflag + 4,
                         c->list_valid ? 0 : 1};
             const bool drawn = !first && !c->any_mh;
             if (!drawn && !fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
@@ -836,9 +836,8 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
             RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
             const bool draw_next = !c->any_mh && !last;
             RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild, ls.rebuild_next, draw_next ? 1 : 0,
-                                     ks + 1));
-            RUN(c, K_SCAN, launch_mid(c->cfg, c->w, 0, 1, ls.rebuild));
-            RUN(c, K_SCATTER, launch_scatter(c->cfg, c->w, &ls));
+                                     ks + 1, &ls));
+            RUN(c, K_SCATTER, launch_rebuild(c->cfg, c->w, ls));
             RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, andersen ? nullptr : vel));
             c->list_valid = true;
             ++c->list_gen;

@@ -139,7 +139,7 @@ struct Workspace {
     void *ref;             // [Ntot] record of each particle at the last build (original order)
     int32_t *nbr;          // [kmax][Ntot] partner slots, column k of slot s at k * Ntot + s
     int32_t *nnb;          // [Ntot] partners of each slot
-    int32_t *lflag;        // [4]: rebuild request for even / odd steps, list overflow, builds
+    int32_t *lflag;        // [8]: rebuild request for even / odd steps, list overflow, builds, scan ready
 };
 
 struct LaunchCfg {
@@ -165,6 +165,7 @@ struct ListStep {
     int32_t *rebuild_next;   // request flag of the next step
     int32_t *overflow;
     int32_t *rebuilds;       // count of list builds
+    int32_t *ready;          // rebuild: cell scan done (set by the rebuild launch, cleared by the totals launch)
     int force_rebuild;
 };
 
@@ -186,10 +187,12 @@ hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageReque
 size_t stage_lds_bytes(const LaunchCfg &c, int sample_in_kernel, int *table_lds, int *tab_max);
 hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
                       const int32_t *scan_gate = nullptr, const int32_t *bin_gate = nullptr,
-                      int32_t *clear_flag = nullptr, int sample_next = 0, uint64_t sample_step = 0);
+                      int32_t *clear_flag = nullptr, int sample_next = 0, uint64_t sample_step = 0,
+                      const ListStep *ls = nullptr);
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
                          int accumulate, int scatter, const int32_t *bin_gate = nullptr);
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);
+hipError_t launch_rebuild(const LaunchCfg &c, const Workspace &w, const ListStep &ls);
 hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick);
 hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick);
 hipError_t launch_energy(const LaunchCfg &c, const Workspace &w, const void *q, const void *vel);

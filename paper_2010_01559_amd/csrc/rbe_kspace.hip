@@ -24,6 +24,8 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rbe_device.h"
 #include "rbe_internal.h"
 
@@ -402,14 +404,13 @@ struct MidArgs {
     int32_t *modes_next;
     double *mode_w_next;
     int32_t *clear_flag;
+    int32_t *clear_flag2;
 };
 
 // Cell of a stored record and its atomic rank within the cell.
 template <typename KM>
-__device__ void mid_bin(const MidArgs<KM> &a, int b)
+__device__ void mid_bin_tile(const MidArgs<KM> &a, int ti)
 {
-    const int ti = 4 * b + (int)(threadIdx.x >> 8);
-    if (ti >= a.n_part_tiles) return;
     const Tile t = a.part_tiles[ti];
     const int k = threadIdx.x & 255;
     if (k >= t.count) return;
@@ -431,6 +432,16 @@ __device__ void mid_bin(const MidArgs<KM> &a, int b)
     a.cellid[i] = c;
     a.rank[i] = atomicAdd(&a.count[c], 1);
 }
+
+// Few blocks, each striding over the 256-particle tiles: on the many steps
+// where nothing is binned the launch costs only their dispatch.
+template <typename KM>
+__device__ void mid_bin(const MidArgs<KM> &a, int b)
+{
+    for (int ti = 4 * b + (int)(threadIdx.x >> 8); ti < a.n_part_tiles; ti += 4 * a.n_bin_blocks)
+        mid_bin_tile<KM>(a, ti);
+}
+
 
 template <typename KM>
 __device__ void mid_final(const MidArgs<KM> &a, int gm)
@@ -539,11 +550,121 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
     if (tid == 0) st[ncell] = S.off + carry;
 }
 
+// ---------------------------------------------------------------------------
+// k_rebuild: the rest of a neighbour-list rebuild (does nothing unless the
+// step's rebuild flag is set).  Block 0 scans every system's cell counts and
+// then raises `ready`; every other block waits for it (block 0 is dispatched
+// first and waits on nobody, so the wait ends) and then strides over the
+// 256-particle tiles, scattering them into cell order: slot, record,
+// reference record.  The wait is bounded;
+// if the bound is ever reached the block raises the error flag instead.
+// ---------------------------------------------------------------------------
+struct RebuildArgs {
+    const SysDev *sys;
+    int R;
+    const int32_t *gate;
+    int32_t *ready;
+    int32_t *count;
+    int32_t *start;
+    const Tile *part_tiles;
+    int n_part_tiles;
+    const int32_t *cellid;
+    const int32_t *rank;
+    const void *packed;
+    int32_t *sorted_idx;
+    void *sorted;
+    int32_t *slot_of;
+    void *ref;
+    int32_t *overflow;
+    int32_t *builds;
+    int32_t *flag;
+};
+
+template <typename Rec>
+__global__ __launch_bounds__(1024) void k_rebuild(RebuildArgs a)
+{
+    if (*a.gate == 0) return;
+    if (blockIdx.x == 0) {
+        for (int r = 0; r < a.R; ++r) mid_scan(a.sys[r], r, a.count, a.start);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            *a.overflow = 0;
+            *a.builds += 1;
+            __threadfence();
+            __hip_atomic_store(a.ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        int ok = 0;
+        for (int it = 0; it < (1 << 24); ++it) {
+            if (__hip_atomic_load(a.ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (!ok) atomicOr(a.flag, 2);
+        s_ok = ok;
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    __threadfence();
+    const int nw = gridDim.x - 1;
+    for (int ti = 4 * (blockIdx.x - 1) + (int)(threadIdx.x >> 8); ti < a.n_part_tiles; ti += 4 * nw) {
+        const Tile t = a.part_tiles[ti];
+        const int k = threadIdx.x & 255;
+        if (k >= t.count) continue;
+        const int64_t i = a.sys[t.sys].off + t.start + k;
+        const int slot = a.start[a.cellid[i] + t.sys] + a.rank[i];
+        const Rec v = reinterpret_cast<const Rec *>(a.packed)[i];
+        a.sorted_idx[slot] = (int32_t)i;
+        reinterpret_cast<Rec *>(a.sorted)[slot] = v;
+        a.slot_of[i] = slot;
+        reinterpret_cast<Rec *>(a.ref)[i] = v;
+    }
+}
+
+hipError_t launch_rebuild(const LaunchCfg &c, const Workspace &w, const ListStep &ls)
+{
+    RebuildArgs a;
+    a.sys = w.sys;
+    a.R = c.R;
+    a.gate = ls.rebuild;
+    a.ready = ls.ready;
+    a.count = w.cell_count;
+    a.start = w.cell_start;
+    a.part_tiles = w.part_tiles;
+    a.n_part_tiles = c.n_part_tiles;
+    a.cellid = w.cellid;
+    a.rank = w.rank;
+    a.packed = w.packed;
+    a.sorted_idx = w.sorted_idx;
+    a.sorted = w.sorted;
+    a.slot_of = w.slot_of;
+    a.ref = w.ref;
+    a.overflow = ls.overflow;
+    a.builds = ls.rebuilds;
+    a.flag = w.flag;
+    // few blocks: on the many steps without a rebuild the launch costs only
+    // their dispatch
+    const int nb = 1 + std::min(16, (c.n_part_tiles + 3) / 4);
+    if (c.prec == RBE_FP64)
+        k_rebuild<PartD><<<nb, 1024, 0, c.stream>>>(a);
+    else
+        k_rebuild<PackF><<<nb, 1024, 0, c.stream>>>(a);
+    return hipGetLastError();
+}
+
 template <typename KM>
 __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
 {
     extern __shared__ double mid_tab[];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.clear_flag) *a.clear_flag = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.clear_flag) {
+        *a.clear_flag = 0;
+        if (a.clear_flag2) *a.clear_flag2 = 0;
+    }
     if ((int)blockIdx.x < a.n_final_blocks) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         mid_final<KM>(a, blockIdx.x * 16 + wave);
@@ -990,7 +1111,7 @@ hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageReque
 template <typename KM>
 static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
                                const int32_t *gate, const int32_t *bin_gate, int32_t *clear_flag, int sample_next,
-                               uint64_t sample_step)
+                               uint64_t sample_step, const ListStep *ls)
 {
     MidArgs<KM> a;
     a.sys = w.sys;
@@ -1009,7 +1130,7 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.do_scan = do_scan;
     a.scan_gate = gate;
     a.bin_gate = bin_gate;
-    a.n_bin_blocks = bin_gate ? (c.n_part_tiles + 3) / 4 : 0;
+    a.n_bin_blocks = bin_gate ? std::min(16, (c.n_part_tiles + 3) / 4) : 0;
     a.part_tiles = w.part_tiles;
     a.n_part_tiles = c.n_part_tiles;
     a.packed = w.packed;
@@ -1022,6 +1143,7 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.modes_next = w.modes_alt;
     a.mode_w_next = w.mode_w_alt;
     a.clear_flag = clear_flag;
+    a.clear_flag2 = ls ? ls->ready : nullptr;
     const size_t sm = a.table_lds ? sizeof(double) * c.max_table : 0;
     const int nb = a.n_final_blocks + a.n_bin_blocks + a.n_sample_blocks + (do_scan ? c.R : 0);
     if (nb == 0) return hipSuccess;
@@ -1030,11 +1152,13 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
 }
 
 hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan, const int32_t *gate,
-                      const int32_t *bin_gate, int32_t *clear_flag, int sample_next, uint64_t sample_step)
+                      const int32_t *bin_gate, int32_t *clear_flag, int sample_next, uint64_t sample_step,
+                      const ListStep *ls)
 {
-    return c.prec == RBE_FP64
-               ? mid_dispatch<KModeD>(c, w, do_final, do_scan, gate, bin_gate, clear_flag, sample_next, sample_step)
-               : mid_dispatch<KModeF>(c, w, do_final, do_scan, gate, bin_gate, clear_flag, sample_next, sample_step);
+    return c.prec == RBE_FP64 ? mid_dispatch<KModeD>(c, w, do_final, do_scan, gate, bin_gate, clear_flag,
+                                                     sample_next, sample_step, ls)
+                              : mid_dispatch<KModeF>(c, w, do_final, do_scan, gate, bin_gate, clear_flag,
+                                                     sample_next, sample_step, ls);
 }
 
 template <typename T, typename KM>
