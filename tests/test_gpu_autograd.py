@@ -1,0 +1,105 @@
+"""GPU: the differentiable form (torch.autograd.Function over the library's
+forward and adjoint) against the FP64 oracle's vector-Jacobian product and
+against central finite differences of the loss.
+
+Force-matching loss: mean over all 3N components of (F - F_ref)^2 with a
+constant reference; gradients with respect to positions and charges at a
+fixed mode sample (paper eq. 3.6 for the Fourier part, eq. 2.11 and eq. 4.1
+for the real-space and LJ parts).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2010_01559_amd.rbe as R
+from paper_2010_01559_amd import workloads as W
+from paper_2010_01559_amd.autograd import force_matching_loss, rbe_forces
+from gpu_util import host, make_ctx, rel_l2, rounded
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_grads(s, pos, q, modes, Fref, parts, lj):
+    w = O.rbe_weights(s.alpha, s.L, s.p)
+    F = np.zeros((3, s.n))
+    if parts & R.RBE_PART_KSPACE:
+        F += O.kspace_force(pos, q, s.L, modes, w, s.coulomb)
+    if parts & R.RBE_PART_REAL:
+        F += O.real_force(pos, q, s.L, s.alpha, s.r_cut, s.coulomb, lj)[0]
+    G = 2.0 * (F - Fref) / F.size
+    gq, gr = O.forces_vjp(pos, q, s.L, s.alpha, s.r_cut, modes, w, G, s.coulomb, lj, parts=parts)
+    return F, gq, gr
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBE_FP64, 1e-10), (R.RBE_FP32, 1e-5)])
+@pytest.mark.parametrize("parts", [R.RBE_PART_ALL, R.RBE_PART_KSPACE, R.RBE_PART_REAL])
+def test_loss_gradient_matches_oracle(prec, tol, parts):
+    s = W.gaussian_charge_system(n=2000, p=50)
+    ctx = make_ctx(s, prec)
+    dt = torch.float64 if prec == R.RBE_FP64 else torch.float32
+    pos, q = rounded(s, prec)
+    P = torch.tensor(pos, dtype=dt, device="cuda", requires_grad=True)
+    Q = torch.tensor(q, dtype=dt, device="cuda", requires_grad=True)
+    Fref = torch.as_tensor(np.random.default_rng(4).normal(size=(3, s.n)), dtype=dt, device="cuda")
+    m = torch.zeros((3, s.p), dtype=torch.int32, device="cuda")
+    R.rbe_sample_k(ctx, 11, m)
+    loss = force_matching_loss(ctx, P, Q, Fref, parts)
+    loss.backward()
+    Fo, gqo, gro = _oracle_grads(s, pos, q, m.cpu().numpy(), host(Fref), parts, s.lj)
+    assert float(loss.detach()) == pytest.approx(((Fo - host(Fref)) ** 2).mean(), rel=10 * tol)
+    assert rel_l2(host(P.grad), gro) <= tol
+    assert rel_l2(host(Q.grad), gqo) <= tol
+
+
+def test_loss_gradient_central_differences():
+    """FP64 on the GPU alone: d loss / d q_i and d loss / d x_i by central
+    differences of the GPU loss, against autograd (Coulomb only, particles
+    away from the cutoff sphere)."""
+    s = W.gaussian_charge_system(n=400, p=40, density=0.1)
+    ctx = make_ctx(s, R.RBE_FP64)
+    P = torch.tensor(s.pos, device="cuda", requires_grad=True)
+    Q = torch.tensor(s.q, device="cuda", requires_grad=True)
+    Fref = torch.as_tensor(np.random.default_rng(9).normal(size=(3, s.n)), device="cuda")
+    R.rbe_sample_k(ctx, 3)
+    loss = force_matching_loss(ctx, P, Q, Fref)
+    loss.backward()
+    gP, gQ = host(P.grad), host(Q.grad)
+
+    def L_of(pp, qq):
+        with torch.no_grad():
+            return float(force_matching_loss(ctx, pp, qq, Fref))
+
+    h = 1e-5
+    pos = s.pos
+    checked = 0
+    for i in range(0, s.n, 37):
+        d = pos[:, :] - pos[:, i:i + 1]
+        d -= s.L * np.round(d / s.L)
+        r = np.sqrt((d * d).sum(0))
+        if np.any(np.abs(r - s.r_cut) < 4 * h):
+            continue
+        qp, qm = Q.detach().clone(), Q.detach().clone()
+        qp[i] += h
+        qm[i] -= h
+        fd = (L_of(P.detach(), qp) - L_of(P.detach(), qm)) / (2 * h)
+        assert fd == pytest.approx(gQ[i], rel=1e-5, abs=1e-10)
+        pp, pm = P.detach().clone(), P.detach().clone()
+        pp[0, i] += h
+        pm[0, i] -= h
+        fd = (L_of(pp, Q.detach()) - L_of(pm, Q.detach())) / (2 * h)
+        assert fd == pytest.approx(gP[0, i], rel=1e-5, abs=1e-10)
+        checked += 1
+    assert checked >= 5
+
+
+def test_forces_match_plain_calls():
+    s = W.langevin_electrolyte()
+    ctx = make_ctx(s, R.RBE_FP32)
+    P = torch.as_tensor(s.pos, dtype=torch.float32, device="cuda").contiguous()
+    Q = torch.as_tensor(s.q, dtype=torch.float32, device="cuda").contiguous()
+    R.rbe_sample_k(ctx, 2)
+    F = torch.zeros_like(P)
+    R.rbe_kspace_forces(ctx, P, Q, F)
+    R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
+    assert torch.equal(rbe_forces(ctx, P, Q), F)
