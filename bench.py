@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true", help="pick the Fourier tile shapes by timing")
+    ap.add_argument("--graphs", action="store_true", help="replay the steady-state steps from hipGraphs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -154,6 +155,7 @@ def main():
     F = torch.zeros_like(P)
     stream = ctx.stream
 
+    R.rbe_use_graphs(ctx, args.graphs)
     R.rbe_sample_k(ctx, 0)
     tiles = R.rbe_autotune(ctx, P, Q, reps=20) if args.autotune else R.rbe_get_tiles(ctx)
     R.rbe_kspace_forces(ctx, P, Q, F)

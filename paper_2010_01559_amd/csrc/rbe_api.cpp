@@ -158,6 +158,21 @@ struct rbe_ctx {
     int64_t prof_n[K_COUNT] = {};
     // host staging
     std::vector<double> epart_h;
+    // graphs of steady-state list steps, keyed by everything their
+    // kernel arguments were taken from
+    bool graphs = false;
+    hipStream_t cap_stream = nullptr;
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        LaunchCfg cfg{};
+        Workspace w{};
+        const void *pos, *vel, *q, *force;
+        int par;
+        bool andersen;
+        uint64_t used;
+    };
+    std::vector<StepGraph> step_graphs;
+    uint64_t graph_clock = 0;
 };
 
 namespace {
@@ -238,8 +253,17 @@ rbe_status dalloc(rbe_ctx *c, T **p, size_t bytes)
     return RBE_OK;
 }
 
+void drop_graphs(rbe_ctx *c)
+{
+    for (auto &g : c->step_graphs) (void)hipGraphExecDestroy(g.exec);
+    c->step_graphs.clear();
+}
+
 void free_all(rbe_ctx *c)
 {
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
 }
@@ -582,6 +606,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     ALLOC(w.energy_part, sizeof(double) * 8 * rtiles.size());
     ALLOC(w.flag, sizeof(int32_t) * 4);
     ALLOC(w.lflag, sizeof(int32_t) * 8);
+    ALLOC(w.step_base, sizeof(uint64_t));
     {
         // list-pass tiles: at most one per 32 slots (the 8-lane shape)
         int64_t nl = 0;
@@ -669,6 +694,7 @@ rbe_status rbe_reserve_modes(rbe_ctx *c, int32_t cap)
         *slot = nw;
         return RBE_OK;
     };
+    drop_graphs(c);
     const int old_cap = c->mcap;
     c->mcap = cap;
     rbe_status s;
@@ -789,6 +815,109 @@ rbe_status rbe_real_forces(rbe_ctx *c, const void *pos, const void *q, void *for
     return RBE_OK;
 }
 
+// The four launches of one list-mode step.  With base set (graph capture),
+// s and ks are offsets from the device step number *base, and the force
+// launch advances it by bump.
+static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force, uint64_t s, uint64_t ks,
+                            bool first, bool last, bool fuse_sample, bool andersen, uint64_t *base, uint32_t bump)
+{
+    const int par = (int)(c->list_gen & 1);
+    ListStep ls{c->w.lflag + par, c->w.lflag + (1 - par), c->w.lflag + 2, c->w.lflag + 3, c->w.lflag + 4,
+                c->list_valid ? 0 : 1};
+    ls.step_base = base;
+    ls.step_bump = bump ? base : nullptr;
+    ls.bump = bump;
+    // the staging launch integrates (in particle order); the modes of every
+    // step after the first of a call were drawn by the totals launch of the
+    // step before (exact sampler)
+    const bool drawn = !first && !c->any_mh;
+    if (!drawn && !fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
+    StageRequest rq{pos, vel, force, q, s, ks, 1, 0, (!drawn && fuse_sample) ? 1 : 0, 1, &ls};
+    RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
+    const bool draw_next = !c->any_mh && !last;
+    RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild, ls.rebuild_next, draw_next ? 1 : 0, ks + 1,
+                             &ls));
+    RUN(c, K_SCATTER, launch_rebuild(c->cfg, c->w, ls));
+    RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, andersen ? nullptr : vel));
+    c->list_valid = true;
+    ++c->list_gen;
+    if (draw_next) {
+        std::swap(c->w.modes, c->w.modes_alt);
+        std::swap(c->w.mode_w, c->w.mode_w_alt);
+    }
+    return RBE_OK;
+}
+
+static bool same_bytes(const void *a, const void *b, size_t n) { return std::memcmp(a, b, n) == 0; }
+
+// Step pairs per captured graph (a replay covers 2 * kGraphPairs steps).
+constexpr int kGraphPairs = 8;
+
+// Graph of 2 * kGraphPairs steady-state list steps (neither the first nor the last of a
+// call, modes drawn by the step before, list valid) for the current buffers
+// and parity; captured on first use.
+static rbe_status step_graph(rbe_ctx *c, void *pos, void *vel, const void *q, void *force, bool andersen,
+                             hipGraphExec_t *out)
+{
+    const int par = (int)(c->list_gen & 1);
+    LaunchCfg cfg = c->cfg;
+    for (auto &g : c->step_graphs)
+        if (g.pos == pos && g.vel == vel && g.q == q && g.force == force && g.par == par && g.andersen == andersen &&
+            same_bytes(&g.w, &c->w, sizeof(Workspace)) && same_bytes(&g.cfg, &cfg, sizeof(LaunchCfg))) {
+            g.used = ++c->graph_clock;
+            *out = g.exec;
+            return RBE_OK;
+        }
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    rbe_ctx::StepGraph g;
+    g.cfg = c->cfg;
+    g.w = c->w;
+    g.pos = pos;
+    g.vel = vel;
+    g.q = q;
+    g.force = force;
+    g.par = par;
+    g.andersen = andersen;
+    // capture on the context's own stream, leaving the state as it was
+    const uint64_t gen = c->list_gen;
+    const Workspace w0 = c->w;
+    c->cfg.stream = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    rbe_status st = RBE_OK;
+    if (e == hipSuccess) {
+        // kGraphPairs copies of the two steps; each pair's second force
+        // launch advances the device step number by 2
+        const uint64_t k0 = andersen ? 1 : 0;
+        for (int k = 0; k < kGraphPairs && st == RBE_OK; ++k) {
+            st = list_step(c, pos, vel, q, force, 0, k0, false, false, false, andersen, c->w.step_base, 0);
+            if (st == RBE_OK)
+                st = list_step(c, pos, vel, q, force, 1, k0 + 1, false, false, false, andersen, c->w.step_base, 2);
+        }
+        e = hipStreamEndCapture(c->cap_stream, &graph);
+    }
+    c->cfg.stream = cfg.stream;
+    c->list_gen = gen;
+    c->w = w0;
+    if (st != RBE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(c, e, "capturing the step graph");
+    if (c->step_graphs.size() >= 4) {
+        auto lru = std::min_element(c->step_graphs.begin(), c->step_graphs.end(),
+                                    [](const auto &a, const auto &b) { return a.used < b.used; });
+        (void)hipGraphExecDestroy(lru->exec);
+        c->step_graphs.erase(lru);
+    }
+    g.used = ++c->graph_clock;
+    c->step_graphs.push_back(g);
+    *out = g.exec;
+    return RBE_OK;
+}
+
 rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force, uint64_t first_step,
                     int32_t nsteps)
 {
@@ -814,37 +943,31 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
     // bookkeeping + partials] -> [totals + next step's modes + binning] ->
     // [cell scan + scatter] -> [Fourier + real space + LJ + final half kick],
     // where binning, scan and scatter do work only on rebuild steps (decided
-    // on the device).
+    // on the device).  In list mode the steady-state steps of a call (after
+    // the first, before the last) are replayed in pairs from a graph.
     int table_lds = 0, tab_max = 0;
     const size_t lds = stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max);
     const bool fuse_sample = !c->any_mh && lds <= 64 * 1024;
     const bool list = c->cfg.list_on != 0;
-    for (int32_t t = 0; t < nsteps; ++t) {
+    const bool graphs = list && c->graphs && !c->any_mh && !c->prof;
+    for (int32_t t = 0; t < nsteps;) {
         const uint64_t s = first_step + (uint64_t)t;
         const uint64_t ks = andersen ? s + 1 : s;
         if (list) {
-            // the staging launch integrates (in particle order); the modes of
-            // every step after the first of a call were drawn by the totals
-            // launch of the step before (exact sampler)
-            const bool first = t == 0, last = t == nsteps - 1;
-            const int par = (int)(c->list_gen & 1);
-            ListStep ls{c->w.lflag + par, c->w.lflag + (1 - par), c->w.lflag + 2, c->w.lflag + 3, c->w.lflag + 4,
-                        c->list_valid ? 0 : 1};
-            const bool drawn = !first && !c->any_mh;
-            if (!drawn && !fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
-            StageRequest rq{pos, vel, force, q, s, ks, 1, 0, (!drawn && fuse_sample) ? 1 : 0, 1, &ls};
-            RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
-            const bool draw_next = !c->any_mh && !last;
-            RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild, ls.rebuild_next, draw_next ? 1 : 0,
-                                     ks + 1, &ls));
-            RUN(c, K_SCATTER, launch_rebuild(c->cfg, c->w, ls));
-            RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, andersen ? nullptr : vel));
-            c->list_valid = true;
-            ++c->list_gen;
-            if (draw_next) {
-                std::swap(c->w.modes, c->w.modes_alt);
-                std::swap(c->w.mode_w, c->w.mode_w_alt);
+            const int32_t reps = (nsteps - 1 - t) / (2 * kGraphPairs);
+            if (graphs && t > 0 && c->list_valid && reps > 0) {
+                hipGraphExec_t exec;
+                rbe_status st = step_graph(c, pos, vel, q, force, andersen, &exec);
+                if (st != RBE_OK) return st;
+                RUN(c, K_MISC, launch_set_step(c->cfg, c->w, s));
+                for (int32_t k = 0; k < reps; ++k) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+                c->list_gen += 2 * (uint64_t)kGraphPairs * reps;
+                t += 2 * kGraphPairs * reps;
+                continue;
             }
+            rbe_status st = list_step(c, pos, vel, q, force, s, ks, t == 0, t == nsteps - 1, fuse_sample, andersen,
+                                      nullptr, 0);
+            if (st != RBE_OK) return st;
         } else {
             if (!fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
             StageRequest rq{pos, vel, force, q, s, ks, 1, 1, fuse_sample ? 1 : 0, 1};
@@ -853,8 +976,18 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
             RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, 0, 1));
             RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, andersen ? nullptr : vel));
         }
+        ++t;
     }
     if (nsteps > 0) c->modes_valid = true;
+    return RBE_OK;
+}
+
+rbe_status rbe_use_graphs(rbe_ctx *c, int32_t enable)
+{
+    if (!c) return RBE_ERR_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->graphs = enable != 0;
+    if (!c->graphs) drop_graphs(c);
     return RBE_OK;
 }
 

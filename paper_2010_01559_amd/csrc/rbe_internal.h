@@ -140,6 +140,7 @@ struct Workspace {
     int32_t *nbr;          // [kmax][Ntot] partner slots, column k of slot s at k * Ntot + s
     int32_t *nnb;          // [Ntot] partners of each slot
     int32_t *lflag;        // [8]: rebuild request for even / odd steps, list overflow, builds, scan ready
+    uint64_t *step_base;   // [1]: step number of a graph replay (see ListStep)
 };
 
 struct LaunchCfg {
@@ -167,6 +168,11 @@ struct ListStep {
     int32_t *rebuilds;       // count of list builds
     int32_t *ready;          // rebuild: cell scan done (set by the rebuild launch, cleared by the totals launch)
     int force_rebuild;
+    // graph replays: the step numbers passed to the launches are offsets
+    // from *step_base (device), which the force launch advances by `bump`
+    const uint64_t *step_base = nullptr;
+    uint64_t *step_bump = nullptr;
+    uint32_t bump = 0;
 };
 
 // What one launch of the staging kernel does.
@@ -192,6 +198,7 @@ hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int 
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
                          int accumulate, int scatter, const int32_t *bin_gate = nullptr);
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);
+hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step);
 hipError_t launch_rebuild(const LaunchCfg &c, const Workspace &w, const ListStep &ls);
 hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick);
 hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick);

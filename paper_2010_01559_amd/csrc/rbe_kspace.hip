@@ -253,12 +253,14 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
     if (a.do_sample && a.table_lds)
         for (int k = tid; k < K; k += BS) tab[k] = a.cdf[S.cdf_off + k];
     bool moved = false;
+    const uint64_t base = a.list_mode && a.ls.step_base ? *a.ls.step_base : 0;
+    const uint64_t step = a.step + base, sample_step = a.sample_step + base;
     for (int j = tid; j < count; j += BS) {
         const int il = t.start + j;
         const int64_t i = S.off + il;
         double x[3];
         if (a.do_integrate) {
-            integrate_one<T>(S, il, i, a.ntot, a.pos, a.vel, a.F, a.step, x);
+            integrate_one<T>(S, il, i, a.ntot, a.pos, a.vel, a.F, step, x);
         } else {
             x[0] = (double)a.pos[i];
             x[1] = (double)a.pos[a.ntot + i];
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
             const int l = m0 + tid;
             int mx, my, mz;
             if (a.do_sample) {
-                sample_mode(tabp, S.M, (uint32_t)l, S.seed, a.sample_step, mx, my, mz);
+                sample_mode(tabp, S.M, (uint32_t)l, S.seed, sample_step, mx, my, mz);
                 if (t.aux == 0) {
                     const int o = S.moff + l;
                     a.modes[o] = mx;
@@ -405,6 +407,7 @@ struct MidArgs {
     double *mode_w_next;
     int32_t *clear_flag;
     int32_t *clear_flag2;
+    const uint64_t *step_base;   // added to sample_step when set
 };
 
 // Cell of a stored record and its atomic rank within the cell.
@@ -626,6 +629,19 @@ __global__ __launch_bounds__(1024) void k_rebuild(RebuildArgs a)
     }
 }
 
+__global__ void k_set_step(uint64_t *base, uint64_t step)
+{
+    if (threadIdx.x == 0) *base = step;
+}
+
+// Sets the device step number that graph-replayed steps add to their step
+// offsets (a kernel, so that no memset or copy node is needed).
+hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step)
+{
+    k_set_step<<<1, 64, 0, c.stream>>>(w.step_base, step);
+    return hipGetLastError();
+}
+
 hipError_t launch_rebuild(const LaunchCfg &c, const Workspace &w, const ListStep &ls)
 {
     RebuildArgs a;
@@ -687,7 +703,8 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
         }
         for (int l = threadIdx.x; l < S.p; l += blockDim.x) {
             int mx, my, mz;
-            sample_mode(t, S.M, (uint32_t)l, S.seed, a.sample_step, mx, my, mz);
+            sample_mode(t, S.M, (uint32_t)l, S.seed, a.sample_step + (a.step_base ? *a.step_base : 0), mx, my,
+                        mz);
             const int o = S.moff + l;
             a.modes_next[o] = mx;
             a.modes_next[a.mcap + o] = my;
@@ -1144,6 +1161,7 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.mode_w_next = w.mode_w_alt;
     a.clear_flag = clear_flag;
     a.clear_flag2 = ls ? ls->ready : nullptr;
+    a.step_base = ls ? ls->step_base : nullptr;
     const size_t sm = a.table_lds ? sizeof(double) * c.max_table : 0;
     const int nb = a.n_final_blocks + a.n_bin_blocks + a.n_sample_blocks + (do_scan ? c.R : 0);
     if (nb == 0) return hipSuccess;

@@ -729,6 +729,9 @@ template <typename T, int LPP>
 __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
 {
     __shared__ T s4[4][FT_MAX][3];
+    // no launch of this kernel reads the step number: advance the replay's
+    // base for the next steps
+    if (la.ls.step_bump && blockIdx.x == 0 && threadIdx.x == 0) *la.ls.step_bump += la.ls.bump;
     const int rebuild = *la.ls.rebuild;
     const int nb = rebuild ? la.n_rows : la.n_list;
     if ((int)blockIdx.x >= nb) return;

@@ -43,7 +43,7 @@ STATUS_NAMES = {0: "RBE_OK", -1: "RBE_ERR_INVALID", -2: "RBE_ERR_NOT_NEUTRAL", -
 EXPORTED = ["rbe_normalizer", "rbe_create", "rbe_batch_create", "rbe_destroy", "rbe_last_error",
             "rbe_num_systems", "rbe_num_particles", "rbe_num_modes", "rbe_sample_k", "rbe_set_k",
             "rbe_reserve_modes", "rbe_kspace_forces", "rbe_real_forces", "rbe_step", "rbe_batch_step",
-            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_get_tiles",
+            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_use_graphs", "rbe_get_tiles",
             "rbe_set_tiles", "rbe_autotune", "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name",
             "rbe_profile_count"]
 
@@ -109,6 +109,7 @@ def lib():
     L.rbe_get_rho.argtypes = [vp, vp]
     L.rbe_forces_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32]
     L.rbe_list_builds.argtypes = [vp, C.POINTER(i64)]
+    L.rbe_use_graphs.argtypes = [vp, i32]
     L.rbe_get_tiles.argtypes = [vp, C.POINTER(rbe_tiles)]
     L.rbe_set_tiles.argtypes = [vp, C.POINTER(rbe_tiles)]
     L.rbe_autotune.argtypes = [vp, vp, vp, i32, C.POINTER(rbe_tiles)]
@@ -345,6 +346,11 @@ def rbe_list_builds(ctx):
     v = C.c_int64()
     _check(lib().rbe_list_builds(ctx.handle, C.byref(v)), ctx.handle)
     return v.value
+
+
+def rbe_use_graphs(ctx, enable):
+    """Replay the steady-state steps of rbe_step from captured graphs (default) or not."""
+    _check(lib().rbe_use_graphs(ctx.handle, int(bool(enable))), ctx.handle)
 
 
 def rbe_get_tiles(ctx):
