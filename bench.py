@@ -17,7 +17,9 @@ kernel of the step (the longest one as "roofline"), and the FP64 CPU oracle
 timed on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--autotune] [--calibrate-copy]
+                       [--autotune] [--calibrate-copy] [--graphs]
+       python bench.py --suite PATH   (N x P sweep, batched vs loop,
+                                       forward vs backward, classical Ewald)
 """
 from __future__ import annotations
 
@@ -38,10 +40,12 @@ METRIC = "k-space particle–mode pairs/s (N·P) + MD steps/s at N=1e5, P=100, 1
 # Algorithmic work in FP32 VALU issue slots (an FP64 add/mul/FMA takes 2, a
 # transcendental op 4) and the chip's FP32 vector peak: 256 CUs x 128 FP32
 # lanes/clock x 2 flop x 2.4 GHz.  One slot counts as 2 flop.
-# Per particle-mode pair:
-SLOTS_FORCE = 3 * 2 + 2 * 2 + 2 * 4 + 2 + 3   # phase (3 FP64 FMA), wrap (2 FP64), sin+cos, Im term, 3 FMA
-SLOTS_RHO = 3 * 2 + 2 * 2 + 2 * 4 + 2         # phase, wrap, sin+cos, 2 FMA
-# Real space, per candidate distance test (3 integer differences, 3
+# Per particle-mode pair, with the phase of the exact-wrap FP32 scheme
+# (theta = fract(m . s_hi) + m . s_lo: 3 products, 1 fract, 3 FMA, 1 add):
+SLOTS_PHASE = 8
+SLOTS_RHO = SLOTS_PHASE + 2 * 4 + 2           # phase, sin+cos, 2 FMA into (C, S)
+SLOTS_FORCE = SLOTS_PHASE + 2 * 4 + 2 + 3     # phase, sin+cos, cos S - sin C, 3 FMA into F
+# Real space, per neighbour-list entry (3 integer differences, 3
 # conversions, |d|^2, compare) and per pair inside the cutoff (displacement,
 # rsqrt, exp, the erfc rational form with its reciprocal, Coulomb and LJ
 # factors, force accumulation); both counted over ordered pairs.
@@ -64,6 +68,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true", help="pick the Fourier tile shapes by timing")
+    ap.add_argument("--suite", metavar="PATH", help="run the sweep/batched/gradient/Ewald suite into PATH instead")
     ap.add_argument("--graphs", action="store_true", help="replay the steady-state steps from hipGraphs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
@@ -93,22 +98,16 @@ def cpu_baseline(s, modes, budget_s):
                       f"P={s.p} workload in {el:.1f} s"}
 
 
-def real_space_counts(s):
-    """Ordered candidate pairs of the 27-cell stencil and ordered pairs within
-    the largest cutoff, for the initial configuration."""
+def real_space_counts(s, skin):
+    """Ordered pairs within the largest cutoff plus the list skin (the list
+    entries a step tests) and within the largest cutoff, for the initial
+    configuration."""
     from scipy.spatial import cKDTree
     rmax = max(s.r_cut, s.lj[2] * s.lj[1]) if s.lj[0] > 0 else s.r_cut
-    nc = min(int(np.floor(s.L / rmax)), 128)
-    frac = np.mod(s.pos / s.L, 1.0)
-    c = np.minimum((frac * nc).astype(np.int64), nc - 1)
-    cnt = np.zeros((nc, nc, nc), np.int64)
-    np.add.at(cnt, (c[2], c[1], c[0]), 1)
-    near = sum(np.roll(cnt, (dz, dy, dx), axis=(0, 1, 2))
-               for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1))
-    cand = int((cnt * near).sum()) - s.n
-    tree = cKDTree(frac.T * s.L, boxsize=s.L)
+    tree = cKDTree(np.mod(s.pos, s.L).T, boxsize=s.L)
+    entries = 2 * len(tree.query_pairs(rmax + skin, output_type="ndarray"))
     pairs = 2 * len(tree.query_pairs(rmax, output_type="ndarray"))
-    return cand, pairs
+    return entries, pairs
 
 
 def source_sha(name):
@@ -127,12 +126,200 @@ def traffic_for(name):
     return round((t["fetch_kib"] + t["write_kib"]) * 1024 * t["scale"])
 
 
+# ---------------------------------------------------------------------------
+# Suite (--suite PATH): the N x P sweep, batched replicas against a loop of
+# single-system calls, the differentiable form, and classical Ewald on the
+# same kernels.  Written to PATH as one JSON document.
+# ---------------------------------------------------------------------------
+
+def _timed(torch, stream, fn, reps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(reps):
+        fn(k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _kernel_us(R, ctx, fn, reps):
+    R.rbe_profile_enable(ctx, True)
+    for k in range(reps):
+        fn(k)
+    prof = R.rbe_profile_read(ctx)
+    R.rbe_profile_enable(ctx, False)
+    return {name: 1e3 * ms / n for name, (ms, n) in prof.items() if n}
+
+
+def _frac(slots, us):
+    ach = slots * 2 / (us * 1e-6) / 1e12
+    return {"achieved": round(ach, 3), "frac": round(ach / PEAK_FP32_TFLOPS, 4), "avg_launch_us": round(us, 2)}
+
+
+def suite_np_sweep(torch, R, W, log):
+    """N in {1e4, 1e5, 1e6} x P in {50, 100, 200, 500}: Fourier-only pairs/s
+    (sample + structure factor + force), MD steps/s, and the ALU roofline of
+    the structure-factor and force launches."""
+    out = []
+    for n in (10000, 100000, 1000000):
+        s = W.metric_system() if n == 100000 else W.scaling_system(n, 100)
+        for p in (50, 100, 200, 500):
+            ctx = R.rbe_create(R.params_from_system(s, R.RBE_FP32, p=p))
+            P = R.to_device(s.pos, ctx)
+            Q = R.to_device(s.q, ctx)
+            V = R.to_device(s.vel, ctx)
+            F = torch.zeros_like(P)
+            R.rbe_sample_k(ctx, 0)
+            R.rbe_kspace_forces(ctx, P, Q, F)
+            R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
+
+            def four(k):
+                R.rbe_sample_k(ctx, 1000 + k)
+                R.rbe_kspace_forces(ctx, P, Q, F)
+
+            four(0)
+            k_ms = _timed(torch, ctx.stream, four, 100)
+            kus = _kernel_us(R, ctx, four, 50)
+            R.rbe_step(ctx, P, V, Q, F, 1, 20)
+            st_ms = _timed(torch, ctx.stream, lambda k: R.rbe_step(ctx, P, V, Q, F, 21 + 100 * k, 100), 1) / 100
+            pairs = n * p
+            row = {"n": n, "p": p, "kspace_pairs_per_s": pairs * 1e3 / k_ms, "kspace_ms": k_ms,
+                   "md_steps_per_s": 1e3 / st_ms, "md_pairs_per_s": pairs * 1e3 / st_ms, "md_ms": st_ms,
+                   "stage": _frac(pairs * SLOTS_RHO, kus["stage"]), "kforce": _frac(pairs * SLOTS_FORCE, kus["kforce"])}
+            log(f"sweep n={n} p={p}: kspace {row['kspace_pairs_per_s']:.3e} pairs/s, "
+                f"step {1e3 * st_ms:.1f} us, stage {row['stage']['frac']}, kforce {row['kforce']['frac']}")
+            out.append(row)
+            del ctx, P, Q, V, F
+            torch.cuda.empty_cache()
+    return out
+
+
+def suite_batched(torch, R, W, log, steps=100):
+    """64 replicas, N ~ U[500, 20000], 10% divalent: one batched context
+    against a loop of 64 single-system contexts, same steps."""
+    systems = W.replica_systems()
+    params = [R.params_from_system(x, R.RBE_FP32) for x in systems]
+    ntot = sum(x.n for x in systems)
+    pairs = sum(x.n * x.p for x in systems)
+    bctx = R.rbe_batch_create(params)
+    cat = lambda a: np.concatenate(a, axis=-1)
+    P = R.to_device(cat([x.pos for x in systems]), bctx)
+    Q = R.to_device(cat([x.q for x in systems]), bctx)
+    V = R.to_device(cat([x.vel for x in systems]), bctx)
+    F = torch.zeros_like(P)
+    R.rbe_step(bctx, P, V, Q, F, 0, 10)
+    b_ms = _timed(torch, bctx.stream, lambda k: R.rbe_step(bctx, P, V, Q, F, 10, steps), 1) / steps
+    ctxs, st = [], []
+    for x, pr in zip(systems, params):
+        c = R.rbe_create(pr)
+        t = [R.to_device(x.pos, c), None, R.to_device(x.vel, c), None]
+        t[1] = R.to_device(x.q, c)
+        t[3] = torch.zeros_like(t[0])
+        R.rbe_step(c, t[0], t[2], t[1], t[3], 0, 10)
+        ctxs.append(c)
+        st.append(t)
+
+    def loop(k):
+        for c, t in zip(ctxs, st):
+            R.rbe_step(c, t[0], t[2], t[1], t[3], 10, steps)
+
+    l_ms = _timed(torch, ctxs[0].stream, loop, 1) / steps
+    row = {"replicas": len(systems), "particles": ntot, "pairs_per_step": pairs,
+           "batched": {"ms_per_step": b_ms, "steps_per_s": 1e3 / b_ms, "pairs_per_s": pairs * 1e3 / b_ms},
+           "loop": {"ms_per_step": l_ms, "steps_per_s": 1e3 / l_ms, "pairs_per_s": pairs * 1e3 / l_ms},
+           "speedup": l_ms / b_ms}
+    log(f"batched {b_ms * 1e3:.1f} us/step vs loop {l_ms * 1e3:.1f} us/step")
+    return row
+
+
+def suite_gradient(torch, R, W, log, reps=50):
+    """N = 30000 Gaussian charges, P = 200: forces forward only against
+    forward + backward of the force-matching loss (autograd over the adjoint)."""
+    from paper_2010_01559_amd.autograd import force_matching_loss, rbe_forces
+    s = W.gaussian_charge_system()
+    ctx = R.rbe_create(R.params_from_system(s, R.RBE_FP32))
+    P = R.to_device(s.pos, ctx).requires_grad_()
+    Q = R.to_device(s.q, ctx).requires_grad_()
+    R.rbe_sample_k(ctx, 5)
+    Fref = torch.zeros((3, s.n), dtype=P.dtype, device=P.device)
+
+    def fwd(k):
+        with torch.no_grad():
+            rbe_forces(ctx, P, Q)
+
+    def fwd_bwd(k):
+        P.grad = None
+        Q.grad = None
+        force_matching_loss(ctx, P, Q, Fref).backward()
+
+    fwd(0)
+    fwd_bwd(0)
+    f_ms = _timed(torch, ctx.stream, fwd, reps)
+    fb_ms = _timed(torch, ctx.stream, fwd_bwd, reps)
+    row = {"n": s.n, "p": s.p, "forward_ms": f_ms, "forward_backward_ms": fb_ms, "ratio": fb_ms / f_ms}
+    log(f"gradient: forward {f_ms * 1e3:.1f} us, forward+backward {fb_ms * 1e3:.1f} us")
+    return row
+
+
+def suite_ewald(torch, R, W, log, tol=1e-4):
+    """Classical Ewald (every mode with exp(-k^2/4 alpha) >= tol, same alpha
+    and r_c as the random batch) on the same kernels, against one random
+    batch evaluation (P = 100), at growing N and density 0.1."""
+    from paper_2010_01559_amd.ewald import ewald_modes, mode_radius2
+    out = []
+    for n in (1000, 3000, 10000, 30000):
+        s = W.scaling_system(n, 100)
+        ctx = R.rbe_create(R.params_from_system(s, R.RBE_FP32))
+        P = R.to_device(s.pos, ctx)
+        Q = R.to_device(s.q, ctx)
+        F = torch.zeros_like(P)
+        R.rbe_sample_k(ctx, 0)
+        rbe_ms = _timed(torch, ctx.stream, lambda k: (R.rbe_sample_k(ctx, k), R.rbe_kspace_forces(ctx, P, Q, F)),
+                        50)
+        real_ms = _timed(torch, ctx.stream, lambda k: R.rbe_real_forces(ctx, P, Q, F), 50)
+        m, w = ewald_modes(s.alpha, s.L, mode_radius2(s.alpha, s.L, tol))
+        R.rbe_reserve_modes(ctx, m.shape[1])
+        R.rbe_set_k(ctx, m, w)
+        R.rbe_kspace_forces(ctx, P, Q, F)
+        ew_ms = _timed(torch, ctx.stream, lambda k: R.rbe_kspace_forces(ctx, P, Q, F), 5)
+        row = {"n": n, "box": s.L, "ewald_modes": int(m.shape[1]), "ewald_kspace_ms": ew_ms,
+               "rbe_kspace_ms": rbe_ms, "real_space_ms": real_ms, "ewald_over_rbe": ew_ms / rbe_ms}
+        log(f"ewald n={n}: {m.shape[1]} modes {ew_ms:.3f} ms vs rbe {rbe_ms:.4f} ms")
+        out.append(row)
+        del ctx, P, Q, F
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_suite(path):
+    import torch
+
+    import paper_2010_01559_amd.rbe as R
+    from paper_2010_01559_amd import workloads as W
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    res = {"sweep": suite_np_sweep(torch, R, W, log)}
+    res["batched"] = suite_batched(torch, R, W, log)
+    res["gradient"] = suite_gradient(torch, R, W, log)
+    res["ewald"] = suite_ewald(torch, R, W, log)
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    log(f"suite written to {path}")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build runs on a "
               f"single MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.suite:
+        run_suite(args.suite)
+        return
     import torch
 
     import paper_2010_01559_amd.rbe as R
@@ -209,9 +396,10 @@ def main():
 
     n, p = s.n, s.p
     pairs = n * p
-    cand, nb = real_space_counts(s)
+    cand, nb = real_space_counts(s, params.skin)
+    # the force launch of a step also evaluates the Fourier force
     work = {"stage": pairs * SLOTS_RHO, "kforce": pairs * SLOTS_FORCE,
-            "real": cand * SLOTS_CHECK + nb * SLOTS_PAIR}
+            "real": cand * SLOTS_CHECK + nb * SLOTS_PAIR + pairs * SLOTS_FORCE}
     rooflines = {}
     for name, slots in work.items():
         if name not in kern:
@@ -260,7 +448,7 @@ def main():
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]} for k, v in kern.items()},
         "kspace_kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
                            for k, v in kkern.items()},
-        "real_space": {"candidate_pairs": cand, "pairs_in_cutoff": nb},
+        "real_space": {"list_entries": cand, "pairs_in_cutoff": nb},
         "roofline": roofline,
         "rooflines": rooflines,
         "fourier_only_rooflines": fourier,
