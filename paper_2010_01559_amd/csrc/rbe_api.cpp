@@ -833,12 +833,16 @@ static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, voi
     const bool drawn = !first && !c->any_mh;
     if (!drawn && !fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
     StageRequest rq{pos, vel, force, q, s, ks, 1, 0, (!drawn && fuse_sample) ? 1 : 0, 1, &ls};
+    // BAOAB: the closing half kick of a step is applied by the next step's
+    // integrator (the force pass would touch the velocities in scattered
+    // original order); only the last step of a call kicks in the force pass
+    rq.kick = !first && !andersen;
     RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
     const bool draw_next = !c->any_mh && !last;
     RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild, ls.rebuild_next, draw_next ? 1 : 0, ks + 1,
                              &ls));
     RUN(c, K_SCATTER, launch_rebuild(c->cfg, c->w, ls));
-    RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, andersen ? nullptr : vel));
+    RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, (andersen || !last) ? nullptr : vel));
     c->list_valid = true;
     ++c->list_gen;
     if (draw_next) {
@@ -937,14 +941,16 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
             refresh_cfg_modes(c);
             if ((s = upload_rho_tiles(c)) != RBE_OK) return s;
         }
-    // one step = four launches: [integrate + bin + draw modes + structure-factor
-    // partials] -> [totals + cell scan] -> [Fourier force + scatter] ->
-    // [real space + LJ + final half kick].  In list mode: [integrate + list
-    // bookkeeping + partials] -> [totals + next step's modes + binning] ->
-    // [cell scan + scatter] -> [Fourier + real space + LJ + final half kick],
-    // where binning, scan and scatter do work only on rebuild steps (decided
-    // on the device).  In list mode the steady-state steps of a call (after
-    // the first, before the last) are replayed in pairs from a graph.
+    // one step = four launches: [closing kick of the step before + integrate
+    // + bin + draw modes + structure-factor partials] -> [totals + cell scan]
+    // -> [Fourier force + scatter] -> [real space + LJ (+ the closing half
+    // kick on the last step of the call)].  In list mode: [closing kick +
+    // integrate + list bookkeeping + partials] -> [totals + next step's modes
+    // + binning] -> [cell scan + scatter] -> [Fourier + real space + LJ (+
+    // closing kick on the last step)], where binning, scan and scatter do
+    // work only on rebuild steps (decided on the device).  With graphs on, the
+    // steady-state steps of a call (after the first, before the last) are
+    // replayed from a captured graph.
     int table_lds = 0, tab_max = 0;
     const size_t lds = stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max);
     const bool fuse_sample = !c->any_mh && lds <= 64 * 1024;
@@ -971,10 +977,12 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
         } else {
             if (!fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
             StageRequest rq{pos, vel, force, q, s, ks, 1, 1, fuse_sample ? 1 : 0, 1};
+            rq.kick = t > 0 && !andersen;
             RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
             RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 1));
             RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, 0, 1));
-            RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, andersen ? nullptr : vel));
+            const bool last = t == nsteps - 1;
+            RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, (andersen || !last) ? nullptr : vel));
         }
         ++t;
     }

@@ -254,12 +254,16 @@ __device__ __forceinline__ void fourier_range(const KModeD *kk, int l0, int l1, 
 // for Andersen, the normal used when the particle collides (`hit`).
 template <typename T>
 __device__ __forceinline__ double integrate_comp(const SysDev &S, int d, int64_t i, int64_t ntot, T *pos, T *vel,
-                                                 const T *F, double xi, bool hit)
+                                                 const T *F, double xi, bool hit, bool kick)
 {
     const int64_t k = d * ntot + i;
     if (S.integrator == RBE_LANGEVIN_BAOAB) {
         const double h = 0.5 * S.dt;
-        double v = (double)vel[k] + h * (double)F[k] / S.mass;  // B
+        T v0 = vel[k];
+        // the previous step's closing half kick, rounded to T as if it had
+        // been stored by the force pass
+        if (kick) v0 = (T)fma(0.5 * S.dt / S.mass, (double)F[k], (double)v0);
+        double v = (double)v0 + h * (double)F[k] / S.mass;      // B
         double r = (double)pos[k] + h * v;                      // A
         v = S.c1 * v + S.c2 * xi;                               // O
         r += h * v;                                             // A
@@ -290,13 +294,13 @@ __device__ __forceinline__ bool andersen_hit(const SysDev &S, int il, uint64_t s
 
 template <typename T>
 __device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i, int64_t ntot, T *pos, T *vel,
-                                              const T *F, uint64_t step, double x[3])
+                                              const T *F, uint64_t step, bool kick, double x[3])
 {
     const bool hit = S.integrator == RBE_LANGEVIN_BAOAB ? false : andersen_hit(S, il, step);
     const bool noise = S.integrator == RBE_LANGEVIN_BAOAB || hit;
     for (int d = 0; d < 3; ++d) {
         const double xi = noise ? normal_t<T>((uint32_t)il, S.seed, step, d) : 0.0;
-        x[d] = integrate_comp<T>(S, d, i, ntot, pos, vel, F, xi, hit);
+        x[d] = integrate_comp<T>(S, d, i, ntot, pos, vel, F, xi, hit, kick);
     }
 }
 

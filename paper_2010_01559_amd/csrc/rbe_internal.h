@@ -185,6 +185,7 @@ struct StageRequest {
     uint64_t sample_step;  // mode sample index
     int integrate, bin, sample, rho;
     const ListStep *list;  // integrate in list mode: update cell-order records, test displacements
+    int kick = 0;          // integrate: first apply the previous step's final half kick (deferred)
 };
 
 // ---- launchers (rbe_kspace.hip, rbe_real.hip) ----

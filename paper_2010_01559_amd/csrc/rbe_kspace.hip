@@ -138,6 +138,7 @@ struct StageArgs {
     uint64_t step;         // integrator noise index
     uint64_t sample_step;  // mode sample index
     int do_integrate, do_bin, do_sample, table_lds, do_rho;
+    int kick;   // deferred closing half kick of the previous step
     int chunk;
     int tab_max;           // LDS doubles reserved for the table
     // neighbour-list mode of a time step
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         const int64_t i = S.off + il;
         double x[3];
         if (a.do_integrate) {
-            integrate_one<T>(S, il, i, a.ntot, a.pos, a.vel, a.F, step, x);
+            integrate_one<T>(S, il, i, a.ntot, a.pos, a.vel, a.F, step, a.kick != 0, x);
         } else {
             x[0] = (double)a.pos[i];
             x[1] = (double)a.pos[a.ntot + i];
@@ -1092,6 +1093,7 @@ static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const S
     a.step = rq.step;
     a.sample_step = rq.sample_step;
     a.do_integrate = rq.integrate;
+    a.kick = rq.kick;
     a.do_bin = rq.bin;
     a.do_sample = rq.sample;
     a.do_rho = rq.rho;

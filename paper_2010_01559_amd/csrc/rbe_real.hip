@@ -388,10 +388,11 @@ __device__ __forceinline__ void finish_particle(const RealArgs<T> &a, const SysD
     a.F[a.ntot + i] = fy;
     a.F[2 * a.ntot + i] = fz;
     if (a.vel) {
+        // the same rounding as the deferred kick of the integrator
         const double h = 0.5 * S.dt / S.mass;
-        a.vel[i] = (T)((double)a.vel[i] + h * (double)fx);
-        a.vel[a.ntot + i] = (T)((double)a.vel[a.ntot + i] + h * (double)fy);
-        a.vel[2 * a.ntot + i] = (T)((double)a.vel[2 * a.ntot + i] + h * (double)fz);
+        a.vel[i] = (T)fma(h, (double)fx, (double)a.vel[i]);
+        a.vel[a.ntot + i] = (T)fma(h, (double)fy, (double)a.vel[a.ntot + i]);
+        a.vel[2 * a.ntot + i] = (T)fma(h, (double)fz, (double)a.vel[2 * a.ntot + i]);
     }
 }
 
