@@ -534,7 +534,9 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     g.prec = c->prec;
     g.ntot = ntot;
     g.mcap = c->mcap;
-    g.rho_chunk = 512;
+    // one structure-factor block per compute unit when the particles allow:
+    // the block's registers leave room for one 1024-thread block per CU
+    g.rho_chunk = (int)std::min<int64_t>(512, std::max<int64_t>(64, ((ntot + 255) / 256 + 7) / 8 * 8));
     g.rho_block = 1024;
     g.force_split = 4;
     g.real_split = 4;
@@ -1124,8 +1126,8 @@ rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
     if (t->rho_block) n.rho_block = t->rho_block;
     if (t->force_split) n.force_split = t->force_split;
     if (t->real_split) n.real_split = t->real_split;
-    if (n.rho_chunk < 64 || n.rho_chunk > 2048 || (n.rho_chunk % 64))
-        return set_err(c, RBE_ERR_INVALID, "rho_chunk must be a multiple of 64 in [64, 2048]");
+    if (n.rho_chunk < 64 || n.rho_chunk > 2048 || (n.rho_chunk % 8))
+        return set_err(c, RBE_ERR_INVALID, "rho_chunk must be a multiple of 8 in [64, 2048]");
     if (n.rho_block != 256 && n.rho_block != 512 && n.rho_block != 1024)
         return set_err(c, RBE_ERR_INVALID, "rho_block must be 256, 512 or 1024");
     if (n.force_split != 1 && n.force_split != 2 && n.force_split != 4)
@@ -1176,7 +1178,8 @@ rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps
     rbe_get_tiles(c, &cur);
     rbe_tiles win = cur;
     float best_rho = 1e30f, best_f = 1e30f;
-    const int chunks[] = {128, 256, 512, 1024};
+    const int fill = (int)std::min<int64_t>(2048, std::max<int64_t>(64, ((c->ntot + 255) / 256 + 7) / 8 * 8));
+    const int chunks[] = {128, 256, 512, 1024, fill};
     const int blocks[] = {256, 512, 1024};
     rbe_status s = RBE_OK;
     for (int ch : chunks)
