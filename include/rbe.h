@@ -221,6 +221,17 @@ rbe_status rbe_forces_vjp(rbe_ctx *ctx, const void *pos, const void *q, const vo
  * or -1 when the context does not use the list.  Synchronises the stream. */
 rbe_status rbe_list_builds(rbe_ctx *ctx, int64_t *builds);
 
+/* Time step of every system from the next rbe_step on.  anneal = 0: the
+ * fixed step dt.  anneal > 0: the annealed burn-in schedule of Sec. 4.2
+ * (Example 2), where the step with index n (the step numbers rbe_step
+ * receives) uses dt_n = anneal / ln(1 + n), n taken as at least 1; the
+ * paper's burn-in uses anneal = 0.01 with the Andersen thermostat, then a
+ * fixed dt.  The schedule is evaluated on the device for every step (BAOAB
+ * coefficients and the Andersen collision probability nu dt_n included).
+ * RBE_ERR_INVALID for a negative or non-finite value.  Synchronises the
+ * stream. */
+rbe_status rbe_set_dt(rbe_ctx *ctx, double dt, double anneal);
+
 /* Graph replay of rbe_step (default off).  With a neighbour list and the
  * exact sampler, the steps of one rbe_step call after its first and before
  * its last are replayed 16 at a time from a captured hipGraph of their

@@ -499,6 +499,8 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         s.c1 = std::exp(-p.gamma * p.dt / p.mass);
         s.c2 = std::sqrt((1.0 - s.c1 * s.c1) * p.kT / p.mass);
         s.nu_dt = p.nu * p.dt;
+        s.nu = p.nu;
+        s.anneal = 0.0;
         s.seed = p.seed;
         // split of FP32 phases: |m| <= 2M must satisfy |m| < 2^(22 - hi_bits)
         {
@@ -844,7 +846,7 @@ static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, voi
     RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild, ls.rebuild_next, draw_next ? 1 : 0, ks + 1,
                              &ls));
     RUN(c, K_SCATTER, launch_rebuild(c->cfg, c->w, ls));
-    RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, (andersen || !last) ? nullptr : vel));
+    RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, (andersen || !last) ? nullptr : vel, s));
     c->list_valid = true;
     ++c->list_gen;
     if (draw_next) {
@@ -984,12 +986,30 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
             RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 1));
             RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, 0, 1));
             const bool last = t == nsteps - 1;
-            RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, (andersen || !last) ? nullptr : vel));
+            RUN(c, K_REAL, launch_real(c->cfg, c->w, force, 1, (andersen || !last) ? nullptr : vel, s));
         }
         ++t;
     }
     if (nsteps > 0) c->modes_valid = true;
     return RBE_OK;
+}
+
+rbe_status rbe_set_dt(rbe_ctx *c, double dt, double anneal)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (!std::isfinite(dt) || dt < 0.0) return set_err(c, RBE_ERR_INVALID, "dt must be finite and >= 0");
+    if (!std::isfinite(anneal) || anneal < 0.0) return set_err(c, RBE_ERR_INVALID, "anneal must be finite and >= 0");
+    for (int r = 0; r < c->R; ++r) {
+        rbe_params &p = c->prm[r];
+        SysDev &s = c->sysh[r];
+        p.dt = dt;
+        s.dt = dt;
+        s.c1 = std::exp(-p.gamma * dt / p.mass);
+        s.c2 = std::sqrt((1.0 - s.c1 * s.c1) * p.kT / p.mass);
+        s.nu_dt = p.nu * dt;
+        s.anneal = anneal;
+    }
+    return upload_sys(c);
 }
 
 rbe_status rbe_use_graphs(rbe_ctx *c, int32_t enable)

@@ -252,20 +252,30 @@ __device__ __forceinline__ void fourier_range(const KModeD *kk, int l0, int l1, 
 // ---------------------------------------------------------------------------
 // Component d of that update; xi is the component's normal (Langevin) or,
 // for Andersen, the normal used when the particle collides (`hit`).
+// Time step of the integrator step with index n: the fixed dt, or the
+// annealed burn-in schedule anneal / ln(1 + n) (Sec. 4.2, Example 2; n is
+// taken as at least 1).
+__device__ __forceinline__ double step_dt(const SysDev &S, uint64_t n)
+{
+    if (S.anneal <= 0.0) return S.dt;
+    return S.anneal / log1p(n < 1 ? 1.0 : (double)n);
+}
+
 template <typename T>
 __device__ __forceinline__ double integrate_comp(const SysDev &S, int d, int64_t i, int64_t ntot, T *pos, T *vel,
-                                                 const T *F, double xi, bool hit, bool kick)
+                                                 const T *F, double xi, bool hit, bool kick, double dt,
+                                                 double dt_prev, double c1, double c2)
 {
     const int64_t k = d * ntot + i;
     if (S.integrator == RBE_LANGEVIN_BAOAB) {
-        const double h = 0.5 * S.dt;
+        const double h = 0.5 * dt;
         T v0 = vel[k];
         // the previous step's closing half kick, rounded to T as if it had
         // been stored by the force pass
-        if (kick) v0 = (T)fma(0.5 * S.dt / S.mass, (double)F[k], (double)v0);
+        if (kick) v0 = (T)fma(0.5 * dt_prev / S.mass, (double)F[k], (double)v0);
         double v = (double)v0 + h * (double)F[k] / S.mass;      // B
         double r = (double)pos[k] + h * v;                      // A
-        v = S.c1 * v + S.c2 * xi;                               // O
+        v = c1 * v + c2 * xi;                                   // O
         r += h * v;                                             // A
         r -= S.L * floor(r * S.invL);
         T rs = (T)r;
@@ -275,8 +285,8 @@ __device__ __forceinline__ double integrate_comp(const SysDev &S, int d, int64_t
         return (double)rs;
     }
     const double sv = sqrt(S.kT / S.mass);
-    const double v = (double)vel[k] + S.dt * (double)F[k] / S.mass;
-    double r = (double)pos[k] + S.dt * v;
+    const double v = (double)vel[k] + dt * (double)F[k] / S.mass;
+    double r = (double)pos[k] + dt * v;
     r -= S.L * floor(r * S.invL);
     T rs = (T)r;
     if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
@@ -289,7 +299,7 @@ __device__ __forceinline__ double integrate_comp(const SysDev &S, int d, int64_t
 __device__ __forceinline__ bool andersen_hit(const SysDev &S, int il, uint64_t step)
 {
     const U4 w = draw((uint32_t)il, kTagAndersen, S.seed, step);
-    return (double)w.x * (1.0 / 4294967296.0) < S.nu_dt;
+    return (double)w.x * (1.0 / 4294967296.0) < (S.anneal > 0.0 ? S.nu * step_dt(S, step) : S.nu_dt);
 }
 
 template <typename T>
@@ -298,9 +308,15 @@ __device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i
 {
     const bool hit = S.integrator == RBE_LANGEVIN_BAOAB ? false : andersen_hit(S, il, step);
     const bool noise = S.integrator == RBE_LANGEVIN_BAOAB || hit;
+    const double dt = step_dt(S, step), dt_prev = kick ? step_dt(S, step - 1) : 0.0;
+    double c1 = S.c1, c2 = S.c2;
+    if (S.anneal > 0.0 && S.integrator == RBE_LANGEVIN_BAOAB) {
+        c1 = exp(-S.gamma * dt / S.mass);
+        c2 = sqrt((1.0 - c1 * c1) * S.kT / S.mass);
+    }
     for (int d = 0; d < 3; ++d) {
         const double xi = noise ? normal_t<T>((uint32_t)il, S.seed, step, d) : 0.0;
-        x[d] = integrate_comp<T>(S, d, i, ntot, pos, vel, F, xi, hit, kick);
+        x[d] = integrate_comp<T>(S, d, i, ntot, pos, vel, F, xi, hit, kick, dt, dt_prev, c1, c2);
     }
 }
 

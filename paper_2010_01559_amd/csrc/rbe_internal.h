@@ -44,6 +44,8 @@ struct SysDev {
     double kT, gamma, dt, mass;
     double c1, c2;          // Ornstein-Uhlenbeck factors exp(-gamma dt/m), sqrt((1-c1^2) kT/m)
     double nu_dt;           // Andersen collision probability per step
+    double nu;              // Andersen collision frequency
+    double anneal;          // > 0: the step of index n uses dt = anneal / ln(1 + n) instead of dt
     double rlist2;          // (largest cutoff + skin)^2
     double half_skin2;      // (skin / 2)^2
     uint64_t seed;
@@ -201,8 +203,10 @@ hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);
 hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step);
 hipError_t launch_rebuild(const LaunchCfg &c, const Workspace &w, const ListStep &ls);
-hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick);
-hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick);
+hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick,
+                            uint64_t kick_step = 0);
+hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick,
+                       uint64_t kick_step = 0);
 hipError_t launch_energy(const LaunchCfg &c, const Workspace &w, const void *q, const void *vel);
 hipError_t launch_vjp_reduce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q,
                              const void *gF);

@@ -348,6 +348,7 @@ struct RealArgs {
     int32_t *flag;
     double *epart;           // ENERGY: [tiles][8]
     const void *km;          // per-mode force constants (KModeF / KModeD) for the fused Fourier force
+    uint64_t kick_step;      // index of the step whose closing half kick is applied (its time step)
 };
 
 // Neighbour-list state seen by the real-space pass of a step.
@@ -389,7 +390,7 @@ __device__ __forceinline__ void finish_particle(const RealArgs<T> &a, const SysD
     a.F[2 * a.ntot + i] = fz;
     if (a.vel) {
         // the same rounding as the deferred kick of the integrator
-        const double h = 0.5 * S.dt / S.mass;
+        const double h = 0.5 * step_dt(S, a.kick_step) / S.mass;
         a.vel[i] = (T)fma(h, (double)fx, (double)a.vel[i]);
         a.vel[a.ntot + i] = (T)fma(h, (double)fy, (double)a.vel[a.ntot + i]);
         a.vel[2 * a.ntot + i] = (T)fma(h, (double)fz, (double)a.vel[2 * a.ntot + i]);
@@ -950,9 +951,10 @@ hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep
 
 template <typename T>
 static RealArgs<T> real_args(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel,
-                             const void *q)
+                             const void *q, uint64_t kick_step = 0)
 {
     RealArgs<T> a;
+    a.kick_step = kick_step;
     a.sys = w.sys;
     a.tiles = w.real_tiles;
     a.start = w.cell_start;
@@ -970,14 +972,15 @@ static RealArgs<T> real_args(const LaunchCfg &c, const Workspace &w, void *force
     return a;
 }
 
-hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick)
+hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick,
+                       uint64_t kick_step)
 {
     if (c.prec == RBE_FP64)
         k_real_rows<double, false><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
-            real_args<double>(c, w, force, accumulate, vel_kick, nullptr));
+            real_args<double>(c, w, force, accumulate, vel_kick, nullptr, kick_step));
     else
         k_real_rows<float, false><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
-            real_args<float>(c, w, force, accumulate, vel_kick, nullptr));
+            real_args<float>(c, w, force, accumulate, vel_kick, nullptr, kick_step));
     return hipGetLastError();
 }
 
@@ -1007,7 +1010,8 @@ static void real_step_dispatch(const LaunchCfg &c, const RealArgs<T> &a, const L
     }
 }
 
-hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick)
+hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick,
+                            uint64_t kick_step)
 {
     ListArgs la;
     la.ls = ls;
@@ -1018,9 +1022,9 @@ hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListSt
     la.nnb = w.nnb;
     la.kmax = c.kmax;
     if (c.prec == RBE_FP64)
-        real_step_dispatch<double>(c, real_args<double>(c, w, force, 0, vel_kick, nullptr), la);
+        real_step_dispatch<double>(c, real_args<double>(c, w, force, 0, vel_kick, nullptr, kick_step), la);
     else
-        real_step_dispatch<float>(c, real_args<float>(c, w, force, 0, vel_kick, nullptr), la);
+        real_step_dispatch<float>(c, real_args<float>(c, w, force, 0, vel_kick, nullptr, kick_step), la);
     return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ STATUS_NAMES = {0: "RBE_OK", -1: "RBE_ERR_INVALID", -2: "RBE_ERR_NOT_NEUTRAL", -
 EXPORTED = ["rbe_normalizer", "rbe_create", "rbe_batch_create", "rbe_destroy", "rbe_last_error",
             "rbe_num_systems", "rbe_num_particles", "rbe_num_modes", "rbe_sample_k", "rbe_set_k",
             "rbe_reserve_modes", "rbe_kspace_forces", "rbe_real_forces", "rbe_step", "rbe_batch_step",
-            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_use_graphs", "rbe_get_tiles",
+            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_set_dt", "rbe_use_graphs", "rbe_get_tiles",
             "rbe_set_tiles", "rbe_autotune", "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name",
             "rbe_profile_count"]
 
@@ -110,6 +110,7 @@ def lib():
     L.rbe_forces_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32]
     L.rbe_list_builds.argtypes = [vp, C.POINTER(i64)]
     L.rbe_use_graphs.argtypes = [vp, i32]
+    L.rbe_set_dt.argtypes = [vp, C.c_double, C.c_double]
     L.rbe_get_tiles.argtypes = [vp, C.POINTER(rbe_tiles)]
     L.rbe_set_tiles.argtypes = [vp, C.POINTER(rbe_tiles)]
     L.rbe_autotune.argtypes = [vp, vp, vp, i32, C.POINTER(rbe_tiles)]
@@ -346,6 +347,13 @@ def rbe_list_builds(ctx):
     v = C.c_int64()
     _check(lib().rbe_list_builds(ctx.handle, C.byref(v)), ctx.handle)
     return v.value
+
+
+def rbe_set_dt(ctx, dt, anneal=0.0):
+    """Fixed time step dt, or (anneal > 0) the burn-in schedule dt_n = anneal / ln(1 + n)."""
+    _check(lib().rbe_set_dt(ctx.handle, float(dt), float(anneal)), ctx.handle)
+    for p in ctx.params:
+        p.dt = float(dt)
 
 
 def rbe_use_graphs(ctx, enable):
