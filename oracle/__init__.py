@@ -113,6 +113,16 @@ def lib():
                                         C.c_int, _dp, _dp]
         L.oracle_kinetic_energy.restype = C.c_double
         L.oracle_kinetic_energy.argtypes = [C.c_int, _dp, C.c_double]
+        L.oracle_pair_virial.restype = None
+        L.oracle_pair_virial.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]
+        L.oracle_kspace_virial.restype = C.c_double
+        L.oracle_kspace_virial.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_int, _ip, _dp,
+                                           C.c_double]
+        L.oracle_pair_histogram.restype = None
+        L.oracle_pair_histogram.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_int,
+                                            np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")]
     return _lib
 
 
@@ -306,3 +316,26 @@ def forces_vjp(pos, q, L, alpha, rc, modes, weight, gF, coulomb=1.0, lj=(0.0, 1.
 def kinetic_energy(vel, mass=1.0):
     vel = _f64(vel)
     return lib().oracle_kinetic_energy(vel.shape[1], vel, mass)
+
+
+# -- observables (Sec. 4.1, eq. 4.3; charge-charge correlation) --------------------
+
+def pair_virial(pos, q, L, alpha, rc, coulomb=1.0, lj=(0.0, 1.0, 2.5)):
+    """(real-space Coulomb, LJ) sums over unordered pairs of r_ij . F_ij."""
+    wr, wl = C.c_double(), C.c_double()
+    lib().oracle_pair_virial(_f64(q).shape[0], _f64(pos), _f64(q), L, alpha, rc, coulomb, lj[0], lj[1], lj[2],
+                             C.byref(wr), C.byref(wl))
+    return wr.value, wl.value
+
+
+def kspace_virial(pos, q, L, alpha, modes, weight, coulomb=1.0):
+    """Fourier part of the pair sum of r_ij . F_ij for a weighted mode list."""
+    pos, q, modes, weight = _f64(pos), _f64(q), _i32(modes), _f64(weight)
+    return lib().oracle_kspace_virial(q.shape[0], pos, q, L, alpha, modes.shape[1], modes, weight, coulomb)
+
+
+def pair_histogram(pos, q, L, r_max, nbins):
+    """[3, nbins] int64 counts of pairs i < j by bin and class (++, +-, --)."""
+    counts = np.zeros((3, nbins), np.int64)
+    lib().oracle_pair_histogram(_f64(q).shape[0], _f64(pos), _f64(q), L, r_max, nbins, counts)
+    return counts

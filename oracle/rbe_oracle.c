@@ -803,3 +803,92 @@ double oracle_kinetic_energy(int n, const double *vel, double mass)
     for (int k = 0; k < 3 * n; ++k) e += 0.5 * mass * vel[k] * vel[k];
     return e;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Observables of Sec. 4.1 (eq. 4.3): the pair virial and its Fourier part,  */
+/* and pair-distance counts for the charge-charge correlation.               */
+/* ------------------------------------------------------------------------ */
+
+/* Sum over unordered pairs (all periodic images within the cutoffs) of
+ * r_ij . F_ij with r_ij = r_j - r_i and F_ij the force of j on i, for the
+ * real-space Coulomb part (returned in *w_real) and the shifted LJ part
+ * (*w_lj).  Eq. (4.3) uses half of this sum. */
+void oracle_pair_virial(int n, const double *pos, const double *q, double L, double alpha, double rc,
+                        double coulomb, double lj_eps, double lj_sigma, double lj_rc, double *w_real, double *w_lj)
+{
+    double rmax = rc > lj_rc ? rc : lj_rc;
+    int nimg = rmax < 0.5 * L ? 0 : (int)ceil(rmax / L) + 1;
+    double wr = 0.0, wl = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double dx0 = pos[j] - pos[i], dy0 = pos[n + j] - pos[n + i], dz0 = pos[2 * n + j] - pos[2 * n + i];
+            dx0 -= L * floor(dx0 / L + 0.5);
+            dy0 -= L * floor(dy0 / L + 0.5);
+            dz0 -= L * floor(dz0 / L + 0.5);
+            for (int a = -nimg; a <= nimg; ++a)
+                for (int b = -nimg; b <= nimg; ++b)
+                    for (int c = -nimg; c <= nimg; ++c) {
+                        if (j == i && a == 0 && b == 0 && c == 0) continue;
+                        double dx = dx0 + a * L, dy = dy0 + b * L, dz = dz0 + c * L;
+                        double r = sqrt(dx * dx + dy * dy + dz * dz);
+                        /* F_ij = -coulomb q_i q_j G(r) r_ij / r, so r_ij . F_ij = -coulomb q_i q_j G(r) r */
+                        if (r <= rc) wr += 0.5 * (-coulomb * q[i] * q[j] * orc_G(r, alpha) * r);
+                        if (lj_eps != 0.0 && r < lj_rc) {
+                            double V, dV;
+                            orc_lj(r, lj_eps, lj_sigma, lj_rc, &V, &dV);
+                            /* F_ij = dV/dr r_ij / r: r_ij . F_ij = r dV/dr */
+                            wl += 0.5 * r * dV;
+                        }
+                    }
+        }
+    *w_real = wr;
+    *w_lj = wl;
+}
+
+/* Fourier part of the same sum for the mode list with weights w_l: each mode
+ * contributes e_l (2 pi^2 |m|^2 / (alpha L^2) - 1), where e_l is its energy
+ * term coulomb w_l |rho_l|^2 / (2 pi L |m|^2) (the volume derivative of
+ * eq. 2.6's Fourier sum at fixed scaled positions, in the sign convention of
+ * the pair sum above). */
+double oracle_kspace_virial(int n, const double *pos, const double *q, double L, double alpha, int nm,
+                            const int32_t *modes, const double *weight, double coulomb)
+{
+    double *re = (double *)malloc(sizeof(double) * nm);
+    double *im = (double *)malloc(sizeof(double) * nm);
+    oracle_rho(n, pos, q, L, nm, modes, re, im);
+    double w = 0.0;
+    for (int l = 0; l < nm; ++l) {
+        double m2 = (double)modes[l] * modes[l] + (double)modes[nm + l] * modes[nm + l] +
+                    (double)modes[2 * nm + l] * modes[2 * nm + l];
+        double e = coulomb * weight[l] * (re[l] * re[l] + im[l] * im[l]) / (2.0 * ORC_PI * L * m2);
+        w += e * (2.0 * ORC_PI * ORC_PI * m2 / (alpha * L * L) - 1.0);
+    }
+    free(re);
+    free(im);
+    return w;
+}
+
+/* Counts of unordered pairs i < j (minimum image, r_max <= L/2) by distance
+ * bin of width dr = r_max / nbins and by charge class: 0 both q > 0, 1 one
+ * of each, 2 both q <= 0.  counts is [3][nbins], added to.  The bin of a
+ * pair is the largest b with (b dr)^2 <= r^2 (computed from r^2 with fused
+ * multiply-adds), so that the decision rests on correctly rounded operations
+ * only; pairs with r >= r_max are not counted. */
+void oracle_pair_histogram(int n, const double *pos, const double *q, double L, double r_max, int nbins,
+                           int64_t *counts)
+{
+    double dr = r_max / nbins;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double dx = pos[j] - pos[i], dy = pos[n + j] - pos[n + i], dz = pos[2 * n + j] - pos[2 * n + i];
+            dx -= L * rint(dx / L);
+            dy -= L * rint(dy / L);
+            dz -= L * rint(dz / L);
+            double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            int b = 0;
+            while (b < nbins && ((b + 1) * dr) * ((b + 1) * dr) <= r2) ++b;
+            if (b >= nbins) continue;
+            int cls = 2 - ((q[i] > 0.0) + (q[j] > 0.0));
+            counts[(int64_t)cls * nbins + b] += 1;
+        }
+}
