@@ -59,7 +59,7 @@ enum { RBE_FP32 = 0, RBE_FP64 = 1 };
 enum { RBE_LANGEVIN_BAOAB = 0, RBE_LEAPFROG_ANDERSEN = 1 };
 
 /* Mode sampler. */
-enum { RBE_SAMPLER_EXACT = 0, RBE_SAMPLER_MH = 1 };
+enum { RBE_SAMPLER_EXACT = 0, RBE_SAMPLER_MH = 1, RBE_SAMPLER_FIXED = 2 };
 
 /* Parts selector for rbe_forces_vjp. */
 enum { RBE_PART_KSPACE = 1, RBE_PART_REAL = 2, RBE_PART_ALL = 3 };
@@ -91,7 +91,10 @@ typedef struct rbe_params {
     uint64_t seed;       /* key of the counter-based generator */
     int32_t precision;   /* RBE_FP32 or RBE_FP64 (all systems of a batch alike) */
     int32_t integrator;  /* RBE_LANGEVIN_BAOAB or RBE_LEAPFROG_ANDERSEN */
-    int32_t sampler;     /* RBE_SAMPLER_EXACT or RBE_SAMPLER_MH */
+    int32_t sampler;     /* RBE_SAMPLER_EXACT, RBE_SAMPLER_MH, or RBE_SAMPLER_FIXED: rbe_step keeps
+                            the active list of rbe_set_k / rbe_sample_k every step instead of drawing
+                            a new batch (with the classical Ewald list of rbe_set_k: Ewald dynamics on
+                            the same kernels); single-system contexts only */
     int32_t flags;       /* reserved, 0 */
 } rbe_params;
 
@@ -104,6 +107,10 @@ typedef struct rbe_energy_t {
     double e_lj;       /* shifted LJ energy (eq. 4.1) */
     double e_kin;      /* sum m |v_i|^2 / 2 (0 when vel is NULL) */
     double virial;     /* sum over real-space and LJ pairs of r_ij . F_ij (pair part of eq. 4.3) */
+    double virial_kspace; /* Fourier part of the same sum on the active modes: sum over modes of
+                          e_l (2 pi^2 |m_l|^2 / (alpha L^2) - 1), e_l the mode's term of e_kspace
+                          (scaling derivative of the Fourier sum); eq. 4.3 uses
+                          vir = (virial + virial_kspace) / 2 */
     double charge_sum; /* sum q_i, for the neutrality check */
     int32_t nonfinite; /* non-zero if any kernel met a non-finite force since the last call */
     int32_t reserved;
@@ -231,6 +238,19 @@ rbe_status rbe_list_builds(rbe_ctx *ctx, int64_t *builds);
  * RBE_ERR_INVALID for a negative or non-finite value.  Synchronises the
  * stream. */
 rbe_status rbe_set_dt(rbe_ctx *ctx, double dt, double anneal);
+
+/* Pair-distance counts of every system (Sec. 4.1: the pair correlations
+ * g_++, g_+- behind the charge-charge correlation rho(r) = g_++ - g_+-).
+ * Adds to counts (device, int64 [R][3][nbins]) the number of pairs i < j of
+ * each system at minimum-image distance r < r_max, in bin floor(r / dr) with
+ * dr = r_max / nbins (decided exactly: the largest b with (b dr)^2 <= r^2,
+ * r^2 from the wrapped displacement with fused multiply-adds in FP64), by
+ * class: 0 both q > 0, 1 one of each sign, 2 both q <= 0.  pos, q: the
+ * context's precision, original order.  All pairs are visited (O(N^2) per
+ * system): an analysis call, not a time-step kernel.  RBE_ERR_INVALID unless
+ * 0 < r_max <= L/2 for every system and 1 <= nbins <= 4096.  Asynchronous. */
+rbe_status rbe_pair_histogram(rbe_ctx *ctx, const void *pos, const void *q, double r_max, int32_t nbins,
+                              int64_t *counts);
 
 /* Graph replay of rbe_step (default off).  With a neighbour list and the
  * exact sampler, the steps of one rbe_step call after its first and before

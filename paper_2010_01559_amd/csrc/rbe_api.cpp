@@ -107,7 +107,8 @@ rbe_status validate(const rbe_params &p, std::string &err)
     if (p.precision != RBE_FP32 && p.precision != RBE_FP64) return err = "unknown precision", RBE_ERR_INVALID;
     if (p.integrator != RBE_LANGEVIN_BAOAB && p.integrator != RBE_LEAPFROG_ANDERSEN)
         return err = "unknown integrator", RBE_ERR_INVALID;
-    if (p.sampler != RBE_SAMPLER_EXACT && p.sampler != RBE_SAMPLER_MH) return err = "unknown sampler", RBE_ERR_INVALID;
+    if (p.sampler != RBE_SAMPLER_EXACT && p.sampler != RBE_SAMPLER_MH && p.sampler != RBE_SAMPLER_FIXED)
+        return err = "unknown sampler", RBE_ERR_INVALID;
     if (p.flags != 0) return err = "flags must be 0", RBE_ERR_INVALID;
     const double H = normaliser_H(p.alpha, p.box);
     if (1.0 / (H * H * H) > 0.5)
@@ -141,6 +142,7 @@ struct rbe_ctx {
     bool list_valid = false;       // the neighbour list matches the cell order in `sorted`
     uint64_t list_gen = 0;         // steps taken in list mode (selects the rebuild flag)
     bool any_mh = false;
+    bool fixed = false;            // rbe_step keeps the active mode list
     LaunchCfg cfg{};
     Workspace w{};
     size_t partial_cap = 0;        // doubles allocated for partial
@@ -520,11 +522,17 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         }
         c->sysh.push_back(s);
         if (p.sampler == RBE_SAMPLER_MH) c->any_mh = true;
+        if (p.sampler == RBE_SAMPLER_FIXED) c->fixed = true;
         off += p.n;
         moff += p.p;
         cell_off += (s.ncell + 3) & ~3;
         max_cells = std::max(max_cells, s.ncell);
         max_table = std::max(max_table, 2 * s.M + 1);
+    }
+    if (c->fixed && R != 1) {
+        g_create_error = "the fixed sampler needs a single-system context";
+        delete c;
+        return RBE_ERR_INVALID;
     }
     c->mcap = moff;
     refresh_cfg_modes(c);
@@ -834,7 +842,7 @@ static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, voi
     // the staging launch integrates (in particle order); the modes of every
     // step after the first of a call were drawn by the totals launch of the
     // step before (exact sampler)
-    const bool drawn = !first && !c->any_mh;
+    const bool drawn = c->fixed || (!first && !c->any_mh);
     if (!drawn && !fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
     StageRequest rq{pos, vel, force, q, s, ks, 1, 0, (!drawn && fuse_sample) ? 1 : 0, 1, &ls};
     // BAOAB: the closing half kick of a step is applied by the next step's
@@ -842,7 +850,7 @@ static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, voi
     // original order); only the last step of a call kicks in the force pass
     rq.kick = !first && !andersen;
     RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
-    const bool draw_next = !c->any_mh && !last;
+    const bool draw_next = !c->any_mh && !c->fixed && !last;
     RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild, ls.rebuild_next, draw_next ? 1 : 0, ks + 1,
                              &ls));
     RUN(c, K_SCATTER, launch_rebuild(c->cfg, c->w, ls));
@@ -936,7 +944,9 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
     for (int r = 1; r < c->R; ++r)
         if ((c->prm[r].integrator == RBE_LEAPFROG_ANDERSEN) != andersen)
             return set_err(c, RBE_ERR_INVALID, "all systems of a batch must use one integrator");
-    for (int r = 0; r < c->R; ++r)
+    if (c->fixed && !c->modes_valid)
+        return set_err(c, RBE_ERR_STATE, "fixed sampler: set the modes with rbe_set_k or rbe_sample_k first");
+    for (int r = 0; r < c->R && !c->fixed; ++r)
         if (c->sysh[r].p != c->prm[r].p) {
             // explicit modes were set: stepping resamples, so restore p
             c->sysh[r].p = c->prm[r].p;
@@ -979,8 +989,8 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
                                       nullptr, 0);
             if (st != RBE_OK) return st;
         } else {
-            if (!fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
-            StageRequest rq{pos, vel, force, q, s, ks, 1, 1, fuse_sample ? 1 : 0, 1};
+            if (!c->fixed && !fuse_sample) RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, ks, c->any_mh ? 1 : 0));
+            StageRequest rq{pos, vel, force, q, s, ks, 1, 1, (!c->fixed && fuse_sample) ? 1 : 0, 1};
             rq.kick = t > 0 && !andersen;
             RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
             RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 1));
@@ -991,6 +1001,20 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
         ++t;
     }
     if (nsteps > 0) c->modes_valid = true;
+    return RBE_OK;
+}
+
+rbe_status rbe_pair_histogram(rbe_ctx *c, const void *pos, const void *q, double r_max, int32_t nbins,
+                              int64_t *counts)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (!pos || !q || !counts) return set_err(c, RBE_ERR_INVALID, "pos, q and counts must be non-NULL");
+    if (nbins < 1 || nbins > 4096) return set_err(c, RBE_ERR_INVALID, "nbins must be in [1, 4096]");
+    if (!std::isfinite(r_max) || r_max <= 0.0) return set_err(c, RBE_ERR_INVALID, "r_max must be > 0");
+    for (int r = 0; r < c->R; ++r)
+        if (r_max > 0.5 * c->sysh[r].L)
+            return set_err(c, RBE_ERR_INVALID, fmt("r_max %.6g exceeds half the box of system %d", r_max, r));
+    RUN(c, K_MISC, launch_pair_hist(c->cfg, c->w, pos, q, r_max, nbins, counts));
     return RBE_OK;
 }
 
@@ -1056,17 +1080,21 @@ rbe_status rbe_energy(rbe_ctx *c, const void *pos, const void *q, const void *ve
     rbe_status ret = RBE_OK;
     for (int r = 0; r < c->R; ++r) {
         const SysDev &S = c->sysh[r];
-        double ek = 0.0;
+        double ek = 0.0, wk = 0.0;
         for (int l = 0; l < S.p; ++l) {
             const int o = S.moff + l;
             const double mx = modes[o], my = modes[c->mcap + o], mz = modes[2 * (size_t)c->mcap + o];
             const double m2 = mx * mx + my * my + mz * mz;
             const double rr = rho[2 * o] * rho[2 * o] + rho[2 * o + 1] * rho[2 * o + 1];
             // (2 pi/(V k^2)) |rho|^2 with k = 2 pi m/L  ==  |rho|^2 / (2 pi L |m|^2)
-            ek += wts[o] * rr / (2.0 * kPi * S.L * m2);
+            const double el = wts[o] * rr / (2.0 * kPi * S.L * m2);
+            ek += el;
+            // lambda dE/dlambda under r -> lambda r, L -> lambda L at fixed alpha
+            wk += el * (2.0 * kPi * kPi * m2 / (S.alpha * S.L * S.L) - 1.0);
         }
         rbe_energy_t &e = out[r];
         e.e_kspace = S.coulomb * ek;
+        e.virial_kspace = S.coulomb * wk;
         e.e_self = -S.coulomb * std::sqrt(S.alpha / kPi) * acc[8 * r + 4];
         e.e_real = acc[8 * r + 0];
         e.e_lj = acc[8 * r + 1];

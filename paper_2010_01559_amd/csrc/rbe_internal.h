@@ -202,6 +202,8 @@ hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos
                          int accumulate, int scatter, const int32_t *bin_gate = nullptr);
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);
 hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step);
+hipError_t launch_pair_hist(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, double r_max,
+                            int nbins, int64_t *counts);
 hipError_t launch_rebuild(const LaunchCfg &c, const Workspace &w, const ListStep &ls);
 hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick,
                             uint64_t kick_step = 0);

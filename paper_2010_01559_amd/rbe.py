@@ -32,7 +32,7 @@ RBE_ERR_STATE = -7
 RBE_ERR_NO_DEVICE = -8
 RBE_FP32, RBE_FP64 = 0, 1
 RBE_LANGEVIN_BAOAB, RBE_LEAPFROG_ANDERSEN = 0, 1
-RBE_SAMPLER_EXACT, RBE_SAMPLER_MH = 0, 1
+RBE_SAMPLER_EXACT, RBE_SAMPLER_MH, RBE_SAMPLER_FIXED = 0, 1, 2
 RBE_PART_KSPACE, RBE_PART_REAL, RBE_PART_ALL = 1, 2, 3
 
 STATUS_NAMES = {0: "RBE_OK", -1: "RBE_ERR_INVALID", -2: "RBE_ERR_NOT_NEUTRAL", -3: "RBE_ERR_CUTOFF",
@@ -43,7 +43,7 @@ STATUS_NAMES = {0: "RBE_OK", -1: "RBE_ERR_INVALID", -2: "RBE_ERR_NOT_NEUTRAL", -
 EXPORTED = ["rbe_normalizer", "rbe_create", "rbe_batch_create", "rbe_destroy", "rbe_last_error",
             "rbe_num_systems", "rbe_num_particles", "rbe_num_modes", "rbe_sample_k", "rbe_set_k",
             "rbe_reserve_modes", "rbe_kspace_forces", "rbe_real_forces", "rbe_step", "rbe_batch_step",
-            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_set_dt", "rbe_use_graphs", "rbe_get_tiles",
+            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_pair_histogram", "rbe_set_dt", "rbe_use_graphs", "rbe_get_tiles",
             "rbe_set_tiles", "rbe_autotune", "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name",
             "rbe_profile_count"]
 
@@ -64,7 +64,8 @@ class rbe_params(C.Structure):
 
 class rbe_energy_t(C.Structure):
     _fields_ = [("e_kspace", C.c_double), ("e_self", C.c_double), ("e_real", C.c_double), ("e_lj", C.c_double),
-                ("e_kin", C.c_double), ("virial", C.c_double), ("charge_sum", C.c_double),
+                ("e_kin", C.c_double), ("virial", C.c_double), ("virial_kspace", C.c_double),
+                ("charge_sum", C.c_double),
                 ("nonfinite", C.c_int32), ("reserved", C.c_int32)]
 
 
@@ -111,6 +112,7 @@ def lib():
     L.rbe_list_builds.argtypes = [vp, C.POINTER(i64)]
     L.rbe_use_graphs.argtypes = [vp, i32]
     L.rbe_set_dt.argtypes = [vp, C.c_double, C.c_double]
+    L.rbe_pair_histogram.argtypes = [vp, vp, vp, C.c_double, i32, vp]
     L.rbe_get_tiles.argtypes = [vp, C.POINTER(rbe_tiles)]
     L.rbe_set_tiles.argtypes = [vp, C.POINTER(rbe_tiles)]
     L.rbe_autotune.argtypes = [vp, vp, vp, i32, C.POINTER(rbe_tiles)]
@@ -347,6 +349,14 @@ def rbe_list_builds(ctx):
     v = C.c_int64()
     _check(lib().rbe_list_builds(ctx.handle, C.byref(v)), ctx.handle)
     return v.value
+
+
+def rbe_pair_histogram(ctx, pos, q, r_max, nbins, counts):
+    """Adds pair counts to counts (device int64 [R, 3, nbins]; classes ++, +-, --)."""
+    torch = _torch()
+    cp = _ptr(counts, ctx, (ctx.R, 3, int(nbins)), torch.int64, "counts")
+    _check(lib().rbe_pair_histogram(ctx.handle, _vec3(ctx, pos, "pos"), _scal(ctx, q, "q"), float(r_max),
+                                    int(nbins), cp), ctx.handle)
 
 
 def rbe_set_dt(ctx, dt, anneal=0.0):
