@@ -871,9 +871,9 @@ double oracle_kspace_virial(int n, const double *pos, const double *q, double L,
 /* Counts of unordered pairs i < j (minimum image, r_max <= L/2) by distance
  * bin of width dr = r_max / nbins and by charge class: 0 both q > 0, 1 one
  * of each, 2 both q <= 0.  counts is [3][nbins], added to.  The bin of a
- * pair is the largest b with (b dr)^2 <= r^2 (computed from r^2 with fused
- * multiply-adds), so that the decision rests on correctly rounded operations
- * only; pairs with r >= r_max are not counted. */
+ * pair is the largest b with (b dr)^2 <= r^2 (the wrap and r^2 written with
+ * fused multiply-adds), so that the decision rests on correctly rounded
+ * operations only; pairs with r >= r_max are not counted. */
 void oracle_pair_histogram(int n, const double *pos, const double *q, double L, double r_max, int nbins,
                            int64_t *counts)
 {
@@ -881,9 +881,9 @@ void oracle_pair_histogram(int n, const double *pos, const double *q, double L, 
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j) {
             double dx = pos[j] - pos[i], dy = pos[n + j] - pos[n + i], dz = pos[2 * n + j] - pos[2 * n + i];
-            dx -= L * rint(dx / L);
-            dy -= L * rint(dy / L);
-            dz -= L * rint(dz / L);
+            dx = fma(-L, rint(dx / L), dx);
+            dy = fma(-L, rint(dy / L), dy);
+            dz = fma(-L, rint(dz / L), dz);
             double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             int b = 0;
             while (b < nbins && ((b + 1) * dr) * ((b + 1) * dr) <= r2) ++b;
