@@ -268,8 +268,8 @@ def suite_ewald(torch, R, W, log, tol=1e-4):
     batch evaluation (P = 100), at growing N and density 0.1."""
     from paper_2010_01559_amd.ewald import ewald_modes, mode_radius2
     out = []
-    for n in (1000, 3000, 10000, 30000):
-        s = W.scaling_system(n, 100)
+    for n in (1000, 3000, 10000, 30000, 100000):
+        s = W.metric_system() if n == 100000 else W.scaling_system(n, 100)
         ctx = R.rbe_create(R.params_from_system(s, R.RBE_FP32))
         P = R.to_device(s.pos, ctx)
         Q = R.to_device(s.q, ctx)
@@ -284,7 +284,8 @@ def suite_ewald(torch, R, W, log, tol=1e-4):
         R.rbe_kspace_forces(ctx, P, Q, F)
         ew_ms = _timed(torch, ctx.stream, lambda k: R.rbe_kspace_forces(ctx, P, Q, F), 5)
         row = {"n": n, "box": s.L, "ewald_modes": int(m.shape[1]), "ewald_kspace_ms": ew_ms,
-               "rbe_kspace_ms": rbe_ms, "real_space_ms": real_ms, "ewald_over_rbe": ew_ms / rbe_ms}
+               "ewald_pairs_per_s": n * m.shape[1] * 1e3 / ew_ms, "rbe_kspace_ms": rbe_ms,
+               "real_space_ms": real_ms, "ewald_over_rbe": ew_ms / rbe_ms}
         log(f"ewald n={n}: {m.shape[1]} modes {ew_ms:.3f} ms vs rbe {rbe_ms:.4f} ms")
         out.append(row)
         del ctx, P, Q, F

@@ -721,8 +721,15 @@ rbe_status rbe_reserve_modes(rbe_ctx *c, int32_t cap)
         c->modes_valid = false;
         return s;
     }
-    c->partial_cap = partial_need(c, 64);
+    // sized for the current chunk (a long list at a small chunk would need
+    // tiles x cap partials); rbe_set_tiles refuses smaller chunks afterwards
+    c->partial_cap = partial_need(c, c->cfg.rho_chunk);
     if ((s = swap_alloc((void **)&c->w.partial, sizeof(double) * c->partial_cap)) != RBE_OK) return s;
+    if (cap > 1024) {
+        // partial forces of mode-split force passes
+        const size_t esz = c->prec == RBE_FP64 ? sizeof(double) : sizeof(float);
+        if ((s = swap_alloc(&c->w.fpart, esz * 3 * (size_t)kMaxModeSplit * c->ntot)) != RBE_OK) return s;
+    }
     c->modes_valid = false;
     refresh_cfg_modes(c);
     return upload_rho_tiles(c);
@@ -788,12 +795,25 @@ rbe_status rbe_set_k(rbe_ctx *c, const int32_t *modes, int32_t nm, const double 
 
 // Structure factors of pos with the active modes (one staging launch and
 // the reduction), then the force pass when force is given.
+// Long mode lists (classical Ewald) are split over blocks so that a launch
+// holds a few blocks per compute unit even for small N.
+static int mode_split(int blocks, int modes, int modes_per_part)
+{
+    if (blocks >= 512) return 1;
+    const int want = (512 + blocks - 1) / blocks;
+    const int most = (modes + modes_per_part - 1) / modes_per_part;
+    return std::max(1, std::min(std::min(want, most), kMaxModeSplit));
+}
+
 static rbe_status kspace_impl(rbe_ctx *c, const void *pos, const void *q, void *force, int accumulate)
 {
     StageRequest rq{const_cast<void *>(pos), nullptr, nullptr, q, 0, 0, 0, 0, 0, 1};
+    rq.mode_split = mode_split(c->cfg.n_rho_tiles, c->max_p, 256);
     RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
     RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0));
-    if (force) RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, accumulate, 0));
+    const int fblocks = (c->cfg.n_force_tiles * c->cfg.force_split + 3) / 4;
+    const int fs = c->w.fpart ? mode_split(fblocks, c->max_p, 1024) : 1;
+    if (force) RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, accumulate, 0, nullptr, fs));
     return RBE_OK;
 }
 
@@ -1190,6 +1210,9 @@ rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
     if (48 * (size_t)n.rho_chunk + 16 * (size_t)n.rho_block > 64 * 1024 ||
         32 * ((size_t)n.rho_chunk + 256) + 28 * (size_t)n.rho_block > 64 * 1024)
         return set_err(c, RBE_ERR_INVALID, "rho_chunk and rho_block need more than 64 KB of LDS");
+    if (partial_need(c, n.rho_chunk) > c->partial_cap)
+        return set_err(c, RBE_ERR_INVALID, "rho_chunk too small for the structure-factor partials of the reserved "
+                                           "mode capacity");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cfg.rho_chunk = n.rho_chunk;
     c->cfg.rho_block = n.rho_block;

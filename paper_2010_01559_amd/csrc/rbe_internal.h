@@ -107,6 +107,10 @@ enum KernelId {
     K_COUNT
 };
 
+// Most blocks a long mode list is split over per particle chunk (classical
+// Ewald through rbe_set_k).
+constexpr int kMaxModeSplit = 32;
+
 // Device workspace of a context.
 struct Workspace {
     SysDev *sys;           // [R]
@@ -143,6 +147,8 @@ struct Workspace {
     int32_t *nnb;          // [Ntot] partners of each slot
     int32_t *lflag;        // [8]: rebuild request for even / odd steps, list overflow, builds, scan ready
     uint64_t *step_base;   // [1]: step number of a graph replay (see ListStep)
+    void *fpart;           // [kMaxModeSplit][3][Ntot] partial forces of mode-split force passes (long
+                           // mode lists only; NULL until rbe_reserve_modes raises the capacity)
 };
 
 struct LaunchCfg {
@@ -188,6 +194,7 @@ struct StageRequest {
     int integrate, bin, sample, rho;
     const ListStep *list;  // integrate in list mode: update cell-order records, test displacements
     int kick = 0;          // integrate: first apply the previous step's final half kick (deferred)
+    int mode_split = 1;    // no integration/binning/sampling: split the modes over this many blocks per chunk
 };
 
 // ---- launchers (rbe_kspace.hip, rbe_real.hip) ----
@@ -199,7 +206,7 @@ hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int 
                       int32_t *clear_flag = nullptr, int sample_next = 0, uint64_t sample_step = 0,
                       const ListStep *ls = nullptr);
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
-                         int accumulate, int scatter, const int32_t *bin_gate = nullptr);
+                         int accumulate, int scatter, const int32_t *bin_gate = nullptr, int mode_split = 1);
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);
 hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step);
 hipError_t launch_pair_hist(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, double r_max,

@@ -301,7 +301,14 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
     }
     if (!a.do_rho) return;
     const int P = S.p;
-    const int Pt = P < BS ? P : BS;
+    // modes [mb, me) of this block: a launch with gridDim.y > 1 splits long
+    // mode lists (classical Ewald) over blocks; it never integrates, bins or
+    // samples, so every y-block may stage the chunk on its own
+    const int ys = (int)gridDim.y;
+    const int mb = (int)(((int64_t)P * blockIdx.y) / ys), me = (int)(((int64_t)P * (blockIdx.y + 1)) / ys);
+    const int Pm = me - mb;
+    if (Pm <= 0) return;
+    const int Pt = Pm < BS ? Pm : BS;
     const int G = BS / Pt < kRhoGroupsMax ? BS / Pt : kRhoGroupsMax;
     // zero-charge records up to a multiple of 8 G, so the unrolled loop
     // below needs no bounds tests
@@ -312,9 +319,9 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
     }
     const double *tabp = a.table_lds ? tab : a.cdf + S.cdf_off;
     double *prow = a.partial + 2 * ((int64_t)a.part_off[t.sys] + (int64_t)t.aux * P);
-    for (int m0 = 0; m0 < P; m0 += Pt) {
+    for (int m0 = mb; m0 < me; m0 += Pt) {
         // modes of this tile into LDS: drawn here or read from the mode arrays
-        if (tid < Pt && m0 + tid < P) {
+        if (tid < Pt && m0 + tid < me) {
             const int l = m0 + tid;
             int mx, my, mz;
             if (a.do_sample) {
@@ -339,7 +346,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         __syncthreads();
         const int lt = tid % Pt, g = tid / Pt;
         const int l = m0 + lt;
-        const bool act = g < G && l < P;
+        const bool act = g < G && l < me;
         double C = 0.0, Sn = 0.0;
         if (act) {
             const T mx = (T)smode[lt], my = (T)smode[BS + lt], mz = (T)smode[2 * BS + lt];
@@ -353,7 +360,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         }
         red[tid] = make_double2(C, Sn);
         __syncthreads();
-        if (tid < Pt && l < P) {
+        if (tid < Pt && l < me) {
             double c = 0.0, s = 0.0;
             for (int gg = 0; gg < G; ++gg) {
                 const double2 v = red[gg * Pt + lt];
@@ -752,6 +759,9 @@ struct ForceArgs {
     int32_t *count;
     int32_t *bin_cellid;
     int32_t *bin_rank;
+    // gridDim.y > 1: the mode list is split over y; partial sums go to
+    // fpart[y][3][ntot] and k_fsum finishes the particles
+    T *fpart;
 };
 
 template <typename T, typename KM, int SPLIT>
@@ -776,7 +786,8 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
             for (int d = 0; d < 3; ++d) s3[d] = frac01((double)a.pos[d * a.ntot + i] * S.invL);
             qi = a.q[i];
         }
-        const int l0 = (S.p * part) / SPLIT, l1 = (S.p * (part + 1)) / SPLIT;
+        const int64_t nparts = (int64_t)SPLIT * gridDim.y, gp = (int64_t)blockIdx.y * SPLIT + part;
+        const int l0 = (int)((S.p * gp) / nparts), l1 = (int)((S.p * (gp + 1)) / nparts);
         const KM *kk = a.km + S.moff;
         T f[3] = {0, 0, 0};
         if constexpr (sizeof(T) == 4) {
@@ -803,6 +814,13 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
         }
     }
     if (i < 0) return;
+    if (gridDim.y > 1) {
+        T *fp = a.fpart + (int64_t)blockIdx.y * 3 * a.ntot;
+        fp[i] = fx;
+        fp[a.ntot + i] = fy;
+        fp[2 * a.ntot + i] = fz;
+        return;
+    }
     fx *= -qi;
     fy *= -qi;
     fz *= -qi;
@@ -841,6 +859,23 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
         else
             reinterpret_cast<PartD *>(a.sorted)[slot] = reinterpret_cast<const PartD *>(a.packed)[i];
     }
+}
+
+// Sum of the mode-split partial forces in a fixed order, then the charge
+// factor, the finiteness check and the store (or accumulation).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fsum(const T *__restrict__ fpart, int ysplit, const T *__restrict__ q,
+                                              int64_t ntot, T *__restrict__ F, int accumulate, int32_t *flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot) return;
+    T f[3] = {0, 0, 0};
+    for (int y = 0; y < ysplit; ++y)
+        for (int d = 0; d < 3; ++d) f[d] += fpart[((int64_t)y * 3 + d) * ntot + i];
+    const T qi = q[i];
+    for (int d = 0; d < 3; ++d) f[d] *= -qi;
+    if (!isfinite(f[0] + f[1] + f[2])) atomicOr(flag, 1);
+    for (int d = 0; d < 3; ++d) F[d * ntot + i] = accumulate ? F[d * ntot + i] + f[d] : f[d];
 }
 
 // ---------------------------------------------------------------------------
@@ -1002,7 +1037,8 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const SysDev *__restrict__ s
             gy = gF[ntot + i];
             gz = gF[2 * ntot + i];
         }
-        const int l0 = (S.p * part) / SPLIT, l1 = (S.p * (part + 1)) / SPLIT;
+        const int64_t nparts = (int64_t)SPLIT * gridDim.y, gp = (int64_t)blockIdx.y * SPLIT + part;
+        const int l0 = (int)((S.p * gp) / nparts), l1 = (int)((S.p * (gp + 1)) / nparts);
         const KV *kk = kv + S.moff;
 #pragma unroll 2
         for (int l = l0; l < l1; ++l) {
@@ -1107,7 +1143,7 @@ static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const S
     const size_t sm = stage_lds_bytes(c, rq.sample, &table_lds, &tab_max);
     a.table_lds = table_lds;
     a.tab_max = tab_max;
-    dim3 g(c.n_rho_tiles);
+    dim3 g(c.n_rho_tiles, rq.mode_split > 1 ? rq.mode_split : 1);
     switch (c.rho_block) {
     case 256:
         k_stage_rho<T, 256><<<g, 256, sm, c.stream>>>(a);
@@ -1183,9 +1219,10 @@ hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int 
 
 template <typename T, typename KM>
 static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *F,
-                                  int acc, int scatter, const int32_t *bin_gate)
+                                  int acc, int scatter, const int32_t *bin_gate, int mode_split)
 {
     ForceArgs<T, KM> a;
+    a.fpart = (T *)w.fpart;
     a.sys = w.sys;
     a.tiles = w.force_tiles;
     a.ntiles = c.n_force_tiles;
@@ -1208,25 +1245,30 @@ static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const 
     a.bin_cellid = w.cellid;
     a.bin_rank = w.rank;
     const int n = c.n_force_tiles;
+    const int ys = mode_split > 1 && w.fpart ? mode_split : 1;
     switch (c.force_split) {
     case 1:
-        k_kforce<T, KM, 1><<<(n + 3) / 4, 256, 0, c.stream>>>(a);
+        k_kforce<T, KM, 1><<<dim3((n + 3) / 4, ys), 256, 0, c.stream>>>(a);
         break;
     case 2:
-        k_kforce<T, KM, 2><<<(n + 1) / 2, 256, 0, c.stream>>>(a);
+        k_kforce<T, KM, 2><<<dim3((n + 1) / 2, ys), 256, 0, c.stream>>>(a);
         break;
     default:
-        k_kforce<T, KM, 4><<<n, 256, 0, c.stream>>>(a);
+        k_kforce<T, KM, 4><<<dim3(n, ys), 256, 0, c.stream>>>(a);
         break;
     }
+    if (ys > 1)
+        k_fsum<T><<<(int)((c.ntot + 255) / 256), 256, 0, c.stream>>>((const T *)w.fpart, ys, (const T *)q, c.ntot,
+                                                                      (T *)F, acc, w.flag);
     return hipGetLastError();
 }
 
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
-                         int accumulate, int scatter, const int32_t *bin_gate)
+                         int accumulate, int scatter, const int32_t *bin_gate, int mode_split)
 {
-    return c.prec == RBE_FP64 ? kforce_dispatch<double, KModeD>(c, w, pos, q, force, accumulate, scatter, bin_gate)
-                              : kforce_dispatch<float, KModeF>(c, w, pos, q, force, accumulate, scatter, bin_gate);
+    return c.prec == RBE_FP64
+               ? kforce_dispatch<double, KModeD>(c, w, pos, q, force, accumulate, scatter, bin_gate, mode_split)
+               : kforce_dispatch<float, KModeF>(c, w, pos, q, force, accumulate, scatter, bin_gate, mode_split);
 }
 
 template <typename T, typename KM>

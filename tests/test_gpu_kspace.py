@@ -121,6 +121,26 @@ def test_classical_ewald_through_set_k():
     assert rel_l2(host(F), Fo) <= 1e-12
 
 
+@pytest.mark.parametrize("prec,tol", [(R.RBE_FP64, 1e-12), (R.RBE_FP32, 1e-5)])
+def test_long_ewald_list_split_over_blocks(prec, tol):
+    """About 22k modes on 3000 particles: both passes split the mode list
+    over blocks (partial sums added in a fixed order); forces and the Fourier
+    energy against the oracle on the same list."""
+    s = W.langevin_electrolyte()
+    s.lj = (0.0, 1.0, 2.5)
+    ctx = make_ctx(s, prec)
+    m, w = O.ewald_modes(s.alpha, s.L, 300)
+    assert m.shape[1] > 20000
+    R.rbe_reserve_modes(ctx, m.shape[1])
+    R.rbe_set_k(ctx, m, w)
+    P, Q, V, F = device_state(ctx, s)
+    pos, q = rounded(s, prec)
+    R.rbe_kspace_forces(ctx, P, Q, F)
+    assert rel_l2(host(F), O.kspace_force(pos, q, s.L, m, w)) <= tol
+    _, (e,) = R.rbe_energy(ctx, P, Q)
+    assert e["e_kspace"] == pytest.approx(O.kspace_energy(pos, q, s.L, m, w), rel=tol)
+
+
 def test_net_kspace_force_vanishes_fp32_full_size():
     s = W.metric_system()
     ctx = make_ctx(s, R.RBE_FP32)
