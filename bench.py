@@ -54,10 +54,19 @@ SLOTS_PAIR = 6 + 3 + 3 * 4 + 3 + 5 + 9 + 4 + 3 + 6 + 6
 PEAK_FP32_TFLOPS = 157.3
 
 # HBM traffic per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch, averaged over the launches of the step),
-# multiplied by the ratio of the true size of a plain copy to what the same
-# counters read for it.  Valid only for the kernel source it was taken on.
-TRAFFIC = {}
+# WRITE_SIZE, KiB per dispatch, averaged over the launches of the profiled
+# run), each multiplied by the ratio of the true size of a 256 MiB device
+# copy to what the same counter reads for it.  Valid only for the kernel
+# source it was taken on (sha256 prefix); otherwise reported as null.
+# k_stage_rho averages the step and Fourier-only variants of the run.
+TRAFFIC = {
+    "real": {"fetch_kib": 12398.9, "write_kib": 9333.6, "fetch_scale": 2.0, "write_scale": 1.0,
+             "src": "774a3e658dc84c78"},
+    "stage": {"fetch_kib": 1356.9, "write_kib": 1611.1, "fetch_scale": 2.0, "write_scale": 1.0,
+              "src": "b35683ea47946546"},
+    "kforce": {"fetch_kib": 942.9, "write_kib": 1171.9, "fetch_scale": 2.0, "write_scale": 1.0,
+               "src": "b35683ea47946546"},
+}
 
 
 def parse():
@@ -123,7 +132,7 @@ def traffic_for(name):
     t = TRAFFIC.get(name)
     if not t or t["src"] != source_sha(KERNEL_SOURCE[name]):
         return None
-    return round((t["fetch_kib"] + t["write_kib"]) * 1024 * t["scale"])
+    return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
 
 
 # ---------------------------------------------------------------------------
@@ -418,7 +427,7 @@ def main():
         us = kkern[name]["avg_us"]
         ach = slots * 2 / (us * 1e-6) / 1e12
         fourier[name] = {"achieved": round(ach, 3), "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                         "avg_launch_us": round(us, 2)}
+                         "avg_launch_us": round(us, 2), "traffic": traffic_for(name)}
 
     cpu = None
     if not args.no_cpu:
