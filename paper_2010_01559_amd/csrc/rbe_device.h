@@ -252,6 +252,17 @@ __device__ __forceinline__ void fourier_range(const KModeD *kk, int l0, int l1, 
 // ---------------------------------------------------------------------------
 // Component d of that update; xi is the component's normal (Langevin) or,
 // for Andersen, the normal used when the particle collides (`hit`).
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (each
+// with its own L2).  For a grid of n tiles laid out in space order, block b
+// (b < n) takes tile xcd_tile(b, n): XCD x = b mod 8 gets the x-th contiguous
+// eighth of the tiles, so spatial neighbours share an L2.  A bijection of
+// [0, n) for any n.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // Time step of the integrator step with index n: the fixed dt, or the
 // annealed burn-in schedule anneal / ln(1 + n) (Sec. 4.2, Example 2; n is
 // taken as at least 1).

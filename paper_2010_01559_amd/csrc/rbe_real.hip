@@ -737,7 +737,8 @@ __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
     const int rebuild = *la.ls.rebuild;
     const int nb = rebuild ? la.n_rows : la.n_list;
     if ((int)blockIdx.x >= nb) return;
-    const Tile t = rebuild ? a.tiles[blockIdx.x] : la.list_tiles[blockIdx.x];
+    const int ti = xcd_tile((int)blockIdx.x, nb);
+    const Tile t = rebuild ? a.tiles[ti] : la.list_tiles[ti];
     const SysDev S = a.sys[t.sys];
     const bool allpairs = t.aux == 1;
     fourier_tile<T>(a, S, allpairs ? a.packed : a.sorted, S.off + t.start, t.count, s4);
