@@ -855,7 +855,7 @@ static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, voi
 {
     const int par = (int)(c->list_gen & 1);
     ListStep ls{c->w.lflag + par, c->w.lflag + (1 - par), c->w.lflag + 2, c->w.lflag + 3, c->w.lflag + 4,
-                c->list_valid ? 0 : 1};
+                c->w.lflag + 5, c->list_valid ? 0 : 1};
     ls.step_base = base;
     ls.step_bump = bump ? base : nullptr;
     ls.bump = bump;
@@ -873,7 +873,6 @@ static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, voi
     const bool draw_next = !c->any_mh && !c->fixed && !last;
     RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, ls.rebuild, ls.rebuild_next, draw_next ? 1 : 0, ks + 1,
                              &ls));
-    RUN(c, K_SCATTER, launch_rebuild(c->cfg, c->w, ls));
     RUN(c, K_REAL, launch_real_step(c->cfg, c->w, ls, force, (andersen || !last) ? nullptr : vel, s));
     c->list_valid = true;
     ++c->list_gen;
@@ -978,11 +977,11 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
     // one step = four launches: [closing kick of the step before + integrate
     // + bin + draw modes + structure-factor partials] -> [totals + cell scan]
     // -> [Fourier force + scatter] -> [real space + LJ (+ the closing half
-    // kick on the last step of the call)].  In list mode: [closing kick +
-    // integrate + list bookkeeping + partials] -> [totals + next step's modes
-    // + binning] -> [cell scan + scatter] -> [Fourier + real space + LJ (+
-    // closing kick on the last step)], where binning, scan and scatter do
-    // work only on rebuild steps (decided on the device).  With graphs on, the
+    // kick on the last step of the call)].  In list mode, three: [closing
+    // kick + integrate + list bookkeeping + partials] -> [totals + next
+    // step's modes + binning, cell scan and scatter] -> [Fourier + real space
+    // + LJ (+ closing kick on the last step)], where binning, scan and
+    // scatter do work only on rebuild steps (decided on the device).  With graphs on, the
     // steady-state steps of a call (after the first, before the last) are
     // replayed from a captured graph.
     int table_lds = 0, tab_max = 0;

@@ -145,7 +145,8 @@ struct Workspace {
     void *ref;             // [Ntot] record of each particle at the last build (original order)
     int32_t *nbr;          // [kmax][Ntot] partner slots, column k of slot s at k * Ntot + s
     int32_t *nnb;          // [Ntot] partners of each slot
-    int32_t *lflag;        // [8]: rebuild request for even / odd steps, list overflow, builds, scan ready
+    int32_t *lflag;        // [8]: rebuild request for even / odd steps, list overflow, builds, scan ready,
+                           //      binning blocks done
     uint64_t *step_base;   // [1]: step number of a graph replay (see ListStep)
     void *fpart;           // [kMaxModeSplit][3][Ntot] partial forces of mode-split force passes (long
                            // mode lists only; NULL until rbe_reserve_modes raises the capacity)
@@ -174,7 +175,8 @@ struct ListStep {
     int32_t *rebuild_next;   // request flag of the next step
     int32_t *overflow;
     int32_t *rebuilds;       // count of list builds
-    int32_t *ready;          // rebuild: cell scan done (set by the rebuild launch, cleared by the totals launch)
+    int32_t *ready;          // rebuild: cell scan done (raised in the totals launch, reset by the staging launch)
+    int32_t *bins_done;      // rebuild: binning blocks finished (same)
     int force_rebuild;
     // graph replays: the step numbers passed to the launches are offsets
     // from *step_base (device), which the force launch advances by `bump`
@@ -211,7 +213,6 @@ hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep
 hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step);
 hipError_t launch_pair_hist(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, double r_max,
                             int nbins, int64_t *counts);
-hipError_t launch_rebuild(const LaunchCfg &c, const Workspace &w, const ListStep &ls);
 hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListStep &ls, void *force, void *vel_kick,
                             uint64_t kick_step = 0);
 hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick,

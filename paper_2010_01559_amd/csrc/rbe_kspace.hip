@@ -25,6 +25,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "rbe_device.h"
 #include "rbe_internal.h"
@@ -253,6 +254,11 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
     const int K = 2 * S.M + 1;
     if (a.do_sample && a.table_lds)
         for (int k = tid; k < K; k += BS) tab[k] = a.cdf[S.cdf_off + k];
+    if (a.list_mode && blockIdx.x == 0 && tid == 0) {
+        // the rebuild of this step (in the totals launch) starts from zero
+        *a.ls.ready = 0;
+        *a.ls.bins_done = 0;
+    }
     bool moved = false;
     const uint64_t base = a.list_mode && a.ls.step_base ? *a.ls.step_base : 0;
     const uint64_t step = a.step + base, sample_step = a.sample_step + base;
@@ -382,6 +388,31 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
 //  * cell scan: one block per system turns the cell counts into global slot
 //    starts (exclusive prefix + S.off) and clears the counts.
 // ---------------------------------------------------------------------------
+// Gated list rebuild inside the totals launch: binning blocks, then one
+// scan block, then scatter blocks, ordered by bounded device flags.
+struct RebuildArgs {
+    const SysDev *sys;
+    int R;
+    const int32_t *gate;
+    int32_t *ready;
+    int32_t *count;
+    int32_t *start;
+    const Tile *part_tiles;
+    int n_part_tiles;
+    const int32_t *cellid;
+    const int32_t *rank;
+    const void *packed;
+    int32_t *sorted_idx;
+    void *sorted;
+    int32_t *slot_of;
+    void *ref;
+    int32_t *overflow;
+    int32_t *builds;
+    int32_t *flag;
+    int32_t *bins_done;     // binning blocks finished (reset by the staging launch)
+    int n_bin;              // binning blocks of the launch
+};
+
 template <typename KM>
 struct MidArgs {
     const SysDev *sys;
@@ -414,8 +445,12 @@ struct MidArgs {
     int32_t *modes_next;
     double *mode_w_next;
     int32_t *clear_flag;
-    int32_t *clear_flag2;
     const uint64_t *step_base;   // added to sample_step when set
+    // list rebuild (gated by bin_gate): one scan block and n_reb_scatter
+    // scatter blocks after all the others
+    int reb;
+    int n_reb_scatter;
+    RebuildArgs rb;
 };
 
 // Cell of a stored record and its atomic rank within the cell.
@@ -562,68 +597,64 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
 }
 
 // ---------------------------------------------------------------------------
-// k_rebuild: the rest of a neighbour-list rebuild (does nothing unless the
-// step's rebuild flag is set).  Block 0 scans every system's cell counts and
-// then raises `ready`; every other block waits for it (block 0 is dispatched
-// first and waits on nobody, so the wait ends) and then strides over the
-// 256-particle tiles, scattering them into cell order: slot, record,
-// reference record.  The wait is bounded;
-// if the bound is ever reached the block raises the error flag instead.
+// List rebuild inside the totals launch (work only when the step's rebuild
+// flag is set).  The binning blocks count their particles into the cells and
+// then each adds one to bins_done; the scan block, which comes after them in
+// block order, waits for all of them, scans every system's counts and raises
+// `ready`; the scatter blocks, last in block order, wait for it and stride
+// over the 256-particle tiles, moving records into cell order.  The launch
+// has a few dozen 1024-thread blocks, all resident at once, and a block only
+// waits for blocks of lower index, so every wait ends; the waits are bounded
+// anyway and raise the error flag if the bound is reached.  The staging
+// launch of each step resets bins_done and ready.
 // ---------------------------------------------------------------------------
-struct RebuildArgs {
-    const SysDev *sys;
-    int R;
-    const int32_t *gate;
-    int32_t *ready;
-    int32_t *count;
-    int32_t *start;
-    const Tile *part_tiles;
-    int n_part_tiles;
-    const int32_t *cellid;
-    const int32_t *rank;
-    const void *packed;
-    int32_t *sorted_idx;
-    void *sorted;
-    int32_t *slot_of;
-    void *ref;
-    int32_t *overflow;
-    int32_t *builds;
-    int32_t *flag;
-};
 
-template <typename Rec>
-__global__ __launch_bounds__(1024) void k_rebuild(RebuildArgs a)
+// Thread 0 waits (bounded) until *p reaches want; the block learns the
+// outcome.  A timeout sets bit 2 of the error flag.
+__device__ bool block_wait(int32_t *p, int want, int32_t *flag)
 {
-    if (*a.gate == 0) return;
-    if (blockIdx.x == 0) {
-        for (int r = 0; r < a.R; ++r) mid_scan(a.sys[r], r, a.count, a.start);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            *a.overflow = 0;
-            *a.builds += 1;
-            __threadfence();
-            __hip_atomic_store(a.ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        return;
-    }
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
         int ok = 0;
         for (int it = 0; it < (1 << 24); ++it) {
-            if (__hip_atomic_load(a.ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) {
                 ok = 1;
                 break;
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        if (!ok) atomicOr(a.flag, 2);
+        if (!ok) atomicOr(flag, 2);
         s_ok = ok;
     }
     __syncthreads();
-    if (!s_ok) return;
     __threadfence();
-    const int nw = gridDim.x - 1;
-    for (int ti = 4 * (blockIdx.x - 1) + (int)(threadIdx.x >> 8); ti < a.n_part_tiles; ti += 4 * nw) {
+    return s_ok != 0;
+}
+
+// Scan block of a rebuild: waits for every binning block, turns the cell
+// counts of all systems into slot starts, clears the overflow flag, counts
+// the build and releases the scatter blocks.
+__device__ void rebuild_scan(const RebuildArgs &a)
+{
+    if (!block_wait(a.bins_done, a.n_bin, a.flag)) return;
+    for (int r = 0; r < a.R; ++r) mid_scan(a.sys[r], r, a.count, a.start);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *a.overflow = 0;
+        *a.builds += 1;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(a.ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Scatter block b of nb: moves records into cell order once the scan is out,
+// and records each particle's slot and list reference record.
+template <typename Rec>
+__device__ void rebuild_scatter(const RebuildArgs &a, int b, int nb)
+{
+    if (!block_wait(a.ready, 1, a.flag)) return;
+    for (int ti = 4 * b + (int)(threadIdx.x >> 8); ti < a.n_part_tiles; ti += 4 * nb) {
         const Tile t = a.part_tiles[ti];
         const int k = threadIdx.x & 255;
         if (k >= t.count) continue;
@@ -650,45 +681,12 @@ hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step
     return hipGetLastError();
 }
 
-hipError_t launch_rebuild(const LaunchCfg &c, const Workspace &w, const ListStep &ls)
-{
-    RebuildArgs a;
-    a.sys = w.sys;
-    a.R = c.R;
-    a.gate = ls.rebuild;
-    a.ready = ls.ready;
-    a.count = w.cell_count;
-    a.start = w.cell_start;
-    a.part_tiles = w.part_tiles;
-    a.n_part_tiles = c.n_part_tiles;
-    a.cellid = w.cellid;
-    a.rank = w.rank;
-    a.packed = w.packed;
-    a.sorted_idx = w.sorted_idx;
-    a.sorted = w.sorted;
-    a.slot_of = w.slot_of;
-    a.ref = w.ref;
-    a.overflow = ls.overflow;
-    a.builds = ls.rebuilds;
-    a.flag = w.flag;
-    // few blocks: on the many steps without a rebuild the launch costs only
-    // their dispatch
-    const int nb = 1 + std::min(16, (c.n_part_tiles + 3) / 4);
-    if (c.prec == RBE_FP64)
-        k_rebuild<PartD><<<nb, 1024, 0, c.stream>>>(a);
-    else
-        k_rebuild<PackF><<<nb, 1024, 0, c.stream>>>(a);
-    return hipGetLastError();
-}
 
 template <typename KM>
 __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
 {
     extern __shared__ double mid_tab[];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.clear_flag) {
-        *a.clear_flag = 0;
-        if (a.clear_flag2) *a.clear_flag2 = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.clear_flag) *a.clear_flag = 0;
     if ((int)blockIdx.x < a.n_final_blocks) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         mid_final<KM>(a, blockIdx.x * 16 + wave);
@@ -696,7 +694,14 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
     }
     const int b = blockIdx.x - a.n_final_blocks;
     if (b < a.n_bin_blocks) {
-        if (*a.bin_gate != 0) mid_bin<KM>(a, b);
+        if (*a.bin_gate == 0) return;
+        mid_bin<KM>(a, b);
+        if (a.reb) {
+            // publish this block's counts, cell ids and ranks
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) atomicAdd(a.rb.bins_done, 1);
+        }
         return;
     }
     const int b2 = b - a.n_bin_blocks;
@@ -721,10 +726,19 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
         }
         return;
     }
+    const int b3 = b2 - a.n_sample_blocks;
+    if (a.reb) {
+        if (*a.bin_gate == 0) return;
+        using Rec = typename std::conditional<sizeof(KM) == sizeof(KModeF), PackF, PartD>::type;
+        if (b3 == 0)
+            rebuild_scan(a.rb);
+        else
+            rebuild_scatter<Rec>(a.rb, b3 - 1, a.n_reb_scatter);
+        return;
+    }
     if (!a.do_scan) return;
     if (a.scan_gate && *a.scan_gate == 0) return;
-    const int r = b2 - a.n_sample_blocks;
-    mid_scan(a.sys[r], r, a.count, a.start);
+    mid_scan(a.sys[b3], b3, a.count, a.start);
 }
 
 // ---------------------------------------------------------------------------
@@ -1198,10 +1212,36 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.modes_next = w.modes_alt;
     a.mode_w_next = w.mode_w_alt;
     a.clear_flag = clear_flag;
-    a.clear_flag2 = ls ? ls->ready : nullptr;
     a.step_base = ls ? ls->step_base : nullptr;
+    // a list step: the gated rebuild runs in this launch
+    a.reb = ls && bin_gate ? 1 : 0;
+    a.n_reb_scatter = a.reb ? std::min(16, (c.n_part_tiles + 3) / 4) : 0;
+    if (a.reb) {
+        RebuildArgs &r = a.rb;
+        r.sys = w.sys;
+        r.R = c.R;
+        r.gate = bin_gate;
+        r.ready = ls->ready;
+        r.count = w.cell_count;
+        r.start = w.cell_start;
+        r.part_tiles = w.part_tiles;
+        r.n_part_tiles = c.n_part_tiles;
+        r.cellid = w.cellid;
+        r.rank = w.rank;
+        r.packed = w.packed;
+        r.sorted_idx = w.sorted_idx;
+        r.sorted = w.sorted;
+        r.slot_of = w.slot_of;
+        r.ref = w.ref;
+        r.overflow = ls->overflow;
+        r.builds = ls->rebuilds;
+        r.flag = w.flag;
+        r.bins_done = ls->bins_done;
+        r.n_bin = a.n_bin_blocks;
+    }
     const size_t sm = a.table_lds ? sizeof(double) * c.max_table : 0;
-    const int nb = a.n_final_blocks + a.n_bin_blocks + a.n_sample_blocks + (do_scan ? c.R : 0);
+    const int nb = a.n_final_blocks + a.n_bin_blocks + a.n_sample_blocks + (do_scan ? c.R : 0) +
+                   (a.reb ? 1 + a.n_reb_scatter : 0);
     if (nb == 0) return hipSuccess;
     k_mid<KM><<<nb, 1024, sm, c.stream>>>(a);
     return hipGetLastError();
