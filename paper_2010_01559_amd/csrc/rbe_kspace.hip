@@ -238,7 +238,11 @@ __device__ __forceinline__ void rho_term(const PartD &v, double mx, double my, d
 constexpr int kRhoGroupsMax = 32;
 constexpr int kRhoUnroll = 8;
 
-template <typename T, int BS>
+// FULL = false compiles a lean variant for launches that only stage the
+// particles and compute structure factors (force calls, energies, long
+// Ewald lists): without the integrator, binning, sampling and list code it
+// needs far fewer registers, so more blocks share a compute unit.
+template <typename T, int BS, bool FULL>
 __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -252,21 +256,21 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
     const int tid = threadIdx.x;
     const int count = t.count;
     const int K = 2 * S.M + 1;
-    if (a.do_sample && a.table_lds)
+    if (FULL && a.do_sample && a.table_lds)
         for (int k = tid; k < K; k += BS) tab[k] = a.cdf[S.cdf_off + k];
-    if (a.list_mode && blockIdx.x == 0 && tid == 0) {
+    if (FULL && a.list_mode && blockIdx.x == 0 && tid == 0) {
         // the rebuild of this step (in the totals launch) starts from zero
         *a.ls.ready = 0;
         *a.ls.bins_done = 0;
     }
     bool moved = false;
-    const uint64_t base = a.list_mode && a.ls.step_base ? *a.ls.step_base : 0;
+    const uint64_t base = FULL && a.list_mode && a.ls.step_base ? *a.ls.step_base : 0;
     const uint64_t step = a.step + base, sample_step = a.sample_step + base;
     for (int j = tid; j < count; j += BS) {
         const int il = t.start + j;
         const int64_t i = S.off + il;
         double x[3];
-        if (a.do_integrate) {
+        if (FULL && a.do_integrate) {
             integrate_one<T>(S, il, i, a.ntot, a.pos, a.vel, a.F, step, a.kick != 0, x);
         } else {
             x[0] = (double)a.pos[i];
@@ -277,7 +281,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         const T qi = a.q[i];
         RR v;
         if constexpr (sizeof(T) == 4) {
-            if (a.list_mode) {
+            if (FULL && a.list_mode) {
                 // the force pass reads the stored 32-bit records: take the
                 // phases of the structure factor from the same fractions
                 split_fix(to_fix(sx), S, v.hx, v.lx);
@@ -292,10 +296,10 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
             rho_record(S, sx, sy, sz, qi, v);
         }
         sp[j] = v;
-        if (a.do_bin) bin_one<T>(S, i, sx, sy, sz, qi, a.count, a.cellid, a.rank, a.packed);
-        if (a.list_mode) moved |= list_update<T>(S, i, sx, sy, sz, qi, a);
+        if (FULL && a.do_bin) bin_one<T>(S, i, sx, sy, sz, qi, a.count, a.cellid, a.rank, a.packed);
+        if (FULL && a.list_mode) moved |= list_update<T>(S, i, sx, sy, sz, qi, a);
     }
-    if (a.list_mode) {
+    if (FULL && a.list_mode) {
         // one request per block; block 0 adds the host's and the overflow's
         const int any = __syncthreads_or(moved ? 1 : 0);
         if (tid == 0) {
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         if (tid < Pt && m0 + tid < me) {
             const int l = m0 + tid;
             int mx, my, mz;
-            if (a.do_sample) {
+            if (FULL && a.do_sample) {
                 sample_mode(tabp, S.M, (uint32_t)l, S.seed, sample_step, mx, my, mz);
                 if (t.aux == 0) {
                     const int o = S.moff + l;
@@ -1158,15 +1162,25 @@ static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const S
     a.table_lds = table_lds;
     a.tab_max = tab_max;
     dim3 g(c.n_rho_tiles, rq.mode_split > 1 ? rq.mode_split : 1);
+    const bool full = rq.integrate || rq.bin || rq.sample || rq.list;
     switch (c.rho_block) {
     case 256:
-        k_stage_rho<T, 256><<<g, 256, sm, c.stream>>>(a);
+        if (full)
+            k_stage_rho<T, 256, true><<<g, 256, sm, c.stream>>>(a);
+        else
+            k_stage_rho<T, 256, false><<<g, 256, sm, c.stream>>>(a);
         break;
     case 512:
-        k_stage_rho<T, 512><<<g, 512, sm, c.stream>>>(a);
+        if (full)
+            k_stage_rho<T, 512, true><<<g, 512, sm, c.stream>>>(a);
+        else
+            k_stage_rho<T, 512, false><<<g, 512, sm, c.stream>>>(a);
         break;
     default:
-        k_stage_rho<T, 1024><<<g, 1024, sm, c.stream>>>(a);
+        if (full)
+            k_stage_rho<T, 1024, true><<<g, 1024, sm, c.stream>>>(a);
+        else
+            k_stage_rho<T, 1024, false><<<g, 1024, sm, c.stream>>>(a);
         break;
     }
     return hipGetLastError();
