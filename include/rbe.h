@@ -195,7 +195,11 @@ rbe_status rbe_real_forces(rbe_ctx *ctx, const void *pos, const void *q, void *f
  * vel, force hold the new state, positions wrapped into [0, L).
  * RBE_LEAPFROG_ANDERSEN: the leapfrog + Andersen loop of Sec. 3.1 with vel
  * the half-step velocity; the force computed at the end of step s uses the
- * modes of index s + 1. */
+ * modes of index s + 1.  With RBE_SAMPLER_FIXED no modes are drawn: every
+ * step uses the active list (RBE_ERR_STATE if there is none).  The time step
+ * is dt, or the schedule set by rbe_set_dt.  Results do not depend on how a
+ * run is split into calls (bit for bit in FP32).  Asynchronous; no
+ * allocation. */
 rbe_status rbe_step(rbe_ctx *ctx, void *pos, void *vel, const void *q, void *force, uint64_t first_step,
                     int32_t nsteps);
 

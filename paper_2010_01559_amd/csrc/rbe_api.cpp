@@ -23,7 +23,7 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 const char *kKernelNames[K_COUNT] = {"sample", "stage",      "mid",        "kforce",   "scatter", "real",
-                                     "energy", "vjp_reduce", "vjp_gather", "vjp_real", "scan",    "misc"};
+                                     "energy", "vjp_reduce", "vjp_gather", "vjp_real", "misc"};
 
 std::string fmt(const char *f, ...)
 {
@@ -813,7 +813,7 @@ static rbe_status kspace_impl(rbe_ctx *c, const void *pos, const void *q, void *
     RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0));
     const int fblocks = (c->cfg.n_force_tiles * c->cfg.force_split + 3) / 4;
     const int fs = c->w.fpart ? mode_split(fblocks, c->max_p, 1024) : 1;
-    if (force) RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, accumulate, 0, nullptr, fs));
+    if (force) RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, accumulate, 0, fs));
     return RBE_OK;
 }
 

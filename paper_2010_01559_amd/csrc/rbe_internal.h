@@ -102,7 +102,6 @@ enum KernelId {
     K_VJP_REDUCE,
     K_VJP_GATHER,
     K_VJP_REAL,
-    K_SCAN,         // cell scan of a list rebuild (exits at once on other steps)
     K_MISC,
     K_COUNT
 };
@@ -208,8 +207,8 @@ hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int 
                       int32_t *clear_flag = nullptr, int sample_next = 0, uint64_t sample_step = 0,
                       const ListStep *ls = nullptr);
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
-                         int accumulate, int scatter, const int32_t *bin_gate = nullptr, int mode_split = 1);
-hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls = nullptr);
+                         int accumulate, int scatter, int mode_split = 1);
+hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w);
 hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step);
 hipError_t launch_pair_hist(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, double r_max,
                             int nbins, int64_t *counts);

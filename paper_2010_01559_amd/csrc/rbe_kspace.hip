@@ -772,11 +772,6 @@ struct ForceArgs {
     const void *packed;
     int32_t *sorted_idx;
     void *sorted;
-    // binning of a list rebuild, from the records the staging pass stored
-    const int32_t *bin_gate;
-    int32_t *count;
-    int32_t *bin_cellid;
-    int32_t *bin_rank;
     // gridDim.y > 1: the mode list is split over y; partial sums go to
     // fpart[y][3][ntot] and k_fsum finishes the particles
     T *fpart;
@@ -851,24 +846,6 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
     a.F[i] = fx;
     a.F[a.ntot + i] = fy;
     a.F[2 * a.ntot + i] = fz;
-    if (a.bin_gate && *a.bin_gate) {
-        const SysDev S = a.sys[sysi];
-        int cx, cy, cz;
-        if constexpr (sizeof(T) == 4) {
-            const PackF v = reinterpret_cast<const PackF *>(a.packed)[i];
-            cx = cell_of_fix(v.x, S.nc);
-            cy = cell_of_fix(v.y, S.nc);
-            cz = cell_of_fix(v.z, S.nc);
-        } else {
-            const PartD v = reinterpret_cast<const PartD *>(a.packed)[i];
-            cx = cell_of_frac(v.x, S.nc);
-            cy = cell_of_frac(v.y, S.nc);
-            cz = cell_of_frac(v.z, S.nc);
-        }
-        const int c = S.cell_off + (cz * S.nc + cy) * S.nc + cx;
-        a.bin_cellid[i] = c;
-        a.bin_rank[i] = atomicAdd(&a.count[c], 1);
-    }
     if (a.do_scatter) {
         const int slot = a.start[a.cellid[i] + sysi] + a.rank[i];
         a.sorted_idx[slot] = (int32_t)i;
@@ -1273,7 +1250,7 @@ hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int 
 
 template <typename T, typename KM>
 static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *F,
-                                  int acc, int scatter, const int32_t *bin_gate, int mode_split)
+                                  int acc, int scatter, int mode_split)
 {
     ForceArgs<T, KM> a;
     a.fpart = (T *)w.fpart;
@@ -1294,10 +1271,6 @@ static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const 
     a.packed = w.packed;
     a.sorted_idx = w.sorted_idx;
     a.sorted = w.sorted;
-    a.bin_gate = bin_gate;
-    a.count = w.cell_count;
-    a.bin_cellid = w.cellid;
-    a.bin_rank = w.rank;
     const int n = c.n_force_tiles;
     const int ys = mode_split > 1 && w.fpart ? mode_split : 1;
     switch (c.force_split) {
@@ -1318,11 +1291,10 @@ static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const 
 }
 
 hipError_t launch_kforce(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *force,
-                         int accumulate, int scatter, const int32_t *bin_gate, int mode_split)
+                         int accumulate, int scatter, int mode_split)
 {
-    return c.prec == RBE_FP64
-               ? kforce_dispatch<double, KModeD>(c, w, pos, q, force, accumulate, scatter, bin_gate, mode_split)
-               : kforce_dispatch<float, KModeF>(c, w, pos, q, force, accumulate, scatter, bin_gate, mode_split);
+    return c.prec == RBE_FP64 ? kforce_dispatch<double, KModeD>(c, w, pos, q, force, accumulate, scatter, mode_split)
+                              : kforce_dispatch<float, KModeF>(c, w, pos, q, force, accumulate, scatter, mode_split);
 }
 
 template <typename T, typename KM>

@@ -751,26 +751,14 @@ __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
         list_body<T, LPP>(a, la, t, S, s4);
 }
 
-// Stand-alone scatter into cell order (the force kernel does this inline
-// during a time step).
-// With a list step (gate), it runs only on rebuild steps and also records
-// each particle's slot and reference record, clears the overflow flag and
-// counts the build.
+// Stand-alone scatter into cell order (force and energy calls; a time step
+// on the neighbour list scatters inside the totals launch).
 template <typename Rec>
 __global__ __launch_bounds__(256) void k_scatter(const SysDev *__restrict__ sys, const Tile *__restrict__ tiles,
                                                  const int32_t *__restrict__ start, const int32_t *__restrict__ cellid,
                                                  const int32_t *__restrict__ rank, const Rec *__restrict__ packed,
-                                                 int32_t *__restrict__ sorted_idx, Rec *__restrict__ sorted,
-                                                 const int32_t *gate, int32_t *overflow, int32_t *builds,
-                                                 int32_t *slot_of, Rec *ref)
+                                                 int32_t *__restrict__ sorted_idx, Rec *__restrict__ sorted)
 {
-    if (gate) {
-        if (*gate == 0) return;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            *overflow = 0;
-            *builds += 1;
-        }
-    }
     const Tile t = tiles[blockIdx.x];
     if ((int)threadIdx.x >= t.count) return;
     const int64_t i = sys[t.sys].off + t.start + threadIdx.x;
@@ -778,10 +766,6 @@ __global__ __launch_bounds__(256) void k_scatter(const SysDev *__restrict__ sys,
     const Rec v = packed[i];
     sorted_idx[slot] = (int32_t)i;
     sorted[slot] = v;
-    if (gate) {
-        slot_of[i] = slot;
-        ref[i] = v;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -932,21 +916,16 @@ hipError_t launch_fill_zero(hipStream_t s, void *ptr, int64_t nbytes)
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w, const ListStep *ls)
+hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w)
 {
-    const int32_t *gate = ls ? ls->rebuild : nullptr;
-    int32_t *ovf = ls ? ls->overflow : nullptr;
-    int32_t *nb = ls ? ls->rebuilds : nullptr;
     if (c.prec == RBE_FP64)
         k_scatter<PartD><<<c.n_part_tiles, 256, 0, c.stream>>>(w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
                                                                (const PartD *)w.packed, w.sorted_idx,
-                                                               (PartD *)w.sorted, gate, ovf, nb, w.slot_of,
-                                                               (PartD *)w.ref);
+                                                               (PartD *)w.sorted);
     else
         k_scatter<PackF><<<c.n_part_tiles, 256, 0, c.stream>>>(w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
                                                                (const PackF *)w.packed, w.sorted_idx,
-                                                               (PackF *)w.sorted, gate, ovf, nb, w.slot_of,
-                                                               (PackF *)w.ref);
+                                                               (PackF *)w.sorted);
     return hipGetLastError();
 }
 

@@ -172,3 +172,36 @@ def test_batched_step_matches_each_system():
         assert np.linalg.norm(dp) / np.linalg.norm(po) <= 1e-10, r
         assert rel_l2(v[:, off:off + s.n], vo) <= 1e-10, r
         off += s.n
+
+
+def test_many_systems_rebuild_inside_the_totals_launch():
+    """Forty small systems stepped together with a thin skin and a long time
+    step: the totals launch then holds more blocks than there are compute
+    units and rebuilds the list on many steps.  Every system follows its own
+    single-system context (same tiles), and no wait inside the launch timed
+    out (the error flag stays clear)."""
+    import torch
+    systems = W.replica_systems(R=40, nmin=300, nmax=800, seed=79)
+    over = dict(skin=0.1, dt=0.004)
+    params = [R.params_from_system(s, R.RBE_FP32, **over) for s in systems]
+    ctx = R.rbe_batch_create(params)
+    R.rbe_set_tiles(ctx, rho_chunk=64, rho_block=256)
+    cat = lambda k: np.concatenate([getattr(s, k) for s in systems], -1)
+    P, V, Q = (R.to_device(cat(k), ctx) for k in ("pos", "vel", "q"))
+    F = torch.zeros_like(P)
+    initial_force(ctx, P, Q, F)
+    R.rbe_batch_step(ctx, P, V, Q, F, 1, 12)
+    assert R.rbe_list_builds(ctx) >= 4
+    st, es = R.rbe_energy(ctx, P, Q, V)
+    assert st == R.RBE_OK and all(e["nonfinite"] == 0 for e in es)
+    p, v = host(P), host(V)
+    off = 0
+    for s, prm in zip(systems, params):
+        c1 = R.rbe_create(prm)
+        R.rbe_set_tiles(c1, rho_chunk=64, rho_block=256)
+        P1, Q1, V1, F1 = device_state(c1, s)
+        initial_force(c1, P1, Q1, F1)
+        R.rbe_step(c1, P1, V1, Q1, F1, 1, 12)
+        assert pos_err(P1, p[:, off:off + s.n], s.L) <= 1e-5
+        assert rel_l2(host(V1), v[:, off:off + s.n]) <= 1e-5
+        off += s.n
