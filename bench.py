@@ -87,24 +87,44 @@ def parse():
 def cpu_baseline(s, modes, budget_s):
     """Time the FP64 oracle's Fourier evaluation (structure factor + force) on
     the metric workload: whole evaluations at N = 1e5, P = 100 repeated until
-    the budget is spent."""
+    the budget is spent, with every host thread, then single-threaded."""
     import oracle as O
     O.build()
     pos = s.pos.astype(np.float32).astype(np.float64)
     q = s.q
     w = O.rbe_weights(s.alpha, s.L, s.p)
     O.rbe_kspace_force(pos[:, :1000], q[:1000], s.L, s.alpha, modes)  # load + warm
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        O.kspace_force(pos, q, s.L, modes, w)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or reps >= 1000:
-            break
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": s.n * s.p * reps / el, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+
+    def rate(budget):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            O.kspace_force(pos, q, s.L, modes, w)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > budget or reps >= 1000:
+                return s.n * s.p * reps / el, reps, el
+
+    threads = O.set_threads(0)
+    v, reps, el = rate(budget_s)
+    O.set_threads(1)
+    v1, reps1, el1 = rate(budget_s / 2)
+    O.set_threads(threads)
+    return {"value": v, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} full Fourier evaluations (structure factor + force, FP64) of the N={s.n}, "
-                      f"P={s.p} workload in {el:.1f} s"}
+                      f"P={s.p} workload in {el:.1f} s on {threads} threads; single-threaded {reps1} "
+                      f"in {el1:.1f} s",
+            "single_thread_value": v1, "host_cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def real_space_counts(s, skin):

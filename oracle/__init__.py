@@ -120,6 +120,8 @@ def lib():
         L.oracle_kspace_virial.restype = C.c_double
         L.oracle_kspace_virial.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_int, _ip, _dp,
                                            C.c_double]
+        L.oracle_set_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_pair_histogram.restype = None
         L.oracle_pair_histogram.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_int,
                                             np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")]
@@ -339,3 +341,8 @@ def pair_histogram(pos, q, L, r_max, nbins):
     counts = np.zeros((3, nbins), np.int64)
     lib().oracle_pair_histogram(_f64(q).shape[0], _f64(pos), _f64(q), L, r_max, nbins, counts)
     return counts
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (n <= 0 leaves them); returns the count."""
+    return lib().oracle_set_threads(int(n))

@@ -26,6 +26,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PI 3.14159265358979323846264338327950288
 
@@ -891,4 +894,17 @@ void oracle_pair_histogram(int n, const double *pos, const double *q, double L, 
             int cls = 2 - ((q[i] > 0.0) + (q[j] > 0.0));
             counts[(int64_t)cls * nbins + b] += 1;
         }
+}
+
+/* Threads of the OpenMP loops (for timing the oracle single-threaded and
+ * with every core); returns the count in effect afterwards. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
