@@ -58,14 +58,17 @@ PEAK_FP32_TFLOPS = 157.3
 # run), each multiplied by the ratio of the true size of a 256 MiB device
 # copy to what the same counter reads for it.  Valid only for the kernel
 # source it was taken on (sha256 prefix); otherwise reported as null.
-# k_stage_rho averages the step and Fourier-only variants of the run.
+# "stage" is the time-step variant of k_stage_rho, "stage_fourier" the lean
+# variant of force calls.
 TRAFFIC = {
-    "real": {"fetch_kib": 12398.9, "write_kib": 9333.6, "fetch_scale": 2.0, "write_scale": 1.0,
-             "src": "774a3e658dc84c78"},
-    "stage": {"fetch_kib": 1356.9, "write_kib": 1611.1, "fetch_scale": 2.0, "write_scale": 1.0,
-              "src": "b35683ea47946546"},
-    "kforce": {"fetch_kib": 942.9, "write_kib": 1171.9, "fetch_scale": 2.0, "write_scale": 1.0,
-               "src": "b35683ea47946546"},
+    "real": {"fetch_kib": 8325.1, "write_kib": 8310.7, "fetch_scale": 2.0, "write_scale": 1.0,
+             "src": "5e2d1f5476412969"},
+    "stage": {"fetch_kib": 3159.0, "write_kib": 7163.8, "fetch_scale": 2.0, "write_scale": 1.0,
+              "src": "3dcc55258867779c"},
+    "stage_fourier": {"fetch_kib": 889.8, "write_kib": 400.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                      "src": "3dcc55258867779c"},
+    "kforce": {"fetch_kib": 936.4, "write_kib": 1171.9, "fetch_scale": 2.0, "write_scale": 1.0,
+               "src": "3dcc55258867779c"},
 }
 
 
@@ -144,8 +147,8 @@ def source_sha(name):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-KERNEL_SOURCE = {"stage": "rbe_kspace.hip", "mid": "rbe_kspace.hip", "kforce": "rbe_kspace.hip",
-                 "sample": "rbe_kspace.hip", "real": "rbe_real.hip"}
+KERNEL_SOURCE = {"stage": "rbe_kspace.hip", "stage_fourier": "rbe_kspace.hip", "mid": "rbe_kspace.hip",
+                 "kforce": "rbe_kspace.hip", "sample": "rbe_kspace.hip", "real": "rbe_real.hip"}
 
 
 def traffic_for(name):
@@ -447,7 +450,8 @@ def main():
         us = kkern[name]["avg_us"]
         ach = slots * 2 / (us * 1e-6) / 1e12
         fourier[name] = {"achieved": round(ach, 3), "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                         "avg_launch_us": round(us, 2), "traffic": traffic_for(name)}
+                         "avg_launch_us": round(us, 2),
+                         "traffic": traffic_for("stage_fourier" if name == "stage" else name)}
 
     cpu = None
     if not args.no_cpu:
