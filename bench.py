@@ -143,8 +143,12 @@ def real_space_counts(s, skin):
 
 
 def source_sha(name):
-    with open(os.path.join(ROOT, "paper_2010_01559_amd", "csrc", name), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of a kernel source together with the headers it includes."""
+    h = hashlib.sha256()
+    for part in (name, "rbe_device.h", "rbe_internal.h"):
+        with open(os.path.join(ROOT, "paper_2010_01559_amd", "csrc", part), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 KERNEL_SOURCE = {"stage": "rbe_kspace.hip", "stage_fourier": "rbe_kspace.hip", "mid": "rbe_kspace.hip",

@@ -166,9 +166,12 @@ struct alignas(16) PackF {
     float q;
 };
 
+// Non-finite or negative input maps to 0, so that a non-finite position can
+// never index outside the cell arrays (the force kernels flag it instead).
 __device__ __forceinline__ uint32_t to_fix(double s)
 {
     const double v = s * 4294967296.0;
+    if (!(v >= 0.0)) return 0u;
     return v >= 4294967295.0 ? 4294967295u : (uint32_t)v;
 }
 
@@ -176,7 +179,8 @@ __device__ __forceinline__ int cell_of_fix(uint32_t u, int nc) { return (int)(((
 
 __device__ __forceinline__ int cell_of_frac(double s, int nc)
 {
-    const int c = (int)(s * nc);
+    if (!(s >= 0.0)) return 0;
+    const int c = s < 1.0 ? (int)(s * nc) : nc - 1;
     return c >= nc ? nc - 1 : c;
 }
 
