@@ -847,7 +847,8 @@ rbe_status rbe_real_forces(rbe_ctx *c, const void *pos, const void *q, void *for
     return RBE_OK;
 }
 
-// The four launches of one list-mode step.  With base set (graph capture),
+// The three launches of one list-mode step (plus the sampling launch of a
+// call's first step when it is not fused).  With base set (graph capture),
 // s and ks are offsets from the device step number *base, and the force
 // launch advances it by bump.
 static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force, uint64_t s, uint64_t ks,
@@ -974,10 +975,10 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
             refresh_cfg_modes(c);
             if ((s = upload_rho_tiles(c)) != RBE_OK) return s;
         }
-    // one step = four launches: [closing kick of the step before + integrate
-    // + bin + draw modes + structure-factor partials] -> [totals + cell scan]
-    // -> [Fourier force + scatter] -> [real space + LJ (+ the closing half
-    // kick on the last step of the call)].  In list mode, three: [closing
+    // one step on the cell list = four launches: [closing kick of the step
+    // before + integrate + bin + draw modes + structure-factor partials] ->
+    // [totals + cell scan] -> [Fourier force + scatter] -> [real space + LJ
+    // (+ the closing half kick on the last step of the call)].  In list mode, three: [closing
     // kick + integrate + list bookkeeping + partials] -> [totals + next
     // step's modes + binning, cell scan and scatter] -> [Fourier + real space
     // + LJ (+ closing kick on the last step)], where binning, scan and

@@ -194,7 +194,7 @@ struct StageRequest {
     uint64_t sample_step;  // mode sample index
     int integrate, bin, sample, rho;
     const ListStep *list;  // integrate in list mode: update cell-order records, test displacements
-    int kick = 0;          // integrate: first apply the previous step's final half kick (deferred)
+    int kick = 0;          // integrate: first apply the previous step's closing half kick (deferred)
     int mode_split = 1;    // no integration/binning/sampling: split the modes over this many blocks per chunk
 };
 

@@ -8,17 +8,22 @@
 //   a_l = coulomb w_l 2 m_l / (L^2 |m_l|^2),  th_il = 2 pi m_l . r_i / L,
 //   rho_l = C_l + i S_l = sum_j q_j exp(i th_jl)       (eq. 2.7)
 // with w_l = S/p for sampled modes.  Only integer modes and one scalar per
-// mode enter; every phase is formed in double and wrapped to [-1/2, 1/2]
-// revolutions before the single-precision sine/cosine.
+// mode enter.  Single-precision phases are formed exactly from a split of
+// the box fraction (phase_split in rbe_device.h) and fed to the hardware
+// sine/cosine in revolutions; the FP64 path wraps in double.
 //
 // Kernels:
 //   k_sample_exact  draw the modes of every system (standalone call)
 //   k_sample_mh     the paper's Metropolis-Hastings chains
-//   k_stage_rho     [integrate] + [bin] + [draw modes] + structure-factor
-//                   partials per particle chunk  (one launch)
-//   k_mid           structure-factor totals + per-mode force constants, and
-//                   the exclusive scan of the cell counts (one launch)
-//   k_kforce        force pass + [scatter into cell order] (one launch)
+//   k_stage_rho     [closing kick + integrate + list bookkeeping] + [bin] +
+//                   [draw modes] + structure-factor partials per particle
+//                   chunk (one launch; a lean instantiation for launches
+//                   that only compute structure factors)
+//   k_mid           structure-factor totals + per-mode force constants,
+//                   the next step's modes, the exclusive scan of the cell
+//                   counts, and the gated list rebuild (one launch)
+//   k_kforce        force pass + [scatter into cell order]; long mode lists
+//                   split over blocks (grid y) and summed by k_fsum
 //   k_vjp_*         adjoint of the force at a fixed mode sample
 #include <hip/hip_runtime.h>
 

@@ -26,7 +26,8 @@
 // Each lane accumulates its FP32 pair terms exactly (on a fixed grid, see
 // qterm); the nine row sums are added in a fixed order, so the result does not
 // depend on the order of the particles inside a cell (which comes from atomic
-// counters) nor on the path (cell or list pass).  Systems with fewer than three cells per side use all-pairs tiles.
+// counters) nor on the path (cell or list pass).  Systems with fewer than
+// three cells per side use all-pairs tiles.
 //
 // List pass: LPP lanes per particle walk its list in strides of LPP; the
 // LPP partial sums are combined by a fixed butterfly.
@@ -726,7 +727,8 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
 
 // Force pass of one time step: the Fourier force plus the real-space force,
 // on the cell list with list build when the step's rebuild flag is set, else
-// on the list; then the final half kick.
+// on the list; then the closing half kick on the last step of a call.  Tiles
+// are taken in XCD order (xcd_tile).
 template <typename T, int LPP>
 __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
 {
