@@ -158,7 +158,11 @@ int32_t rbe_num_modes(const rbe_ctx *ctx);
  * the 1-D cumulative table of eq. (3.4) per component and redraws the zero
  * vector; the MH sampler follows the paper's Metropolis-Hastings recipe
  * (eq. 3.5) with chains that persist in the context.  modes_out, if not
- * NULL, is device memory [3][M_tot] int32 that receives the modes. */
+ * NULL, is device memory [3][M_tot] int32 that receives the modes.  With
+ * the exact sampler and no modes_out the draw is recorded and made by the
+ * next launch that needs the modes (the structure-factor pass of the next
+ * force, energy or adjoint call draws them itself); the modes are the same
+ * either way. */
 rbe_status rbe_sample_k(rbe_ctx *ctx, uint64_t step, int32_t *modes_out);
 
 /* Make an explicit mode list active for a single-system context: modes is

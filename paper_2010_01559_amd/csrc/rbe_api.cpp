@@ -143,6 +143,11 @@ struct rbe_ctx {
     uint64_t list_gen = 0;         // steps taken in list mode (selects the rebuild flag)
     bool any_mh = false;
     bool fixed = false;            // rbe_step keeps the active mode list
+    // rbe_sample_k with the exact sampler only records the draw; the next
+    // structure-factor launch draws the modes itself (or a sampling launch
+    // runs first where that launch cannot)
+    bool sample_pending = false;
+    uint64_t sample_step = 0;
     LaunchCfg cfg{};
     Workspace w{};
     size_t partial_cap = 0;        // doubles allocated for partial
@@ -707,6 +712,7 @@ rbe_status rbe_reserve_modes(rbe_ctx *c, int32_t cap)
         return RBE_OK;
     };
     drop_graphs(c);
+    c->sample_pending = false;
     const int old_cap = c->mcap;
     c->mcap = cap;
     rbe_status s;
@@ -750,8 +756,14 @@ rbe_status rbe_sample_k(rbe_ctx *c, uint64_t step, int32_t *modes_out)
         refresh_cfg_modes(c);
         if ((s = upload_rho_tiles(c)) != RBE_OK) return s;
     }
-    RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, step, c->any_mh ? 1 : 0));
     c->modes_valid = true;
+    if (!c->any_mh && !modes_out) {
+        c->sample_pending = true;
+        c->sample_step = step;
+        return RBE_OK;
+    }
+    c->sample_pending = false;
+    RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, step, c->any_mh ? 1 : 0));
     if (modes_out) {
         for (int d = 0; d < 3; ++d)
             HIPCHK(c, hipMemcpyAsync(modes_out + (size_t)d * c->mtot, c->w.modes + (size_t)d * c->mcap,
@@ -779,6 +791,7 @@ rbe_status rbe_set_k(rbe_ctx *c, const int32_t *modes, int32_t nm, const double 
         wv[l] = weights ? weights[l] : S / (double)nm;
         if (!std::isfinite(wv[l])) return set_err(c, RBE_ERR_INVALID, "non-finite weight");
     }
+    c->sample_pending = false;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->w.modes, m.data(), sizeof(int32_t) * m.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->w.mode_w, wv.data(), sizeof(double) * nm, hipMemcpyHostToDevice));
@@ -805,10 +818,33 @@ static int mode_split(int blocks, int modes, int modes_per_part)
     return std::max(1, std::min(std::min(want, most), kMaxModeSplit));
 }
 
+// Draw a recorded sample now, with its own launch.
+static rbe_status materialize_sample(rbe_ctx *c)
+{
+    if (!c->sample_pending) return RBE_OK;
+    c->sample_pending = false;
+    RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, c->sample_step, 0));
+    return RBE_OK;
+}
+
 static rbe_status kspace_impl(rbe_ctx *c, const void *pos, const void *q, void *force, int accumulate)
 {
     StageRequest rq{const_cast<void *>(pos), nullptr, nullptr, q, 0, 0, 0, 0, 0, 1};
     rq.mode_split = mode_split(c->cfg.n_rho_tiles, c->max_p, 256);
+    if (c->sample_pending) {
+        int table_lds = 0, tab_max = 0;
+        if (stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max) <= 64 * 1024) {
+            // the staging launch draws the recorded sample (every block the
+            // modes it needs; the first tile of each system stores them)
+            rq.sample = 1;
+            rq.sample_step = c->sample_step;
+            rq.mode_split = 1;
+            c->sample_pending = false;
+        } else {
+            rbe_status st = materialize_sample(c);
+            if (st != RBE_OK) return st;
+        }
+    }
     RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
     RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0));
     const int fblocks = (c->cfg.n_force_tiles * c->cfg.force_split + 3) / 4;
@@ -966,6 +1002,12 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
             return set_err(c, RBE_ERR_INVALID, "all systems of a batch must use one integrator");
     if (c->fixed && !c->modes_valid)
         return set_err(c, RBE_ERR_STATE, "fixed sampler: set the modes with rbe_set_k or rbe_sample_k first");
+    if (c->fixed) {
+        rbe_status st = materialize_sample(c);
+        if (st != RBE_OK) return st;
+    } else if (nsteps > 0) {
+        c->sample_pending = false;   // the first step draws its own modes
+    }
     for (int r = 0; r < c->R && !c->fixed; ++r)
         if (c->sysh[r].p != c->prm[r].p) {
             // explicit modes were set: stepping resamples, so restore p
@@ -1229,6 +1271,10 @@ rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps
     if (!pos || !q) return set_err(c, RBE_ERR_INVALID, "pos and q must be non-NULL");
     if (!c->modes_valid) return set_err(c, RBE_ERR_STATE, "no active modes: call rbe_sample_k or rbe_set_k first");
     if (reps < 1) reps = 10;
+    {
+        rbe_status st = materialize_sample(c);
+        if (st != RBE_OK) return st;
+    }
     const bool prof = c->prof;
     c->prof = false;
     hipEvent_t a, b;

@@ -243,13 +243,17 @@ __device__ __forceinline__ void rho_term(const PartD &v, double mx, double my, d
 constexpr int kRhoGroupsMax = 32;
 constexpr int kRhoUnroll = 8;
 
-// FULL = false compiles a lean variant for launches that only stage the
+// VAR = 0 compiles a lean variant for launches that only stage the
 // particles and compute structure factors (force calls, energies, long
 // Ewald lists): without the integrator, binning, sampling and list code it
-// needs far fewer registers, so more blocks share a compute unit.
-template <typename T, int BS, bool FULL>
-__global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
+// needs far fewer registers, so more blocks share a compute unit.  VAR = 1
+// adds the mode draw (force calls after rbe_sample_k), VAR = 2 is the full
+// time-step variant.
+template <typename T, int BS, int VAR>
+__global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T> a)
 {
+    constexpr bool FULL = VAR == 2;     // integrator, binning, list bookkeeping
+    constexpr bool SAMPLE = VAR >= 1;   // draws the modes in the launch
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = a.tiles[blockIdx.x];
     const SysDev S = a.sys[t.sys];
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
     const int tid = threadIdx.x;
     const int count = t.count;
     const int K = 2 * S.M + 1;
-    if (FULL && a.do_sample && a.table_lds)
+    if (SAMPLE && a.do_sample && a.table_lds)
         for (int k = tid; k < K; k += BS) tab[k] = a.cdf[S.cdf_off + k];
     if (FULL && a.list_mode && blockIdx.x == 0 && tid == 0) {
         // the rebuild of this step (in the totals launch) starts from zero
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(BS) void k_stage_rho(StageArgs<T> a)
         if (tid < Pt && m0 + tid < me) {
             const int l = m0 + tid;
             int mx, my, mz;
-            if (FULL && a.do_sample) {
+            if (SAMPLE && a.do_sample) {
                 sample_mode(tabp, S.M, (uint32_t)l, S.seed, sample_step, mx, my, mz);
                 if (t.aux == 0) {
                     const int o = S.moff + l;
@@ -1144,25 +1148,31 @@ static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const S
     a.table_lds = table_lds;
     a.tab_max = tab_max;
     dim3 g(c.n_rho_tiles, rq.mode_split > 1 ? rq.mode_split : 1);
-    const bool full = rq.integrate || rq.bin || rq.sample || rq.list;
+    const int var = (rq.integrate || rq.bin || rq.list) ? 2 : (rq.sample ? 1 : 0);
     switch (c.rho_block) {
     case 256:
-        if (full)
-            k_stage_rho<T, 256, true><<<g, 256, sm, c.stream>>>(a);
+        if (var == 2)
+            k_stage_rho<T, 256, 2><<<g, 256, sm, c.stream>>>(a);
+        else if (var == 1)
+            k_stage_rho<T, 256, 1><<<g, 256, sm, c.stream>>>(a);
         else
-            k_stage_rho<T, 256, false><<<g, 256, sm, c.stream>>>(a);
+            k_stage_rho<T, 256, 0><<<g, 256, sm, c.stream>>>(a);
         break;
     case 512:
-        if (full)
-            k_stage_rho<T, 512, true><<<g, 512, sm, c.stream>>>(a);
+        if (var == 2)
+            k_stage_rho<T, 512, 2><<<g, 512, sm, c.stream>>>(a);
+        else if (var == 1)
+            k_stage_rho<T, 512, 1><<<g, 512, sm, c.stream>>>(a);
         else
-            k_stage_rho<T, 512, false><<<g, 512, sm, c.stream>>>(a);
+            k_stage_rho<T, 512, 0><<<g, 512, sm, c.stream>>>(a);
         break;
     default:
-        if (full)
-            k_stage_rho<T, 1024, true><<<g, 1024, sm, c.stream>>>(a);
+        if (var == 2)
+            k_stage_rho<T, 1024, 2><<<g, 1024, sm, c.stream>>>(a);
+        else if (var == 1)
+            k_stage_rho<T, 1024, 1><<<g, 1024, sm, c.stream>>>(a);
         else
-            k_stage_rho<T, 1024, false><<<g, 1024, sm, c.stream>>>(a);
+            k_stage_rho<T, 1024, 0><<<g, 1024, sm, c.stream>>>(a);
         break;
     }
     return hipGetLastError();
