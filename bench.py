@@ -58,17 +58,17 @@ PEAK_FP32_TFLOPS = 157.3
 # run), each multiplied by the ratio of the true size of a 256 MiB device
 # copy to what the same counter reads for it.  Valid only for the kernel
 # source it was taken on (sha256 prefix); otherwise reported as null.
-# "stage" is the time-step variant of k_stage_rho, "stage_fourier" the lean
-# variant of force calls.
+# "stage" is the time-step variant of k_stage_rho, "stage_fourier" the
+# variant of force calls that also draws the modes recorded by rbe_sample_k.
 TRAFFIC = {
-    "real": {"fetch_kib": 8325.1, "write_kib": 8310.7, "fetch_scale": 2.0, "write_scale": 1.0,
-             "src": "5e2d1f5476412969"},
-    "stage": {"fetch_kib": 3159.0, "write_kib": 7163.8, "fetch_scale": 2.0, "write_scale": 1.0,
-              "src": "3dcc55258867779c"},
-    "stage_fourier": {"fetch_kib": 889.8, "write_kib": 400.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                      "src": "3dcc55258867779c"},
-    "kforce": {"fetch_kib": 936.4, "write_kib": 1171.9, "fetch_scale": 2.0, "write_scale": 1.0,
-               "src": "3dcc55258867779c"},
+    "real": {"fetch_kib": 8317.1, "write_kib": 8271.4, "fetch_scale": 2.0, "write_scale": 1.0,
+             "src": "7d2b93a63ad7a8f6"},
+    "stage": {"fetch_kib": 3159.1, "write_kib": 7163.5, "fetch_scale": 2.0, "write_scale": 1.0,
+              "src": "8eaf0998b21e5b28"},
+    "stage_fourier": {"fetch_kib": 914.8, "write_kib": 402.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                      "src": "8eaf0998b21e5b28"},
+    "kforce": {"fetch_kib": 940.9, "write_kib": 1171.9, "fetch_scale": 2.0, "write_scale": 1.0,
+               "src": "8eaf0998b21e5b28"},
 }
 
 

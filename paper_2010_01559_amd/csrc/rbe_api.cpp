@@ -833,7 +833,10 @@ static rbe_status kspace_impl(rbe_ctx *c, const void *pos, const void *q, void *
     rq.mode_split = mode_split(c->cfg.n_rho_tiles, c->max_p, 256);
     if (c->sample_pending) {
         int table_lds = 0, tab_max = 0;
-        if (stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max) <= 64 * 1024) {
+        // fused when the launch has at most two blocks per CU: every block
+        // draws the modes it needs, which costs more than one sampling
+        // launch once there are many blocks
+        if (c->cfg.n_rho_tiles <= 512 && stage_lds_bytes(c->cfg, 1, &table_lds, &tab_max) <= 64 * 1024) {
             // the staging launch draws the recorded sample (every block the
             // modes it needs; the first tile of each system stores them)
             rq.sample = 1;
