@@ -695,16 +695,18 @@ hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step
 }
 
 
-template <typename KM>
+// LEAN: the structure-factor totals only (force, energy and adjoint calls).
+template <typename KM, bool LEAN>
 __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
 {
     extern __shared__ double mid_tab[];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.clear_flag) *a.clear_flag = 0;
+    if (!LEAN && blockIdx.x == 0 && threadIdx.x == 0 && a.clear_flag) *a.clear_flag = 0;
     if ((int)blockIdx.x < a.n_final_blocks) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         mid_final<KM>(a, blockIdx.x * 16 + wave);
         return;
     }
+    if constexpr (LEAN) return;
     const int b = blockIdx.x - a.n_final_blocks;
     if (b < a.n_bin_blocks) {
         if (*a.bin_gate == 0) return;
@@ -1249,7 +1251,11 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     const int nb = a.n_final_blocks + a.n_bin_blocks + a.n_sample_blocks + (do_scan ? c.R : 0) +
                    (a.reb ? 1 + a.n_reb_scatter : 0);
     if (nb == 0) return hipSuccess;
-    k_mid<KM><<<nb, 1024, sm, c.stream>>>(a);
+    const bool lean = !do_scan && !a.n_bin_blocks && !a.n_sample_blocks && !a.reb && !clear_flag;
+    if (lean)
+        k_mid<KM, true><<<nb, 1024, sm, c.stream>>>(a);
+    else
+        k_mid<KM, false><<<nb, 1024, sm, c.stream>>>(a);
     return hipGetLastError();
 }
 
