@@ -553,7 +553,9 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     // the block's registers leave room for one 1024-thread block per CU
     g.rho_chunk = (int)std::min<int64_t>(512, std::max<int64_t>(64, ((ntot + 255) / 256 + 7) / 8 * 8));
     g.rho_block = 1024;
-    g.force_split = 4;
+    // waves sharing a 64-particle tile in the force pass: four while the
+    // tiles alone would not fill the chip several times over, two beyond
+    g.force_split = ntot >= 500000 ? 2 : 4;
     g.real_split = 4;
     g.kmax = std::min((kmax + 7) & ~7, 1024);
     g.list_on = 0;
