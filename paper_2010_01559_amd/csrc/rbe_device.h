@@ -217,12 +217,41 @@ __device__ __forceinline__ float phase_split(float mx, float my, float mz, float
 
 // Fourier force of the modes [l0, l1) of one system on one particle, summed
 // in mode order (eq. 3.6 without the factor -q_i).  kk is wave-uniform.
-__device__ __forceinline__ void fourier_range(const KModeF *kk, int l0, int l1, const float h[3], const float lo[3],
+// Mode constants are the same for every lane and do not change while a force
+// launch runs: read them through the constant address space from a
+// wave-uniform pointer, so that they arrive by scalar loads (one per wave)
+// instead of a 64-lane vector load of the same bytes.
+template <typename KM>
+__device__ __forceinline__ const __attribute__((address_space(4))) KM *uniform_modes(const KM *kk)
+{
+    const uint64_t p = (uint64_t)kk;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    return (const __attribute__((address_space(4))) KM *)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename KM>
+__device__ __forceinline__ KM load_mode(const __attribute__((address_space(4))) KM *kk, int l)
+{
+    KM k;
+    for (int d = 0; d < 3; ++d) {
+        k.m[d] = kk[l].m[d];
+        k.a[d] = kk[l].a[d];
+    }
+    k.C = kk[l].C;
+    k.S = kk[l].S;
+    return k;
+}
+
+__device__ __forceinline__ void fourier_range(const KModeF *kk0, int l0, int l1, const float h[3], const float lo[3],
                                               float f[3])
 {
+    const auto kk = uniform_modes(kk0);
+    l0 = __builtin_amdgcn_readfirstlane(l0);
+    l1 = __builtin_amdgcn_readfirstlane(l1);
 #pragma unroll 4
     for (int l = l0; l < l1; ++l) {
-        const KModeF k = kk[l];
+        const KModeF k = load_mode(kk, l);
         const float rf = phase_split(k.m[0], k.m[1], k.m[2], h[0], h[1], h[2], lo[0], lo[1], lo[2]);
         const float sn = __builtin_amdgcn_sinf(rf), cs = __builtin_amdgcn_cosf(rf);
         const float im = cs * k.S - sn * k.C;
@@ -232,11 +261,14 @@ __device__ __forceinline__ void fourier_range(const KModeF *kk, int l0, int l1, 
     }
 }
 
-__device__ __forceinline__ void fourier_range(const KModeD *kk, int l0, int l1, const double s[3], double f[3])
+__device__ __forceinline__ void fourier_range(const KModeD *kk0, int l0, int l1, const double s[3], double f[3])
 {
+    const auto kk = uniform_modes(kk0);
+    l0 = __builtin_amdgcn_readfirstlane(l0);
+    l1 = __builtin_amdgcn_readfirstlane(l1);
 #pragma unroll 2
     for (int l = l0; l < l1; ++l) {
-        const KModeD k = kk[l];
+        const KModeD k = load_mode(kk, l);
         const double ph = wrap_rev(fma(k.m[0], s[0], fma(k.m[1], s[1], k.m[2] * s[2])));
         double sn, cs;
         sincospi(2.0 * ph, &sn, &cs);

@@ -238,6 +238,29 @@ __device__ __forceinline__ void rho_term(const PartD &v, double mx, double my, d
     s = fma(v.q, sn, s);
 }
 
+// Structure factor totals and force constants of mode o:
+//   a_l = coulomb w_l 2 m_l / (L^2 |m_l|^2)   (eq. 3.6 with k = 2 pi m / L).
+template <typename KM>
+__device__ __forceinline__ void make_kmode(const SysDev &S, const int32_t *modes, const double *mode_w, int mcap,
+                                           int o, double c, double s, double *rho, KM *km)
+{
+    rho[2 * o] = c;
+    rho[2 * o + 1] = s;
+    const double mx = modes[o], my = modes[mcap + o], mz = modes[2 * mcap + o];
+    const double m2 = mx * mx + my * my + mz * mz;
+    const double f = S.coulomb * mode_w[o] * 2.0 / (S.L * S.L * m2);
+    KM k;
+    k.m[0] = mx;
+    k.m[1] = my;
+    k.m[2] = mz;
+    k.a[0] = f * mx;
+    k.a[1] = f * my;
+    k.a[2] = f * mz;
+    k.C = c;
+    k.S = s;
+    km[o] = k;
+}
+
 // Particle groups per block are capped so that the zero-charge padding of a
 // chunk (up to 8 records per group) stays small.
 constexpr int kRhoGroupsMax = 32;
@@ -513,33 +536,28 @@ __device__ void mid_final(const MidArgs<KM> &a, int gm)
     const double *base = a.partial + 2 * (int64_t)a.part_off[r];
     const int lane = threadIdx.x & 63;
     double c = 0.0, s = 0.0;
-    for (int t = lane; t < nt; t += 64) {
-        c += base[2 * ((int64_t)t * S.p + l)];
-        s += base[2 * ((int64_t)t * S.p + l) + 1];
+    // lane sums tiles lane, lane + 64, ... in order; eight loads are issued
+    // before they are added, so their latencies overlap
+    for (int t0 = lane; t0 < nt; t0 += 8 * 64) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + 64 * u;
+            if (t < nt) v[u] = *reinterpret_cast<const double2 *>(base + 2 * ((int64_t)t * S.p + l));
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t0 + 64 * u < nt) {
+                c += v[u].x;
+                s += v[u].y;
+            }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         c += __shfl_down(c, off, 64);
         s += __shfl_down(s, off, 64);
     }
-    if (lane == 0) {
-        const int o = S.moff + l;
-        a.rho[2 * o] = c;
-        a.rho[2 * o + 1] = s;
-        const double mx = a.modes[o], my = a.modes[a.mcap + o], mz = a.modes[2 * a.mcap + o];
-        const double m2 = mx * mx + my * my + mz * mz;
-        const double f = S.coulomb * a.mode_w[o] * 2.0 / (S.L * S.L * m2);
-        KM k;
-        k.m[0] = mx;
-        k.m[1] = my;
-        k.m[2] = mz;
-        k.a[0] = f * mx;
-        k.a[1] = f * my;
-        k.a[2] = f * mz;
-        k.C = c;
-        k.S = s;
-        a.km[o] = k;
-    }
+    if (lane == 0) make_kmode<KM>(S, a.modes, a.mode_w, a.mcap, S.moff + l, c, s, a.rho, a.km);
 }
 
 // Exclusive scan of one system's cell counts with 1024 threads.  Cells are
