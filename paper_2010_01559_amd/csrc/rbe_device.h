@@ -367,32 +367,71 @@ __device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i
     }
 }
 
+// What the displacement test of a list system needs besides the new
+// position: the particle's cell-order slot and its record at the last list
+// build (kept as plain words).  Neither depends on the integration, so the
+// caller loads them before it and their latency overlaps the integrator's.
+struct ListRef {
+    int32_t slot;
+    uint32_t w[8];   // the record's words (PackF: 4, PartD: 8)
+};
+
+template <typename T>
+__device__ __forceinline__ void load_list_ref(const SysDev &S, int64_t i, const int32_t *slot_of, const void *ref,
+                                              ListRef &r)
+{
+    r.slot = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r.w[k] = 0;
+    if (S.use_list) {
+        r.slot = slot_of[i];
+        if constexpr (sizeof(T) == 4) {
+            const uint4 v = reinterpret_cast<const uint4 *>(ref)[i];
+            r.w[0] = v.x;
+            r.w[1] = v.y;
+            r.w[2] = v.z;
+            r.w[3] = v.w;
+        } else {
+            const uint4 *p = reinterpret_cast<const uint4 *>(ref) + 2 * i;
+            const uint4 a = p[0], b = p[1];
+            r.w[0] = a.x;
+            r.w[1] = a.y;
+            r.w[2] = a.z;
+            r.w[3] = a.w;
+            r.w[4] = b.x;
+            r.w[5] = b.y;
+            r.w[6] = b.z;
+            r.w[7] = b.w;
+        }
+    }
+}
+
 // Stored record of a particle (original order, and cell order for list
 // systems) and the displacement test against skin/2 since the last build.
 template <typename T>
 __device__ __forceinline__ bool record_update(const SysDev &S, int64_t i, double sx, double sy, double sz, T qi,
-                                              void *packed, void *sorted, const int32_t *slot_of, const void *ref)
+                                              void *packed, void *sorted, const ListRef &lr)
 {
     bool moved = false;
     if constexpr (sizeof(T) == 4) {
         const PackF v{to_fix(sx), to_fix(sy), to_fix(sz), (float)qi};
         reinterpret_cast<PackF *>(packed)[i] = v;
         if (S.use_list) {
-            reinterpret_cast<PackF *>(sorted)[slot_of[i]] = v;
-            const PackF r = reinterpret_cast<const PackF *>(ref)[i];
+            reinterpret_cast<PackF *>(sorted)[lr.slot] = v;
+            const uint32_t rx = lr.w[0], ry = lr.w[1], rz = lr.w[2];
             const double u = 1.0 / 4294967296.0 * S.L;
-            const double dx = (double)(int32_t)(v.x - r.x) * u;
-            const double dy = (double)(int32_t)(v.y - r.y) * u;
-            const double dz = (double)(int32_t)(v.z - r.z) * u;
+            const double dx = (double)(int32_t)(v.x - rx) * u;
+            const double dy = (double)(int32_t)(v.y - ry) * u;
+            const double dz = (double)(int32_t)(v.z - rz) * u;
             moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
         }
     } else {
         const PartD v{sx, sy, sz, (double)qi};
         reinterpret_cast<PartD *>(packed)[i] = v;
         if (S.use_list) {
-            reinterpret_cast<PartD *>(sorted)[slot_of[i]] = v;
-            const PartD r = reinterpret_cast<const PartD *>(ref)[i];
-            double dx = v.x - r.x, dy = v.y - r.y, dz = v.z - r.z;
+            reinterpret_cast<PartD *>(sorted)[lr.slot] = v;
+            auto word2 = [&](int k) { return __hiloint2double((int)lr.w[k + 1], (int)lr.w[k]); };
+            double dx = v.x - word2(0), dy = v.y - word2(2), dz = v.z - word2(4);
             dx = (dx - rint(dx)) * S.L;
             dy = (dy - rint(dy)) * S.L;
             dz = (dz - rint(dz)) * S.L;

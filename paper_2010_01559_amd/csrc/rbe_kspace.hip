@@ -181,9 +181,9 @@ __device__ __forceinline__ void bin_one(const SysDev &S, int64_t i, double sx, d
 // displacement since the last list build against skin/2.
 template <typename T>
 __device__ __forceinline__ bool list_update(const SysDev &S, int64_t i, double sx, double sy, double sz, T qi,
-                                            const StageArgs<T> &a)
+                                            const StageArgs<T> &a, const ListRef &lr)
 {
-    return record_update<T>(S, i, sx, sy, sz, qi, a.packed, a.sorted, a.slot_of, a.ref);
+    return record_update<T>(S, i, sx, sy, sz, qi, a.packed, a.sorted, lr);
 }
 
 // LDS record of the structure-factor pass: fractional coordinates in double
@@ -302,6 +302,11 @@ __global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T>
         const int il = t.start + j;
         const int64_t i = S.off + il;
         double x[3];
+        // single precision loads the list reference before integrating; in
+        // double the extra live registers would spill
+        constexpr bool EARLY = sizeof(T) == 4;
+        ListRef lr;
+        if (FULL && EARLY && a.list_mode) load_list_ref<T>(S, i, a.slot_of, a.ref, lr);
         if (FULL && a.do_integrate) {
             integrate_one<T>(S, il, i, a.ntot, a.pos, a.vel, a.F, step, a.kick != 0, x);
         } else {
@@ -329,7 +334,8 @@ __global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T>
         }
         sp[j] = v;
         if (FULL && a.do_bin) bin_one<T>(S, i, sx, sy, sz, qi, a.count, a.cellid, a.rank, a.packed);
-        if (FULL && a.list_mode) moved |= list_update<T>(S, i, sx, sy, sz, qi, a);
+        if (FULL && !EARLY && a.list_mode) load_list_ref<T>(S, i, a.slot_of, a.ref, lr);
+        if (FULL && a.list_mode) moved |= list_update<T>(S, i, sx, sy, sz, qi, a, lr);
     }
     if (FULL && a.list_mode) {
         // one request per block; block 0 adds the host's and the overflow's
