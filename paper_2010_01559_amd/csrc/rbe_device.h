@@ -309,37 +309,33 @@ __device__ __forceinline__ double step_dt(const SysDev &S, uint64_t n)
 }
 
 template <typename T>
-__device__ __forceinline__ double integrate_comp(const SysDev &S, int d, int64_t i, int64_t ntot, T *pos, T *vel,
-                                                 const T *F, double xi, bool hit, bool kick, double dt,
-                                                 double dt_prev, double c1, double c2)
+__device__ __forceinline__ void integrate_comp(const SysDev &S, T p0, T v0, T f, double xi, bool hit, bool kick,
+                                               double dt, double dt_prev, double c1, double c2, T &p1, T &v1)
 {
-    const int64_t k = d * ntot + i;
     if (S.integrator == RBE_LANGEVIN_BAOAB) {
         const double h = 0.5 * dt;
-        T v0 = vel[k];
         // the previous step's closing half kick, rounded to T as if it had
         // been stored by the force pass
-        if (kick) v0 = (T)fma(0.5 * dt_prev / S.mass, (double)F[k], (double)v0);
-        double v = (double)v0 + h * (double)F[k] / S.mass;      // B
-        double r = (double)pos[k] + h * v;                      // A
+        if (kick) v0 = (T)fma(0.5 * dt_prev / S.mass, (double)f, (double)v0);
+        double v = (double)v0 + h * (double)f / S.mass;         // B
+        double r = (double)p0 + h * v;                          // A
         v = c1 * v + c2 * xi;                                   // O
         r += h * v;                                             // A
         r -= S.L * floor(r * S.invL);
         T rs = (T)r;
         if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
-        pos[k] = rs;
-        vel[k] = (T)v;
-        return (double)rs;
+        p1 = rs;
+        v1 = (T)v;
+        return;
     }
     const double sv = sqrt(S.kT / S.mass);
-    const double v = (double)vel[k] + dt * (double)F[k] / S.mass;
-    double r = (double)pos[k] + dt * v;
+    const double v = (double)v0 + dt * (double)f / S.mass;
+    double r = (double)p0 + dt * v;
     r -= S.L * floor(r * S.invL);
     T rs = (T)r;
     if (rs >= (T)S.L || rs < (T)0) rs = (T)0;
-    pos[k] = rs;
-    vel[k] = (T)(hit ? sv * xi : v);
-    return (double)rs;
+    p1 = rs;
+    v1 = (T)(hit ? sv * xi : v);
 }
 
 // Andersen collision of particle il at step.
@@ -361,9 +357,26 @@ __device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i
         c1 = exp(-S.gamma * dt / S.mass);
         c2 = sqrt((1.0 - c1 * c1) * S.kT / S.mass);
     }
+    // all nine loads first: the stores of one component cannot be proven
+    // apart from the loads of the next
+    T p0[3], v0[3], f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        p0[d] = pos[d * ntot + i];
+        v0[d] = vel[d * ntot + i];
+        f[d] = F[d * ntot + i];
+    }
+    T p1[3], v1[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double xi = noise ? normal_t<T>((uint32_t)il, S.seed, step, d) : 0.0;
-        x[d] = integrate_comp<T>(S, d, i, ntot, pos, vel, F, xi, hit, kick, dt, dt_prev, c1, c2);
+        integrate_comp<T>(S, p0[d], v0[d], f[d], xi, hit, kick, dt, dt_prev, c1, c2, p1[d], v1[d]);
+        x[d] = (double)p1[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        pos[d * ntot + i] = p1[d];
+        vel[d * ntot + i] = v1[d];
     }
 }
 
