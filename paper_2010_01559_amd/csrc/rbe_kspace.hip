@@ -495,39 +495,56 @@ struct MidArgs {
     RebuildArgs rb;
 };
 
-// Cell of a stored record and its atomic rank within the cell.
-template <typename KM>
-__device__ void mid_bin_tile(const MidArgs<KM> &a, int ti)
-{
-    const Tile t = a.part_tiles[ti];
-    const int k = threadIdx.x & 255;
-    if (k >= t.count) return;
-    const SysDev S = a.sys[t.sys];
-    const int64_t i = S.off + t.start + k;
-    int cx, cy, cz;
-    if constexpr (sizeof(KM) == sizeof(KModeF)) {
-        const PackF v = reinterpret_cast<const PackF *>(a.packed)[i];
-        cx = cell_of_fix(v.x, S.nc);
-        cy = cell_of_fix(v.y, S.nc);
-        cz = cell_of_fix(v.z, S.nc);
-    } else {
-        const PartD v = reinterpret_cast<const PartD *>(a.packed)[i];
-        cx = cell_of_frac(v.x, S.nc);
-        cy = cell_of_frac(v.y, S.nc);
-        cz = cell_of_frac(v.z, S.nc);
-    }
-    const int c = S.cell_off + (cz * S.nc + cy) * S.nc + cx;
-    a.cellid[i] = c;
-    a.rank[i] = atomicAdd(&a.count[c], 1);
-}
-
 // Few blocks, each striding over the 256-particle tiles: on the many steps
-// where nothing is binned the launch costs only their dispatch.
+// where nothing is binned the launch costs only their dispatch.  A thread
+// takes up to kRebBatch tiles at once: it loads all their records, then
+// issues all the counter atomics, then stores the cell ids and ranks, so
+// that the memory latencies of its particles overlap instead of adding up.
+constexpr int kRebBatch = 8;
+
 template <typename KM>
 __device__ void mid_bin(const MidArgs<KM> &a, int b)
 {
-    for (int ti = 4 * b + (int)(threadIdx.x >> 8); ti < a.n_part_tiles; ti += 4 * a.n_bin_blocks)
-        mid_bin_tile<KM>(a, ti);
+    const int k = threadIdx.x & 255;
+    const int stride = 4 * a.n_bin_blocks;
+    for (int t0 = 4 * b + (int)(threadIdx.x >> 8); t0 < a.n_part_tiles; t0 += kRebBatch * stride) {
+        int64_t idx[kRebBatch];
+        int cell[kRebBatch];
+#pragma unroll
+        for (int u = 0; u < kRebBatch; ++u) {
+            idx[u] = -1;
+            cell[u] = 0;
+            const int ti = t0 + u * stride;
+            if (ti >= a.n_part_tiles) continue;
+            const Tile t = a.part_tiles[ti];
+            if (k >= t.count) continue;
+            const SysDev &S = a.sys[t.sys];
+            const int64_t i = S.off + t.start + k;
+            int cx, cy, cz;
+            if constexpr (sizeof(KM) == sizeof(KModeF)) {
+                const PackF v = reinterpret_cast<const PackF *>(a.packed)[i];
+                cx = cell_of_fix(v.x, S.nc);
+                cy = cell_of_fix(v.y, S.nc);
+                cz = cell_of_fix(v.z, S.nc);
+            } else {
+                const PartD v = reinterpret_cast<const PartD *>(a.packed)[i];
+                cx = cell_of_frac(v.x, S.nc);
+                cy = cell_of_frac(v.y, S.nc);
+                cz = cell_of_frac(v.z, S.nc);
+            }
+            idx[u] = i;
+            cell[u] = S.cell_off + (cz * S.nc + cy) * S.nc + cx;
+        }
+        int rk[kRebBatch];
+#pragma unroll
+        for (int u = 0; u < kRebBatch; ++u) rk[u] = idx[u] >= 0 ? atomicAdd(&a.count[cell[u]], 1) : 0;
+#pragma unroll
+        for (int u = 0; u < kRebBatch; ++u)
+            if (idx[u] >= 0) {
+                a.cellid[idx[u]] = cell[u];
+                a.rank[idx[u]] = rk[u];
+            }
+    }
 }
 
 
@@ -617,14 +634,25 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
 #pragma unroll
         for (int g = 0; g < kScanChunks; ++g) {
             const int idx = base + g * 4096 + 4 * tid;
-            int run = S.off + carry + gpre[g * 16 + wave] + incl[g] - s[g];
+            const int run = S.off + carry + gpre[g * 16 + wave] + incl[g] - s[g];
+            const int o[4] = {run, run + v[g][0], run + v[g][0] + v[g][1], run + v[g][0] + v[g][1] + v[g][2]};
+            if (idx + 3 < ncell) {
+                // whole groups of four: 16-byte stores (the starts of system
+                // r are shifted by r entries, so they are aligned when r % 4 == 0)
+                *reinterpret_cast<int4 *>(cnt + idx) = make_int4(0, 0, 0, 0);
+                if ((r & 3) == 0) {
+                    *reinterpret_cast<int4 *>(st + idx) = make_int4(o[0], o[1], o[2], o[3]);
+                } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (idx + j < ncell) {
-                    st[idx + j] = run;
-                    run += v[g][j];
-                    cnt[idx + j] = 0;
+                    for (int j = 0; j < 4; ++j) st[idx + j] = o[j];
                 }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (idx + j < ncell) {
+                        st[idx + j] = o[j];
+                        cnt[idx + j] = 0;
+                    }
             }
         }
         carry += gpre[kScanChunks * 16];
@@ -686,22 +714,46 @@ __device__ void rebuild_scan(const RebuildArgs &a)
 }
 
 // Scatter block b of nb: moves records into cell order once the scan is out,
-// and records each particle's slot and list reference record.
+// and records each particle's slot and list reference record.  As in the
+// binning, a thread loads everything for up to kScatBatch tiles before it
+// stores (fewer than there: each holds a whole record).
+constexpr int kScatBatch = 4;
+
 template <typename Rec>
 __device__ void rebuild_scatter(const RebuildArgs &a, int b, int nb)
 {
     if (!block_wait(a.ready, 1, a.flag)) return;
-    for (int ti = 4 * b + (int)(threadIdx.x >> 8); ti < a.n_part_tiles; ti += 4 * nb) {
-        const Tile t = a.part_tiles[ti];
-        const int k = threadIdx.x & 255;
-        if (k >= t.count) continue;
-        const int64_t i = a.sys[t.sys].off + t.start + k;
-        const int slot = a.start[a.cellid[i] + t.sys] + a.rank[i];
-        const Rec v = reinterpret_cast<const Rec *>(a.packed)[i];
-        a.sorted_idx[slot] = (int32_t)i;
-        reinterpret_cast<Rec *>(a.sorted)[slot] = v;
-        a.slot_of[i] = slot;
-        reinterpret_cast<Rec *>(a.ref)[i] = v;
+    const int k = threadIdx.x & 255;
+    const int stride = 4 * nb;
+    for (int t0 = 4 * b + (int)(threadIdx.x >> 8); t0 < a.n_part_tiles; t0 += kScatBatch * stride) {
+        int64_t idx[kScatBatch];
+        int cell[kScatBatch], rk[kScatBatch], sys[kScatBatch];
+        Rec v[kScatBatch];
+#pragma unroll
+        for (int u = 0; u < kScatBatch; ++u) {
+            idx[u] = -1;
+            const int ti = t0 + u * stride;
+            if (ti >= a.n_part_tiles) continue;
+            const Tile t = a.part_tiles[ti];
+            if (k >= t.count) continue;
+            const int64_t i = a.sys[t.sys].off + t.start + k;
+            idx[u] = i;
+            sys[u] = t.sys;
+            cell[u] = a.cellid[i];
+            rk[u] = a.rank[i];
+            v[u] = reinterpret_cast<const Rec *>(a.packed)[i];
+        }
+        int slot[kScatBatch];
+#pragma unroll
+        for (int u = 0; u < kScatBatch; ++u) slot[u] = idx[u] >= 0 ? a.start[cell[u] + sys[u]] + rk[u] : 0;
+#pragma unroll
+        for (int u = 0; u < kScatBatch; ++u)
+            if (idx[u] >= 0) {
+                a.sorted_idx[slot[u]] = (int32_t)idx[u];
+                reinterpret_cast<Rec *>(a.sorted)[slot[u]] = v[u];
+                a.slot_of[idx[u]] = slot[u];
+                reinterpret_cast<Rec *>(a.ref)[idx[u]] = v[u];
+            }
     }
 }
 
