@@ -70,7 +70,14 @@ struct PairE {
 // differently).  This holds while partial sums stay below 2^13 in magnitude,
 // far above the pair forces of these systems; the grid is far below
 // single-precision rounding.
-__device__ __forceinline__ double qterm(float v) { return rint((double)v * 0x1p40); }
+// A pair's force component phi * d on that grid.  In single precision the
+// scale is applied to phi first (a power of two, so (phi 2^40) d rounds to
+// the same float as (phi d) 2^40), and the rounding to an integer is done in
+// single precision, where it is exact: the same values as
+// rint((double)(phi d) * 2^40) with fewer double-precision instructions.
+__device__ __forceinline__ float qphi(float phi) { return phi * 0x1p40f; }
+__device__ __forceinline__ double qphi(double phi) { return phi; }
+__device__ __forceinline__ double qterm(float scaled) { return (double)rintf(scaled); }
 __device__ __forceinline__ double qterm(double v) { return v; }
 template <typename T>
 __device__ __forceinline__ double qscale()
@@ -511,9 +518,10 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
         T dx, dy, dz, r2;
         displacement(pa, pb, geo, dx, dy, dz, r2);
         const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
-        fx += qterm(phi * dx);
-        fy += qterm(phi * dy);
-        fz += qterm(phi * dz);
+        const T ph = qphi(phi);
+        fx += qterm(ph * dx);
+        fy += qterm(ph * dy);
+        fz += qterm(ph * dz);
         if constexpr (ENERGY) ev[2] += 0.5 * (double)(phi * r2);
     }
     if constexpr (ENERGY) {
@@ -583,9 +591,10 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
             T dx, dy, dz, r2;
             displacement(pa, pb, geo, dx, dy, dz, r2);
             const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
-            fx += qterm(phi * dx);
-            fy += qterm(phi * dy);
-            fz += qterm(phi * dz);
+            const T ph = qphi(phi);
+            fx += qterm(ph * dx);
+            fy += qterm(ph * dy);
+            fz += qterm(ph * dz);
             if constexpr (ENERGY) vir += 0.5 * (double)(phi * r2);
             if constexpr (BUILD) {
                 if (pos < la->kmax) la->nbr[(int64_t)pos * a.ntot + slot] = b;
@@ -703,9 +712,10 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
                     T dx, dy, dz, r2;
                     displacement(pa, pb[u], geo, dx, dy, dz, r2);
                     const T phi = pair_phi<false>(pc, (T)pa.q, (T)pb[u].q, r2, e);
-                    fx += qterm(phi * dx);
-                    fy += qterm(phi * dy);
-                    fz += qterm(phi * dz);
+                    const T ph = qphi(phi);
+                    fx += qterm(ph * dx);
+                    fy += qterm(ph * dy);
+                    fz += qterm(ph * dz);
                 }
             }
         }
