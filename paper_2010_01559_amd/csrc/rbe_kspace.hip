@@ -34,6 +34,7 @@
 
 #include "rbe_device.h"
 #include "rbe_internal.h"
+#include "rbe_roles.h"
 
 namespace rbe {
 
@@ -238,29 +239,6 @@ __device__ __forceinline__ void rho_term(const PartD &v, double mx, double my, d
     s = fma(v.q, sn, s);
 }
 
-// Structure factor totals and force constants of mode o:
-//   a_l = coulomb w_l 2 m_l / (L^2 |m_l|^2)   (eq. 3.6 with k = 2 pi m / L).
-template <typename KM>
-__device__ __forceinline__ void make_kmode(const SysDev &S, const int32_t *modes, const double *mode_w, int mcap,
-                                           int o, double c, double s, double *rho, KM *km)
-{
-    rho[2 * o] = c;
-    rho[2 * o + 1] = s;
-    const double mx = modes[o], my = modes[mcap + o], mz = modes[2 * mcap + o];
-    const double m2 = mx * mx + my * my + mz * mz;
-    const double f = S.coulomb * mode_w[o] * 2.0 / (S.L * S.L * m2);
-    KM k;
-    k.m[0] = mx;
-    k.m[1] = my;
-    k.m[2] = mz;
-    k.a[0] = f * mx;
-    k.a[1] = f * my;
-    k.a[2] = f * mz;
-    k.C = c;
-    k.S = s;
-    km[o] = k;
-}
-
 // Particle groups per block are capped so that the zero-charge padding of a
 // chunk (up to 8 records per group) stays small.
 constexpr int kRhoGroupsMax = 32;
@@ -422,341 +400,6 @@ __global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T>
     }
 }
 
-// ---------------------------------------------------------------------------
-// k_mid: independent jobs in one launch.
-//  * final structure factors: one wave per (system, mode) adds the tile
-//    partials in a fixed order and fills the per-mode force constants;
-//  * (gated) binning of a neighbour-list rebuild from the stored records;
-//  * cell scan: one block per system turns the cell counts into global slot
-//    starts (exclusive prefix + S.off) and clears the counts.
-// ---------------------------------------------------------------------------
-// Gated list rebuild inside the totals launch: binning blocks, then one
-// scan block, then scatter blocks, ordered by bounded device flags.
-struct RebuildArgs {
-    const SysDev *sys;
-    int R;
-    const int32_t *gate;
-    int32_t *ready;
-    int32_t *count;
-    int32_t *start;
-    const Tile *part_tiles;
-    int n_part_tiles;
-    const int32_t *cellid;
-    const int32_t *rank;
-    const void *packed;
-    int32_t *sorted_idx;
-    void *sorted;
-    int32_t *slot_of;
-    void *ref;
-    int32_t *overflow;
-    int32_t *builds;
-    int32_t *flag;
-    int32_t *bins_done;     // binning blocks finished (reset by the staging launch)
-    int n_bin;              // binning blocks of the launch
-};
-
-template <typename KM>
-struct MidArgs {
-    const SysDev *sys;
-    int R, max_p;
-    int n_final_blocks;   // blocks doing the structure-factor totals
-    const double *partial;
-    const int32_t *part_off;   // [2R]: partial offsets, then tile counts
-    const int32_t *modes;
-    const double *mode_w;
-    int mcap;
-    double *rho;
-    KM *km;
-    int32_t *count;
-    int32_t *start;
-    int do_scan;
-    const int32_t *scan_gate;   // when set, the scan runs only if *scan_gate != 0
-    // binning of a list rebuild (blocks after the totals), only if *bin_gate != 0
-    const int32_t *bin_gate;
-    int n_bin_blocks;
-    const Tile *part_tiles;
-    int n_part_tiles;
-    const void *packed;
-    int32_t *cellid;
-    int32_t *rank;
-    // the next step's modes (one block per system), and a flag to clear
-    int n_sample_blocks;
-    uint64_t sample_step;
-    const double *cdf;
-    int table_lds;
-    int32_t *modes_next;
-    double *mode_w_next;
-    int32_t *clear_flag;
-    const uint64_t *step_base;   // added to sample_step when set
-    // list rebuild (gated by bin_gate): one scan block and n_reb_scatter
-    // scatter blocks after all the others
-    int reb;
-    int n_reb_scatter;
-    RebuildArgs rb;
-};
-
-// Few blocks, each striding over the 256-particle tiles: on the many steps
-// where nothing is binned the launch costs only their dispatch.  A thread
-// takes up to kRebBatch tiles at once: it loads all their records, then
-// issues all the counter atomics, then stores the cell ids and ranks, so
-// that the memory latencies of its particles overlap instead of adding up.
-constexpr int kRebBatch = 8;
-
-template <typename KM>
-__device__ void mid_bin(const MidArgs<KM> &a, int b)
-{
-    const int k = threadIdx.x & 255;
-    const int stride = 4 * a.n_bin_blocks;
-    for (int t0 = 4 * b + (int)(threadIdx.x >> 8); t0 < a.n_part_tiles; t0 += kRebBatch * stride) {
-        int64_t idx[kRebBatch];
-        int cell[kRebBatch];
-#pragma unroll
-        for (int u = 0; u < kRebBatch; ++u) {
-            idx[u] = -1;
-            cell[u] = 0;
-            const int ti = t0 + u * stride;
-            if (ti >= a.n_part_tiles) continue;
-            const Tile t = a.part_tiles[ti];
-            if (k >= t.count) continue;
-            const SysDev &S = a.sys[t.sys];
-            const int64_t i = S.off + t.start + k;
-            int cx, cy, cz;
-            if constexpr (sizeof(KM) == sizeof(KModeF)) {
-                const PackF v = reinterpret_cast<const PackF *>(a.packed)[i];
-                cx = cell_of_fix(v.x, S.nc);
-                cy = cell_of_fix(v.y, S.nc);
-                cz = cell_of_fix(v.z, S.nc);
-            } else {
-                const PartD v = reinterpret_cast<const PartD *>(a.packed)[i];
-                cx = cell_of_frac(v.x, S.nc);
-                cy = cell_of_frac(v.y, S.nc);
-                cz = cell_of_frac(v.z, S.nc);
-            }
-            idx[u] = i;
-            cell[u] = S.cell_off + (cz * S.nc + cy) * S.nc + cx;
-        }
-        int rk[kRebBatch];
-#pragma unroll
-        for (int u = 0; u < kRebBatch; ++u) rk[u] = idx[u] >= 0 ? atomicAdd(&a.count[cell[u]], 1) : 0;
-#pragma unroll
-        for (int u = 0; u < kRebBatch; ++u)
-            if (idx[u] >= 0) {
-                a.cellid[idx[u]] = cell[u];
-                a.rank[idx[u]] = rk[u];
-            }
-    }
-}
-
-
-template <typename KM>
-__device__ void mid_final(const MidArgs<KM> &a, int gm)
-{
-    const int r = gm / a.max_p, l = gm % a.max_p;
-    if (r >= a.R) return;
-    const SysDev S = a.sys[r];
-    if (l >= S.p) return;
-    const int nt = a.part_off[a.R + r];
-    const double *base = a.partial + 2 * (int64_t)a.part_off[r];
-    const int lane = threadIdx.x & 63;
-    double c = 0.0, s = 0.0;
-    // lane sums tiles lane, lane + 64, ... in order; eight loads are issued
-    // before they are added, so their latencies overlap
-    for (int t0 = lane; t0 < nt; t0 += 8 * 64) {
-        double2 v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = t0 + 64 * u;
-            if (t < nt) v[u] = *reinterpret_cast<const double2 *>(base + 2 * ((int64_t)t * S.p + l));
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (t0 + 64 * u < nt) {
-                c += v[u].x;
-                s += v[u].y;
-            }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        c += __shfl_down(c, off, 64);
-        s += __shfl_down(s, off, 64);
-    }
-    if (lane == 0) make_kmode<KM>(S, a.modes, a.mode_w, a.mcap, S.moff + l, c, s, a.rho, a.km);
-}
-
-// Exclusive scan of one system's cell counts with 1024 threads.  Cells are
-// processed in passes of 8 chunks x 4096; thread t owns cells
-// [base + g*4096 + 4t, +4) of chunk g.  Cell offsets are padded to multiples
-// of 4 so the counts load as int4.
-constexpr int kScanChunks = 8;
-
-__device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
-{
-    __shared__ int wtot[kScanChunks * 16];
-    __shared__ int gpre[kScanChunks * 16 + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int32_t *cnt = count + S.cell_off;
-    int32_t *st = start + S.cell_off + r;
-    const int ncell = S.ncell;
-    int carry = 0;
-    for (int base = 0; base < ncell; base += kScanChunks * 4096) {
-        int v[kScanChunks][4];
-        int s[kScanChunks], incl[kScanChunks];
-#pragma unroll
-        for (int g = 0; g < kScanChunks; ++g) {
-            const int idx = base + g * 4096 + 4 * tid;
-            if (idx + 3 < ncell) {
-                const int4 x = *reinterpret_cast<const int4 *>(cnt + idx);
-                v[g][0] = x.x;
-                v[g][1] = x.y;
-                v[g][2] = x.z;
-                v[g][3] = x.w;
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) v[g][j] = (idx + j < ncell) ? cnt[idx + j] : 0;
-            }
-            s[g] = v[g][0] + v[g][1] + v[g][2] + v[g][3];
-        }
-#pragma unroll
-        for (int g = 0; g < kScanChunks; ++g) {
-            incl[g] = wave_incl_scan(s[g]);
-            if (lane == 63) wtot[g * 16 + wave] = incl[g];
-        }
-        __syncthreads();
-        if (wave == 0) {
-            // exclusive prefix of the 128 wave totals in (chunk, wave) order
-            const int x0 = wtot[2 * lane], x1 = wtot[2 * lane + 1];
-            const int inc = wave_incl_scan(x0 + x1);
-            gpre[2 * lane] = inc - x0 - x1;
-            gpre[2 * lane + 1] = inc - x1;
-            if (lane == 63) gpre[kScanChunks * 16] = inc;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int g = 0; g < kScanChunks; ++g) {
-            const int idx = base + g * 4096 + 4 * tid;
-            const int run = S.off + carry + gpre[g * 16 + wave] + incl[g] - s[g];
-            const int o[4] = {run, run + v[g][0], run + v[g][0] + v[g][1], run + v[g][0] + v[g][1] + v[g][2]};
-            if (idx + 3 < ncell) {
-                // whole groups of four: 16-byte stores (the starts of system
-                // r are shifted by r entries, so they are aligned when r % 4 == 0)
-                *reinterpret_cast<int4 *>(cnt + idx) = make_int4(0, 0, 0, 0);
-                if ((r & 3) == 0) {
-                    *reinterpret_cast<int4 *>(st + idx) = make_int4(o[0], o[1], o[2], o[3]);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) st[idx + j] = o[j];
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (idx + j < ncell) {
-                        st[idx + j] = o[j];
-                        cnt[idx + j] = 0;
-                    }
-            }
-        }
-        carry += gpre[kScanChunks * 16];
-        __syncthreads();
-    }
-    if (tid == 0) st[ncell] = S.off + carry;
-}
-
-// ---------------------------------------------------------------------------
-// List rebuild inside the totals launch (work only when the step's rebuild
-// flag is set).  The binning blocks count their particles into the cells and
-// then each adds one to bins_done; the scan block, which comes after them in
-// block order, waits for all of them, scans every system's counts and raises
-// `ready`; the scatter blocks, last in block order, wait for it and stride
-// over the 256-particle tiles, moving records into cell order.  The launch
-// has a few dozen 1024-thread blocks, all resident at once, and a block only
-// waits for blocks of lower index, so every wait ends; the waits are bounded
-// anyway and raise the error flag if the bound is reached.  The staging
-// launch of each step resets bins_done and ready.
-// ---------------------------------------------------------------------------
-
-// Thread 0 waits (bounded) until *p reaches want; the block learns the
-// outcome.  A timeout sets bit 2 of the error flag.
-__device__ bool block_wait(int32_t *p, int want, int32_t *flag)
-{
-    __shared__ int s_ok;
-    if (threadIdx.x == 0) {
-        int ok = 0;
-        for (int it = 0; it < (1 << 24); ++it) {
-            if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) {
-                ok = 1;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        if (!ok) atomicOr(flag, 2);
-        s_ok = ok;
-    }
-    __syncthreads();
-    __threadfence();
-    return s_ok != 0;
-}
-
-// Scan block of a rebuild: waits for every binning block, turns the cell
-// counts of all systems into slot starts, clears the overflow flag, counts
-// the build and releases the scatter blocks.
-__device__ void rebuild_scan(const RebuildArgs &a)
-{
-    if (!block_wait(a.bins_done, a.n_bin, a.flag)) return;
-    for (int r = 0; r < a.R; ++r) mid_scan(a.sys[r], r, a.count, a.start);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        *a.overflow = 0;
-        *a.builds += 1;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(a.ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Scatter block b of nb: moves records into cell order once the scan is out,
-// and records each particle's slot and list reference record.  As in the
-// binning, a thread loads everything for up to kScatBatch tiles before it
-// stores (fewer than there: each holds a whole record).
-constexpr int kScatBatch = 4;
-
-template <typename Rec>
-__device__ void rebuild_scatter(const RebuildArgs &a, int b, int nb)
-{
-    if (!block_wait(a.ready, 1, a.flag)) return;
-    const int k = threadIdx.x & 255;
-    const int stride = 4 * nb;
-    for (int t0 = 4 * b + (int)(threadIdx.x >> 8); t0 < a.n_part_tiles; t0 += kScatBatch * stride) {
-        int64_t idx[kScatBatch];
-        int cell[kScatBatch], rk[kScatBatch], sys[kScatBatch];
-        Rec v[kScatBatch];
-#pragma unroll
-        for (int u = 0; u < kScatBatch; ++u) {
-            idx[u] = -1;
-            const int ti = t0 + u * stride;
-            if (ti >= a.n_part_tiles) continue;
-            const Tile t = a.part_tiles[ti];
-            if (k >= t.count) continue;
-            const int64_t i = a.sys[t.sys].off + t.start + k;
-            idx[u] = i;
-            sys[u] = t.sys;
-            cell[u] = a.cellid[i];
-            rk[u] = a.rank[i];
-            v[u] = reinterpret_cast<const Rec *>(a.packed)[i];
-        }
-        int slot[kScatBatch];
-#pragma unroll
-        for (int u = 0; u < kScatBatch; ++u) slot[u] = idx[u] >= 0 ? a.start[cell[u] + sys[u]] + rk[u] : 0;
-#pragma unroll
-        for (int u = 0; u < kScatBatch; ++u)
-            if (idx[u] >= 0) {
-                a.sorted_idx[slot[u]] = (int32_t)idx[u];
-                reinterpret_cast<Rec *>(a.sorted)[slot[u]] = v[u];
-                a.slot_of[idx[u]] = slot[u];
-                reinterpret_cast<Rec *>(a.ref)[idx[u]] = v[u];
-            }
-    }
-}
-
 __global__ void k_set_step(uint64_t *base, uint64_t step)
 {
     if (threadIdx.x == 0) *base = step;
@@ -771,6 +414,14 @@ hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step
 }
 
 
+// ---------------------------------------------------------------------------
+// k_mid: independent jobs in one launch (roles in rbe_roles.h), in block
+// order: final structure factors (one wave per (system, mode) adds the tile
+// partials in a fixed order and fills the per-mode force constants); gated
+// binning of a neighbour-list rebuild; the next step's modes (one block per
+// system); then either the gated rebuild's scan and scatter blocks or, for
+// cell-list force calls, one cell-scan block per system.
+// ---------------------------------------------------------------------------
 // LEAN: the structure-factor totals only (force, energy and adjoint calls).
 template <typename KM, bool LEAN>
 __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
@@ -797,24 +448,7 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
     }
     const int b2 = b - a.n_bin_blocks;
     if (b2 < a.n_sample_blocks) {
-        // draw the next step's modes of system b2 (exact sampler)
-        const SysDev S = a.sys[b2];
-        const double *t = a.cdf + S.cdf_off;
-        if (a.table_lds) {
-            for (int k = threadIdx.x; k < 2 * S.M + 1; k += blockDim.x) mid_tab[k] = t[k];
-            __syncthreads();
-            t = mid_tab;
-        }
-        for (int l = threadIdx.x; l < S.p; l += blockDim.x) {
-            int mx, my, mz;
-            sample_mode(t, S.M, (uint32_t)l, S.seed, a.sample_step + (a.step_base ? *a.step_base : 0), mx, my,
-                        mz);
-            const int o = S.moff + l;
-            a.modes_next[o] = mx;
-            a.modes_next[a.mcap + o] = my;
-            a.modes_next[2 * a.mcap + o] = mz;
-            a.mode_w_next[o] = S.S / (double)S.p;
-        }
+        mid_sample<KM>(a, b2, a.table_lds ? mid_tab : nullptr);
         return;
     }
     const int b3 = b2 - a.n_sample_blocks;
@@ -822,14 +456,14 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
         if (*a.bin_gate == 0) return;
         using Rec = typename std::conditional<sizeof(KM) == sizeof(KModeF), PackF, PartD>::type;
         if (b3 == 0)
-            rebuild_scan(a.rb);
+            rebuild_scan<16>(a.rb);
         else
             rebuild_scatter<Rec>(a.rb, b3 - 1, a.n_reb_scatter);
         return;
     }
     if (!a.do_scan) return;
     if (a.scan_gate && *a.scan_gate == 0) return;
-    mid_scan(a.sys[b3], b3, a.count, a.start);
+    mid_scan<16>(a.sys[b3], b3, a.count, a.start);
 }
 
 // ---------------------------------------------------------------------------
