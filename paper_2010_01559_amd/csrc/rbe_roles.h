@@ -195,16 +195,17 @@ __device__ void mid_final(const MidArgs<KM> &a, int gm)
 }
 
 // Exclusive scan of one system's cell counts with NW waves (64 NW threads).
-// Cells are processed in passes of 8 chunks x 256 NW; thread t owns cells
+// Cells are processed in passes of NCH chunks x 256 NW; thread t owns cells
 // [base + g*256 NW + 4t, +4) of chunk g.  Cell offsets are padded to
-// multiples of 4 so the counts load as int4.
+// multiples of 4 so the counts load as int4.  Fewer chunks per pass hold
+// fewer registers.
 constexpr int kScanChunks = 8;
 
-template <int NW>
+template <int NW, int NCH = kScanChunks>
 __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
 {
     constexpr int CH = 256 * NW;              // cells per chunk
-    constexpr int NT = kScanChunks * NW;      // wave totals per pass (at most 128)
+    constexpr int NT = NCH * NW;              // wave totals per pass (at most 128)
     static_assert(NT <= 128, "one wave prefixes the wave totals, two per lane");
     __shared__ int wtot[NT];
     __shared__ int gpre[NT + 1];
@@ -213,11 +214,11 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
     int32_t *st = start + S.cell_off + r;
     const int ncell = S.ncell;
     int carry = 0;
-    for (int base = 0; base < ncell; base += kScanChunks * CH) {
-        int v[kScanChunks][4];
-        int s[kScanChunks], incl[kScanChunks];
+    for (int base = 0; base < ncell; base += NCH * CH) {
+        int v[NCH][4];
+        int s[NCH], incl[NCH];
 #pragma unroll
-        for (int g = 0; g < kScanChunks; ++g) {
+        for (int g = 0; g < NCH; ++g) {
             const int idx = base + g * CH + 4 * tid;
             if (idx + 3 < ncell) {
                 const int4 x = *reinterpret_cast<const int4 *>(cnt + idx);
@@ -232,7 +233,7 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
             s[g] = v[g][0] + v[g][1] + v[g][2] + v[g][3];
         }
 #pragma unroll
-        for (int g = 0; g < kScanChunks; ++g) {
+        for (int g = 0; g < NCH; ++g) {
             incl[g] = wave_incl_scan(s[g]);
             if (lane == 63) wtot[g * NW + wave] = incl[g];
         }
@@ -248,7 +249,7 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
         }
         __syncthreads();
 #pragma unroll
-        for (int g = 0; g < kScanChunks; ++g) {
+        for (int g = 0; g < NCH; ++g) {
             const int idx = base + g * CH + 4 * tid;
             const int run = S.off + carry + gpre[g * NW + wave] + incl[g] - s[g];
             const int o[4] = {run, run + v[g][0], run + v[g][0] + v[g][1], run + v[g][0] + v[g][1] + v[g][2]};
@@ -315,11 +316,11 @@ __device__ bool block_wait(int32_t *p, int want, int32_t *flag)
 // Scan block of a rebuild: waits for every binning block, turns the cell
 // counts of all systems into slot starts, clears the overflow flag, counts
 // the build and releases the scatter blocks.
-template <int NW>
+template <int NW, int NCH = kScanChunks>
 __device__ void rebuild_scan(const RebuildArgs &a)
 {
     if (!block_wait(a.bins_done, a.n_bin, a.flag)) return;
-    for (int r = 0; r < a.R; ++r) mid_scan<NW>(a.sys[r], r, a.count, a.start);
+    for (int r = 0; r < a.R; ++r) mid_scan<NW, NCH>(a.sys[r], r, a.count, a.start);
     __syncthreads();
     if (threadIdx.x == 0) {
         *a.overflow = 0;
@@ -343,23 +344,32 @@ __device__ void rebuild_scatter(const RebuildArgs &a, int b, int nb)
     const int k = threadIdx.x & 255;
     const int tpb = (int)(blockDim.x >> 8);
     const int stride = tpb * nb;
+    // records move as 16-byte words (PackF: one, PartD: two)
+    constexpr int W = (int)(sizeof(Rec) / sizeof(uint4));
     for (int t0 = tpb * b + (int)(threadIdx.x >> 8); t0 < a.n_part_tiles; t0 += kScatBatch * stride) {
-        int64_t idx[kScatBatch];
-        int cell[kScatBatch], rk[kScatBatch], sys[kScatBatch];
-        Rec v[kScatBatch];
+        int idx[kScatBatch], cell[kScatBatch], rk[kScatBatch], sys[kScatBatch];
+        uint4 v[kScatBatch][W];
 #pragma unroll
         for (int u = 0; u < kScatBatch; ++u) {
             idx[u] = -1;
+            sys[u] = 0;
+            cell[u] = 0;
+            rk[u] = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) v[u][q] = make_uint4(0, 0, 0, 0);
             const int ti = t0 + u * stride;
-            if (ti >= a.n_part_tiles) continue;
-            const Tile t = a.part_tiles[ti];
-            if (k >= t.count) continue;
-            const int64_t i = a.sys[t.sys].off + t.start + k;
-            idx[u] = i;
-            sys[u] = t.sys;
-            cell[u] = a.cellid[i];
-            rk[u] = a.rank[i];
-            v[u] = reinterpret_cast<const Rec *>(a.packed)[i];
+            if (ti < a.n_part_tiles) {
+                const Tile t = a.part_tiles[ti];
+                if (k < t.count) {
+                    const int i = a.sys[t.sys].off + t.start + k;
+                    idx[u] = i;
+                    sys[u] = t.sys;
+                    cell[u] = a.cellid[i];
+                    rk[u] = a.rank[i];
+#pragma unroll
+                    for (int q = 0; q < W; ++q) v[u][q] = reinterpret_cast<const uint4 *>(a.packed)[(int64_t)i * W + q];
+                }
+            }
         }
         int slot[kScatBatch];
 #pragma unroll
@@ -367,10 +377,13 @@ __device__ void rebuild_scatter(const RebuildArgs &a, int b, int nb)
 #pragma unroll
         for (int u = 0; u < kScatBatch; ++u)
             if (idx[u] >= 0) {
-                a.sorted_idx[slot[u]] = (int32_t)idx[u];
-                reinterpret_cast<Rec *>(a.sorted)[slot[u]] = v[u];
+                a.sorted_idx[slot[u]] = idx[u];
                 a.slot_of[idx[u]] = slot[u];
-                reinterpret_cast<Rec *>(a.ref)[idx[u]] = v[u];
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    reinterpret_cast<uint4 *>(a.sorted)[(int64_t)slot[u] * W + q] = v[u][q];
+                    reinterpret_cast<uint4 *>(a.ref)[(int64_t)idx[u] * W + q] = v[u][q];
+                }
             }
     }
 }
