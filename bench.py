@@ -145,7 +145,7 @@ def real_space_counts(s, skin):
 def source_sha(name):
     """Hash of a kernel source together with the headers it includes."""
     h = hashlib.sha256()
-    for part in (name, "rbe_device.h", "rbe_internal.h"):
+    for part in (name, "rbe_device.h", "rbe_internal.h", "rbe_roles.h"):
         with open(os.path.join(ROOT, "paper_2010_01559_amd", "csrc", part), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -1,9 +1,8 @@
-// Device roles of the launch that follows the staging launch: structure-
-// factor totals and per-mode force constants, the next step's modes, and the
-// gated neighbour-list rebuild (binning, cell scan, scatter into cell order).
-// They run as blocks of the totals launch (k_mid, 1024 threads) or as the
-// leading blocks of a time step's force launch (256 threads); block-size
-// dependent loops take their shape from blockDim.
+// Device roles of the launch that follows the staging launch (k_mid):
+// structure-factor totals and per-mode force constants, the next step's
+// modes, and the gated neighbour-list rebuild (binning, cell scan, scatter
+// into cell order).  Loops that depend on the block size take their shape
+// from blockDim.
 #pragma once
 
 #include <hip/hip_runtime.h>
