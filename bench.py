@@ -61,14 +61,14 @@ PEAK_FP32_TFLOPS = 157.3
 # "stage" is the time-step variant of k_stage_rho, "stage_fourier" the
 # variant of force calls that also draws the modes recorded by rbe_sample_k.
 TRAFFIC = {
-    "real": {"fetch_kib": 9007.3, "write_kib": 7780.9, "fetch_scale": 2.0, "write_scale": 1.0,
-             "src": "341df9bf38b675c2"},
-    "stage": {"fetch_kib": 3155.1, "write_kib": 7169.6, "fetch_scale": 2.0, "write_scale": 1.0,
-              "src": "e906a2d8d4535959"},
+    "real": {"fetch_kib": 9011.6, "write_kib": 7812.9, "fetch_scale": 2.0, "write_scale": 1.0,
+             "src": "bb2bd7dfd861268b"},
+    "stage": {"fetch_kib": 3155.2, "write_kib": 7168.7, "fetch_scale": 2.0, "write_scale": 1.0,
+              "src": "aefb4ec43f9b949a"},
     "stage_fourier": {"fetch_kib": 916.8, "write_kib": 402.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                      "src": "e906a2d8d4535959"},
+                      "src": "aefb4ec43f9b949a"},
     "kforce": {"fetch_kib": 940.9, "write_kib": 1171.9, "fetch_scale": 2.0, "write_scale": 1.0,
-               "src": "e906a2d8d4535959"},
+               "src": "aefb4ec43f9b949a"},
 }
 
 
