@@ -241,3 +241,32 @@ def test_batched_systems_match_single_oracle():
         assert en[r]["e_kspace"] == pytest.approx(ek, rel=1e-11)
         off += s.n
         moff += s.p
+
+
+@pytest.mark.parametrize("p", [1100, 2500])
+def test_langevin_trajectory_many_modes(p):
+    """More modes than threads in a structure-factor block (1024): the mode
+    loop of the staging launch runs several tiles, and the totals launch and
+    the step's fused Fourier force take long mode lists.  Five BAOAB steps on
+    the neighbour list against the oracle, FP32."""
+    s = W.langevin_electrolyte()
+    s.p = p
+    ctx = make_ctx(s, R.RBE_FP32)
+    P, Q, V, F = device_state(ctx, s)
+    pos, q = rounded(s, R.RBE_FP32)
+    vel = s.vel.astype(np.float32).astype(np.float64)
+    R.rbe_sample_k(ctx, 0)
+    R.rbe_kspace_forces(ctx, P, Q, F)
+    R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
+    sysd = O.make_sys(s.n, s.p, s.L, s.alpha, s.r_cut, s.coulomb, s.lj, s.kT, s.gamma, s.dt, s.mass, s.seed)
+    po, vo = pos.copy(), vel.copy()
+    Fo = O.total_force(sysd, po, q, 0)
+    assert rel_l2(host(F), Fo) <= 1e-5
+    R.rbe_step(ctx, P, V, Q, F, 1, 5)
+    for k in range(1, 6):
+        O.baoab_step(sysd, po, vo, q, Fo, k)
+    dp = host(P) - po
+    dp -= s.L * np.round(dp / s.L)
+    assert np.linalg.norm(dp) / np.linalg.norm(po) <= 2e-4
+    assert rel_l2(host(V), vo) <= 2e-4
+    assert rel_l2(host(F), Fo) <= 1e-2
