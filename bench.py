@@ -351,8 +351,8 @@ def run_suite(path):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build runs on a "
-              f"single MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library runs on a "
+              f"single MI355X and has no multi-GPU sharding", file=sys.stderr)
         sys.exit(2)
     if args.suite:
         run_suite(args.suite)
