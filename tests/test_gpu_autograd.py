@@ -103,3 +103,68 @@ def test_forces_match_plain_calls():
     R.rbe_kspace_forces(ctx, P, Q, F)
     R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
     assert torch.equal(rbe_forces(ctx, P, Q), F)
+
+
+def test_gradient_full_size_fp32_against_oracle():
+    """The differentiable form at its benchmark size (N = 30000 Gaussian
+    charges, P = 200, FP32 forward and adjoint): loss and gradients with
+    respect to all positions and charges against the oracle's
+    vector-Jacobian product."""
+    s = W.gaussian_charge_system()
+    ctx = make_ctx(s, R.RBE_FP32)
+    pos, q = rounded(s, R.RBE_FP32)
+    P = torch.tensor(pos, dtype=torch.float32, device="cuda", requires_grad=True)
+    Q = torch.tensor(q, dtype=torch.float32, device="cuda", requires_grad=True)
+    Fref = torch.as_tensor(np.random.default_rng(21).normal(size=(3, s.n)), dtype=torch.float32, device="cuda")
+    m = torch.zeros((3, s.p), dtype=torch.int32, device="cuda")
+    R.rbe_sample_k(ctx, 5, m)
+    loss = force_matching_loss(ctx, P, Q, Fref)
+    loss.backward()
+    Fo, gqo, gro = _oracle_grads(s, pos, q, m.cpu().numpy(), host(Fref), R.RBE_PART_ALL, s.lj)
+    assert float(loss.detach()) == pytest.approx(((Fo - host(Fref)) ** 2).mean(), rel=1e-5)
+    assert rel_l2(host(P.grad), gro) <= 1e-5
+    assert rel_l2(host(Q.grad), gqo) <= 1e-5
+
+
+def test_gradient_full_size_central_differences():
+    """FP64 at N = 30000, P = 200: autograd against central differences of
+    the GPU loss with h = 1e-4 on 64 random particles (charge and one
+    position component each; particles with a partner within 4h of the
+    cutoff sphere are skipped)."""
+    s = W.gaussian_charge_system()
+    ctx = make_ctx(s, R.RBE_FP64)
+    P = torch.tensor(s.pos, device="cuda", requires_grad=True)
+    Q = torch.tensor(s.q, device="cuda", requires_grad=True)
+    Fref = torch.as_tensor(np.random.default_rng(22).normal(size=(3, s.n)), device="cuda")
+    R.rbe_sample_k(ctx, 5)
+    loss = force_matching_loss(ctx, P, Q, Fref)
+    loss.backward()
+    gP, gQ = host(P.grad), host(Q.grad)
+
+    def L_of(pp, qq):
+        with torch.no_grad():
+            return float(force_matching_loss(ctx, pp, qq, Fref))
+
+    h = 1e-4
+    worst = 0.0
+    checked = 0
+    for i in np.random.default_rng(23).choice(s.n, 64, replace=False):
+        d = s.pos - s.pos[:, i:i + 1]
+        d -= s.L * np.round(d / s.L)
+        r = np.sqrt((d * d).sum(0))
+        if np.any(np.abs(r - s.r_cut) < 4 * h):
+            continue
+        qp, qm = Q.detach().clone(), Q.detach().clone()
+        qp[i] += h
+        qm[i] -= h
+        fq = (L_of(P.detach(), qp) - L_of(P.detach(), qm)) / (2 * h)
+        pp, pm = P.detach().clone(), P.detach().clone()
+        pp[0, i] += h
+        pm[0, i] -= h
+        fx = (L_of(pp, Q.detach()) - L_of(pm, Q.detach())) / (2 * h)
+        scale = max(np.abs(gQ).max(), np.abs(gP).max())
+        worst = max(worst, abs(fq - gQ[i]) / scale, abs(fx - gP[0, i]) / scale)
+        checked += 1
+    print(f"worst central-difference deviation {worst:.2e} of the largest gradient entry; {checked} particles")
+    assert checked >= 48
+    assert worst <= 1e-7
