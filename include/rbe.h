@@ -251,8 +251,8 @@ rbe_status rbe_set_dt(rbe_ctx *ctx, double dt, double anneal);
  * g_++, g_+- behind the charge-charge correlation rho(r) = g_++ - g_+-).
  * Adds to counts (device, int64 [R][3][nbins]) the number of pairs i < j of
  * each system at minimum-image distance r < r_max, in bin floor(r / dr) with
- * dr = r_max / nbins (decided exactly: the largest b with (b dr)^2 <= r^2,
- * r^2 from the wrapped displacement with fused multiply-adds in FP64), by
+ * dr = r_max / nbins (r = sqrt(dx^2 + dy^2 + dz^2) of the minimum-image
+ * displacement in FP64, each operation rounded on its own), by
  * class: 0 both q > 0, 1 one of each sign, 2 both q <= 0.  pos, q: the
  * context's precision, original order.  All pairs are visited (O(N^2) per
  * system): an analysis call, not a time-step kernel.  RBE_ERR_INVALID unless

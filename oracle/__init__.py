@@ -41,7 +41,7 @@ class OracleSys(C.Structure):
                 ("rc", C.c_double), ("coulomb", C.c_double), ("lj_eps", C.c_double),
                 ("lj_sigma", C.c_double), ("lj_rc", C.c_double), ("kT", C.c_double),
                 ("gamma", C.c_double), ("dt", C.c_double), ("mass", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("diam", C.c_void_p), ("n_fixed", C.c_int)]
 
 
 _lib = None
@@ -95,6 +95,10 @@ def lib():
         L.oracle_real_force.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                         C.c_double, C.c_double, C.c_double, C.c_int, C.c_void_p, _dp,
                                         C.c_void_p, C.c_void_p]
+        L.oracle_real_force_ex.restype = None
+        L.oracle_real_force_ex.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int,
+                                           C.c_void_p, _dp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_rbe_force_variance.restype = None
         L.oracle_rbe_force_variance.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_double,
                                                 C.c_int, _ip, _dp, C.c_int, _ip, _dp]
@@ -252,8 +256,16 @@ def ewald_modes(alpha, L, mmax2):
 
 # -- real space ------------------------------------------------------------------
 
-def real_force(pos, q, L, alpha, rc, coulomb=1.0, lj=(0.0, 1.0, 2.5), idx=None):
-    """Returns (F [3,nsub], e_real [nsub], e_lj [nsub])."""
+def real_force(pos, q, L, alpha, rc, coulomb=1.0, lj=(0.0, 1.0, 2.5), idx=None, diam=None, cells=False,
+               virial=False):
+    """Real-space Coulomb + shifted LJ (eq. 2.11 second term, eq. 4.1).
+
+    Returns (F [3,nsub], e_real [nsub], e_lj [nsub]) -- half pair energies per
+    listed particle -- plus the half pair virials [nsub] when ``virial``.
+    ``diam``: per-particle diameters (r_off = (d_i + d_j)/2 - sigma), or None.
+    ``cells``: use the linked-cell list instead of the direct sum (same
+    result up to summation order when three or more cells fit).
+    """
     pos, q = _f64(pos), _f64(q)
     n = q.shape[0]
     if idx is None:
@@ -261,11 +273,16 @@ def real_force(pos, q, L, alpha, rc, coulomb=1.0, lj=(0.0, 1.0, 2.5), idx=None):
     else:
         idx = _i32(idx)
         nsub, ip = idx.shape[0], idx.ctypes.data
+    dp = None
+    if diam is not None:
+        diam = _f64(diam)
+        assert diam.shape == (n,)
+        dp = diam.ctypes.data
     F = np.zeros((3, nsub))
-    er, el = np.zeros(nsub), np.zeros(nsub)
-    lib().oracle_real_force(n, pos, q, L, alpha, rc, coulomb, lj[0], lj[1], lj[2], nsub, ip, F,
-                            er.ctypes.data, el.ctypes.data)
-    return F, er, el
+    er, el, vr = np.zeros(nsub), np.zeros(nsub), np.zeros(nsub)
+    lib().oracle_real_force_ex(n, pos, q, L, alpha, rc, coulomb, lj[0], lj[1], lj[2], dp, 1 if cells else 0,
+                               nsub, ip, F, er.ctypes.data, el.ctypes.data, vr.ctypes.data)
+    return (F, er, el, vr) if virial else (F, er, el)
 
 
 def rbe_force_variance(pos, q, L, alpha, p, ewald_mmax2, idx, coulomb=1.0):
@@ -280,8 +297,15 @@ def rbe_force_variance(pos, q, L, alpha, p, ewald_mmax2, idx, coulomb=1.0):
 # -- dynamics ---------------------------------------------------------------------
 
 def make_sys(n, p, L, alpha, rc, coulomb=1.0, lj=(0.0, 1.0, 2.5), kT=1.0, gamma=1.0, dt=1e-3, mass=1.0,
-             seed=0):
-    return OracleSys(n, p, L, alpha, rc, coulomb, lj[0], lj[1], lj[2], kT, gamma, dt, mass, seed)
+             seed=0, diam=None, n_fixed=0):
+    """Oracle system; ``diam`` (per-particle diameters) is kept alive on the
+    returned structure."""
+    s = OracleSys(n, p, L, alpha, rc, coulomb, lj[0], lj[1], lj[2], kT, gamma, dt, mass, seed, None, n_fixed)
+    if diam is not None:
+        s._diam = _f64(diam)
+        assert s._diam.shape == (n,)
+        s.diam = s._diam.ctypes.data
+    return s
 
 
 def langevin_normals(seed, step, i):

@@ -454,7 +454,7 @@ int oracle_ewald_modes(double alpha, double L, int mmax2, int32_t *modes, double
 
 /* ------------------------------------------------------------------------ */
 /* Real space: eq. (2.9) third term and eq. (2.11) second term; shifted      */
-/* Lennard-Jones of eq. (4.1) with r_off = 0.                                */
+/* Lennard-Jones of eq. (4.1) with r_off = (d_i + d_j)/2 - sigma.            */
 /* ------------------------------------------------------------------------ */
 
 /* G(r) of eq. (2.11). */
@@ -464,63 +464,210 @@ static double orc_G(double r, double alpha)
     return erfc(b * r) / (r * r) + 2.0 * b * exp(-alpha * r * r) / (sqrt(ORC_PI) * r);
 }
 
-/* Shifted LJ energy and dV/dr at distance r (r_off = 0). */
-static void orc_lj(double r, double eps, double sig, double rc, double *V, double *dV)
+/* Shifted LJ of eq. (4.1) at centre distance r with offset roff:
+ * s = r - roff, V = 4 eps ((sig/s)^12 - (sig/s)^6) + V_shift for s < rc,
+ * V_shift chosen so that V = 0 at s = rc.  *V is the energy, *dV = dV/dr. */
+static void orc_lj(double r, double roff, double eps, double sig, double rc, double *V, double *dV)
 {
-    double sr6 = pow(sig / r, 6.0), sr12 = sr6 * sr6;
+    double s = r - roff;
+    double sr6 = pow(sig / s, 6.0), sr12 = sr6 * sr6;
     double sc6 = pow(sig / rc, 6.0), sc12 = sc6 * sc6;
     *V = 4.0 * eps * (sr12 - sr6) - 4.0 * eps * (sc12 - sc6);
-    *dV = 4.0 * eps * (-12.0 * sr12 + 6.0 * sr6) / r;
+    *dV = 4.0 * eps * (-12.0 * sr12 + 6.0 * sr6) / s;
 }
 
-/* Real-space Coulomb (erfc) plus shifted LJ forces and energies on the
- * particles listed in idx (all particles when idx is NULL, nsub = n).
- * Every periodic image n with |r_ij + nL| <= rc contributes to the Coulomb
- * part (eq. 2.9); LJ acts for |r_ij + nL| < lj_rc when lj_eps != 0.  Fsub is
- * [3][nsub]; e_real[i]/e_lj[i] (optional) get half of particle i's pair
- * energies so that their sums are the total energies. */
-void oracle_real_force(int n, const double *pos, const double *q, double L, double alpha, double rc,
-                       double coulomb, double lj_eps, double lj_sigma, double lj_rc,
-                       int nsub, const int32_t *idx, double *Fsub, double *e_real, double *e_lj)
+/* Parameters of the real-space sum. */
+typedef struct {
+    double L, alpha, rc, coulomb, lj_eps, lj_sigma, lj_rc;
+    const double *diam;   /* per-particle diameters d_i, or NULL (d_i = sigma, r_off = 0) */
+} orc_rs;
+
+/* r_off of eq. (4.1) for the pair (i, j). */
+static double orc_roff(const orc_rs *P, int i, int j)
 {
-    double rmax = rc > lj_rc ? rc : lj_rc;
-    /* images other than the minimum one lie at least L/2 away per axis */
+    return P->diam ? 0.5 * (P->diam[i] + P->diam[j]) - P->lj_sigma : 0.0;
+}
+
+/* Largest centre distance at which some pair still interacts. */
+static double orc_rmax(const orc_rs *P, int n)
+{
+    double rm = P->rc;
+    if (P->lj_eps != 0.0) {
+        double d1 = P->lj_sigma, d2 = P->lj_sigma;   /* two largest diameters */
+        if (P->diam) {
+            d1 = d2 = -1e300;
+            for (int i = 0; i < n; ++i) {
+                if (P->diam[i] > d1) { d2 = d1; d1 = P->diam[i]; }
+                else if (P->diam[i] > d2) d2 = P->diam[i];
+            }
+            if (n < 2) d2 = d1;
+        }
+        double rl = 0.5 * (d1 + d2) - P->lj_sigma + P->lj_rc;
+        if (rl > rm) rm = rl;
+    }
+    return rm;
+}
+
+/* One image of the pair (i, j) at displacement d = r_j - r_i + nL, |d| = r:
+ * adds the force on i (coefficient times d), half the pair energies and
+ * half of r_ij . F_ij (the pair virial).  Coulomb acts for r <= rc
+ * (eq. 2.9), LJ for r - r_off < lj_rc (eq. 4.1). */
+static void orc_pair(const orc_rs *P, const double *q, int i, int j, double dx, double dy, double dz, double r,
+                     double f[3], double *ur, double *ul, double *vir)
+{
+    double c = 0.0;
+    if (r <= P->rc) {
+        c += -P->coulomb * q[i] * q[j] * orc_G(r, P->alpha) / r;
+        *ur += 0.5 * P->coulomb * q[i] * q[j] * erfc(sqrt(P->alpha) * r) / r;
+    }
+    if (P->lj_eps != 0.0) {
+        double roff = orc_roff(P, i, j);
+        if (r - roff < P->lj_rc) {
+            double V, dV;
+            orc_lj(r, roff, P->lj_eps, P->lj_sigma, P->lj_rc, &V, &dV);
+            c += dV / r;
+            *ul += 0.5 * V;
+        }
+    }
+    f[0] += c * dx;
+    f[1] += c * dy;
+    f[2] += c * dz;
+    *vir += 0.5 * c * r * r;
+}
+
+/* Minimum-image displacement r_j - r_i. */
+static void orc_min_image(const double *pos, int n, int i, int j, double L, double d[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[a * n + j] - pos[a * n + i];
+        d[a] = x - L * floor(x / L + 0.5);
+    }
+}
+
+/* Every image within reach, O(N^2) per listed particle.  Images other than
+ * the minimum one lie at least L/2 away per axis, so for rmax < L/2 only the
+ * minimum image is visited. */
+static void orc_real_direct(int n, const double *pos, const double *q, const orc_rs *P, int nsub,
+                            const int32_t *idx, double *Fsub, double *e_real, double *e_lj, double *vir)
+{
+    double L = P->L, rmax = orc_rmax(P, n);
     int nimg = rmax < 0.5 * L ? 0 : (int)ceil(rmax / L) + 1;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int t = 0; t < nsub; ++t) {
         int i = idx ? idx[t] : t;
-        double fx = 0, fy = 0, fz = 0, ur = 0, ul = 0;
+        double f[3] = {0, 0, 0}, ur = 0, ul = 0, w = 0;
         for (int j = 0; j < n; ++j) {
-            double dx0 = pos[j] - pos[i], dy0 = pos[n + j] - pos[n + i], dz0 = pos[2 * n + j] - pos[2 * n + i];
-            /* start from the minimum image and scan the surrounding images */
-            dx0 -= L * floor(dx0 / L + 0.5);
-            dy0 -= L * floor(dy0 / L + 0.5);
-            dz0 -= L * floor(dz0 / L + 0.5);
+            double d0[3];
+            orc_min_image(pos, n, i, j, L, d0);
             for (int a = -nimg; a <= nimg; ++a)
                 for (int b = -nimg; b <= nimg; ++b)
                     for (int c = -nimg; c <= nimg; ++c) {
                         if (j == i && a == 0 && b == 0 && c == 0) continue;
-                        double dx = dx0 + a * L, dy = dy0 + b * L, dz = dz0 + c * L;
-                        double r2 = dx * dx + dy * dy + dz * dz;
-                        double r = sqrt(r2);
-                        if (r <= rc) {
-                            double g = orc_G(r, alpha);
-                            double f = -coulomb * q[i] * q[j] * g / r;
-                            fx += f * dx; fy += f * dy; fz += f * dz;
-                            ur += 0.5 * coulomb * q[i] * q[j] * erfc(sqrt(alpha) * r) / r;
-                        }
-                        if (lj_eps != 0.0 && r < lj_rc) {
-                            double V, dV;
-                            orc_lj(r, lj_eps, lj_sigma, lj_rc, &V, &dV);
-                            fx += dV * dx / r; fy += dV * dy / r; fz += dV * dz / r;
-                            ul += 0.5 * V;
-                        }
+                        double dx = d0[0] + a * L, dy = d0[1] + b * L, dz = d0[2] + c * L;
+                        double r = sqrt(dx * dx + dy * dy + dz * dz);
+                        if (r > rmax) continue;
+                        orc_pair(P, q, i, j, dx, dy, dz, r, f, &ur, &ul, &w);
                     }
         }
-        Fsub[t] = fx; Fsub[nsub + t] = fy; Fsub[2 * nsub + t] = fz;
+        Fsub[t] = f[0]; Fsub[nsub + t] = f[1]; Fsub[2 * nsub + t] = f[2];
         if (e_real) e_real[t] = ur;
         if (e_lj) e_lj[t] = ul;
+        if (vir) vir[t] = w;
     }
+}
+
+/* Linked-cell list (a neighbour search of our own; the paper only says the
+ * real-space sum is local): nc^3 cells of side L/nc >= rmax, nc >= 3, so the
+ * 27 cells around a particle's cell are distinct and hold every partner
+ * within rmax (minimum image, rmax <= L/3).  head[c] is the first particle
+ * of cell c, next[i] the one after i. */
+static void orc_real_cells(int n, const double *pos, const double *q, const orc_rs *P, int nc, int nsub,
+                           const int32_t *idx, double *Fsub, double *e_real, double *e_lj, double *vir)
+{
+    double L = P->L, rmax = orc_rmax(P, n);
+    int ncell = nc * nc * nc;
+    int *head = (int *)malloc(sizeof(int) * ncell);
+    int *next = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int *cell = (int *)malloc(sizeof(int) * 3 * (n > 0 ? n : 1));
+    for (int c = 0; c < ncell; ++c) head[c] = -1;
+    for (int i = n - 1; i >= 0; --i) {
+        int cc[3];
+        for (int a = 0; a < 3; ++a) {
+            double s = pos[a * n + i] / L;
+            s -= floor(s);
+            int k = (int)(s * nc);
+            cc[a] = k < 0 ? 0 : (k >= nc ? nc - 1 : k);
+            cell[3 * i + a] = cc[a];
+        }
+        int c = (cc[2] * nc + cc[1]) * nc + cc[0];
+        next[i] = head[c];
+        head[c] = i;
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int t = 0; t < nsub; ++t) {
+        int i = idx ? idx[t] : t;
+        double f[3] = {0, 0, 0}, ur = 0, ul = 0, w = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int cx = (cell[3 * i] + dx + nc) % nc, cy = (cell[3 * i + 1] + dy + nc) % nc,
+                        cz = (cell[3 * i + 2] + dz + nc) % nc;
+                    for (int j = head[(cz * nc + cy) * nc + cx]; j >= 0; j = next[j]) {
+                        if (j == i) continue;
+                        double d[3];
+                        orc_min_image(pos, n, i, j, L, d);
+                        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                        if (r > rmax) continue;
+                        orc_pair(P, q, i, j, d[0], d[1], d[2], r, f, &ur, &ul, &w);
+                    }
+                }
+        Fsub[t] = f[0]; Fsub[nsub + t] = f[1]; Fsub[2 * nsub + t] = f[2];
+        if (e_real) e_real[t] = ur;
+        if (e_lj) e_lj[t] = ul;
+        if (vir) vir[t] = w;
+    }
+    free(head);
+    free(next);
+    free(cell);
+}
+
+/* Cells per box side for the linked-cell list, or 0 when fewer than three
+ * cells of side >= rmax fit (the direct sum is used then). */
+static int orc_cells_per_side(const orc_rs *P, int n)
+{
+    double rmax = orc_rmax(P, n);
+    int nc = (int)floor(P->L / rmax);
+    if (nc > 256) nc = 256;
+    return nc >= 3 ? nc : 0;
+}
+
+/* Real-space Coulomb (erfc) plus shifted LJ forces, half pair energies and
+ * half pair virials r_ij . F_ij on the particles listed in idx (all
+ * particles when idx is NULL, nsub = n).  Every periodic image within the
+ * cutoffs counts.  method 0: the O(N^2) direct sum; 1: the linked-cell list
+ * (falls back to the direct sum when fewer than three cells fit).  diam is
+ * NULL or the per-particle diameters of eq. (4.1).  Fsub is [3][nsub];
+ * e_real, e_lj and vir are optional [nsub]. */
+void oracle_real_force_ex(int n, const double *pos, const double *q, double L, double alpha, double rc,
+                          double coulomb, double lj_eps, double lj_sigma, double lj_rc, const double *diam,
+                          int method, int nsub, const int32_t *idx, double *Fsub, double *e_real, double *e_lj,
+                          double *vir)
+{
+    orc_rs P = {L, alpha, rc, coulomb, lj_eps, lj_sigma, lj_rc, diam};
+    int nc = method == 1 ? orc_cells_per_side(&P, n) : 0;
+    if (nc)
+        orc_real_cells(n, pos, q, &P, nc, nsub, idx, Fsub, e_real, e_lj, vir);
+    else
+        orc_real_direct(n, pos, q, &P, nsub, idx, Fsub, e_real, e_lj, vir);
+}
+
+/* The direct sum without diameters (r_off = 0). */
+void oracle_real_force(int n, const double *pos, const double *q, double L, double alpha, double rc,
+                       double coulomb, double lj_eps, double lj_sigma, double lj_rc,
+                       int nsub, const int32_t *idx, double *Fsub, double *e_real, double *e_lj)
+{
+    oracle_real_force_ex(n, pos, q, L, alpha, rc, coulomb, lj_eps, lj_sigma, lj_rc, NULL, 0, nsub, idx, Fsub,
+                         e_real, e_lj, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -592,6 +739,8 @@ typedef struct {
     double lj_eps, lj_sigma, lj_rc;
     double kT, gamma, dt, mass;
     uint64_t seed;
+    const double *diam;   /* per-particle diameters of eq. (4.1), or NULL */
+    int n_fixed;          /* particles 0 .. n_fixed-1 do not move (e.g. the colloid of Sec. 4.2) */
 } oracle_sys;
 
 /* Total force used inside the MD loop: random batch Fourier part with the
@@ -606,8 +755,8 @@ void oracle_total_force(const oracle_sys *s, const double *pos, const double *q,
     oracle_sample_modes(s->alpha, s->L, p, s->seed, step, modes);
     oracle_rbe_weights(s->alpha, s->L, p, w);
     oracle_kspace_force(n, pos, q, s->L, p, modes, w, s->coulomb, F);
-    oracle_real_force(n, pos, q, s->L, s->alpha, s->rc, s->coulomb, s->lj_eps, s->lj_sigma, s->lj_rc,
-                      n, NULL, Fr, NULL, NULL);
+    oracle_real_force_ex(n, pos, q, s->L, s->alpha, s->rc, s->coulomb, s->lj_eps, s->lj_sigma, s->lj_rc, s->diam,
+                         1, n, NULL, Fr, NULL, NULL, NULL);
     for (int k = 0; k < 3 * n; ++k) F[k] += Fr[k];
     free(modes); free(w); free(Fr);
 }
@@ -621,7 +770,7 @@ void oracle_baoab_step(const oracle_sys *s, double *pos, double *vel, const doub
     double h = 0.5 * s->dt;
     double c1 = exp(-s->gamma * s->dt / s->mass);
     double c2 = sqrt((1.0 - c1 * c1) * s->kT / s->mass);
-    for (int i = 0; i < n; ++i) {
+    for (int i = s->n_fixed; i < n; ++i) {
         double xi[3];
         oracle_langevin_normals(s->seed, step, i, xi);
         for (int d = 0; d < 3; ++d) {
@@ -636,7 +785,8 @@ void oracle_baoab_step(const oracle_sys *s, double *pos, double *vel, const doub
         }
     }
     oracle_total_force(s, pos, q, step, F);
-    for (int k = 0; k < 3 * n; ++k) vel[k] += h * F[k] / s->mass; /* B */
+    for (int d = 0; d < 3; ++d)
+        for (int i = s->n_fixed; i < n; ++i) vel[d * n + i] += h * F[d * n + i] / s->mass; /* B */
 }
 
 /* Andersen thermostat with the leapfrog scheme (Sec. 3.1, loop body (1)-(3)):
@@ -651,7 +801,7 @@ void oracle_leapfrog_andersen_step(const oracle_sys *s, double nu, double *pos, 
 {
     int n = s->n;
     double dt = s->dt;
-    for (int i = 0; i < n; ++i) {
+    for (int i = s->n_fixed; i < n; ++i) {
         for (int d = 0; d < 3; ++d) {
             double v = vel[d * n + i] + dt * F[d * n + i] / s->mass;
             double r = pos[d * n + i] + dt * v;
@@ -838,7 +988,7 @@ void oracle_pair_virial(int n, const double *pos, const double *q, double L, dou
                         if (r <= rc) wr += 0.5 * (-coulomb * q[i] * q[j] * orc_G(r, alpha) * r);
                         if (lj_eps != 0.0 && r < lj_rc) {
                             double V, dV;
-                            orc_lj(r, lj_eps, lj_sigma, lj_rc, &V, &dV);
+                            orc_lj(r, 0.0, lj_eps, lj_sigma, lj_rc, &V, &dV);
                             /* F_ij = dV/dr r_ij / r: r_ij . F_ij = r dV/dr */
                             wl += 0.5 * r * dV;
                         }
@@ -873,10 +1023,10 @@ double oracle_kspace_virial(int n, const double *pos, const double *q, double L,
 
 /* Counts of unordered pairs i < j (minimum image, r_max <= L/2) by distance
  * bin of width dr = r_max / nbins and by charge class: 0 both q > 0, 1 one
- * of each, 2 both q <= 0.  counts is [3][nbins], added to.  The bin of a
- * pair is the largest b with (b dr)^2 <= r^2 (the wrap and r^2 written with
- * fused multiply-adds), so that the decision rests on correctly rounded
- * operations only; pairs with r >= r_max are not counted. */
+ * of each, 2 both q <= 0.  counts is [3][nbins], added to.  A pair at
+ * distance r < r_max falls in bin floor(r / dr) (the definition of a
+ * histogram of g(r), Sec. 4.1), with r = sqrt(dx^2 + dy^2 + dz^2) from the
+ * minimum-image displacement, every operation rounded on its own. */
 void oracle_pair_histogram(int n, const double *pos, const double *q, double L, double r_max, int nbins,
                            int64_t *counts)
 {
@@ -884,12 +1034,12 @@ void oracle_pair_histogram(int n, const double *pos, const double *q, double L, 
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j) {
             double dx = pos[j] - pos[i], dy = pos[n + j] - pos[n + i], dz = pos[2 * n + j] - pos[2 * n + i];
-            dx = fma(-L, rint(dx / L), dx);
-            dy = fma(-L, rint(dy / L), dy);
-            dz = fma(-L, rint(dz / L), dz);
-            double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            int b = 0;
-            while (b < nbins && ((b + 1) * dr) * ((b + 1) * dr) <= r2) ++b;
+            dx = dx - L * rint(dx / L);
+            dy = dy - L * rint(dy / L);
+            dz = dz - L * rint(dz / L);
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(r < r_max)) continue;
+            int b = (int)floor(r / dr);
             if (b >= nbins) continue;
             int cls = 2 - ((q[i] > 0.0) + (q[j] > 0.0));
             counts[(int64_t)cls * nbins + b] += 1;

@@ -6,9 +6,11 @@
 // thread owns one particle i and visits the partners j > i of its system,
 // which the block stages through LDS 256 at a time.  Counts go to an LDS
 // histogram (32-bit atomics), then once per block to the global int64
-// counts.  The bin of a pair is decided in FP64 from correctly rounded
-// operations only (division, rint, fused multiply-adds, products), so any
-// implementation that follows the same rule finds the same bin.
+// counts.  A pair at distance r < r_max falls in bin floor(r / dr), with r
+// the square root of dx^2 + dy^2 + dz^2 of the minimum-image displacement
+// in FP64, every operation rounded on its own (contraction into fused
+// multiply-adds is switched off), so that the bin is the one the plain
+// definition gives.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -25,6 +27,7 @@ __global__ __launch_bounds__(kHistTile) void k_pair_hist(const SysDev *__restric
                                                          int64_t ntot, double r_max, int nbins,
                                                          unsigned long long *__restrict__ counts)
 {
+#pragma clang fp contract(off)
     extern __shared__ unsigned int hist[];   // [3][nbins]
     __shared__ double sx[kHistTile], sy[kHistTile], sz[kHistTile];
     __shared__ int spos[kHistTile];
@@ -44,8 +47,6 @@ __global__ __launch_bounds__(kHistTile) void k_pair_hist(const SysDev *__restric
         pi = q[i] > (T)0 ? 1 : 0;
     }
     const double L = S.L, dr = r_max / nbins;
-    const double lim = (double)nbins * dr;
-    const double lim2 = lim * lim;
     for (int j0 = t.start; j0 < S.n; j0 += kHistTile) {
         __syncthreads();
         if (j0 + tid < S.n) {
@@ -61,16 +62,13 @@ __global__ __launch_bounds__(kHistTile) void k_pair_hist(const SysDev *__restric
         for (int u = 0; u < m; ++u) {
             if (j0 + u <= il) continue;
             double dx = sx[u] - xi, dy = sy[u] - yi, dz = sz[u] - zi;
-            dx = fma(-L, rint(dx / L), dx);
-            dy = fma(-L, rint(dy / L), dy);
-            dz = fma(-L, rint(dz / L), dz);
-            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            if (!(r2 < lim2)) continue;
-            // estimate, then settle on the largest b with (b dr)^2 <= r2
-            int b = (int)(sqrt(r2) / dr);
-            if (b > nbins - 1) b = nbins - 1;
-            while (b > 0 && ((double)b * dr) * ((double)b * dr) > r2) --b;
-            while (b < nbins - 1 && ((double)(b + 1) * dr) * ((double)(b + 1) * dr) <= r2) ++b;
+            dx = dx - L * rint(dx / L);
+            dy = dy - L * rint(dy / L);
+            dz = dz - L * rint(dz / L);
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(r < r_max)) continue;
+            const int b = (int)floor(r / dr);
+            if (b >= nbins) continue;
             const int cls = 2 - (pi + spos[u]);
             atomicAdd(&hist[cls * nbins + b], 1u);
         }

@@ -208,3 +208,19 @@ def test_rbe_energy_unbiased():
     vals = np.array(vals)
     z = (vals.mean() - Ue) / (vals.std() / math.sqrt(R))
     assert abs(z) < 5
+
+
+def test_kspace_force_subset_equals_full_rows():
+    """The subset force (the checker of the full-size GPU tests) returns the
+    rows of the full Fourier-space force (eq. 3.6), bit for bit."""
+    rng = np.random.default_rng(71)
+    n, L, alpha, p = 300, 12.0, 0.8, 37
+    pos = rng.random((3, n)) * L
+    q = rng.normal(size=n)
+    q -= q.mean()
+    modes, _ = O.sample_modes(alpha, L, p, 4, 2)
+    w = O.rbe_weights(alpha, L, p)
+    F = O.kspace_force(pos, q, L, modes, w, 7.1)
+    idx = np.array([299, 0, 17, 17, 150], np.int32)
+    Fs = O.kspace_force_subset(pos, q, L, modes, w, idx, 7.1)
+    assert np.array_equal(Fs, F[:, idx])

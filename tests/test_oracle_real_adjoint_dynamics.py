@@ -213,3 +213,238 @@ def test_andersen_collision_rate():
     frac = hit.mean()
     assert frac == pytest.approx(nu * dt, abs=5 * math.sqrt(nu * dt / n))
     assert np.allclose(vel[:, ~hit], 5.0)
+
+
+# -- force coupling of the integrators -------------------------------------------
+#
+# With no friction and no noise, BAOAB reduces to velocity Verlet and the
+# leapfrog loop of Sec. 3.1 (nu = 0) to the same trajectory in staggered
+# velocities.  Both are second order and symplectic: on a bound system the
+# total energy stays within a band whose width falls as dt^2.  A wrong kick
+# (a full dt instead of dt/2, or the closing kick taken with the force from
+# before the drift) makes the error first order or O(1), which these tests
+# catch.
+
+def _lj_cluster(T=0.3, seed=3, L=7.0):
+    """Eight neutral LJ particles on a cube of side 1.12 at the box centre:
+    every pair stays well inside the LJ cutoff 2.5, so the shifted potential
+    is smooth along the whole trajectory."""
+    g = np.arange(2) * 1.12
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()]) + L / 2 - g.mean()
+    rng = np.random.default_rng(seed)
+    v = rng.normal(0.0, math.sqrt(T), pos.shape)
+    v -= v.mean(1, keepdims=True)
+    return np.ascontiguousarray(pos), np.ascontiguousarray(v), L
+
+
+def _lj_energy(pos, vel, L, lj):
+    n = pos.shape[1]
+    _, _, el = O.real_force(pos, np.zeros(n), L, 1.0, 3.0, 1.0, lj)
+    return 0.5 * float((vel ** 2).sum()) + float(el.sum())
+
+
+def _energy_band(dt, integrator, t_end=2.0):
+    pos, vel, L = _lj_cluster()
+    n, lj = pos.shape[1], (1.0, 1.0, 2.5)
+    sysd = O.make_sys(n, 4, L, 1.0, 3.0, 1.0, lj, 0.0, 0.0, dt, 1.0, seed=1)
+    q = np.zeros(n)
+    F = O.total_force(sysd, pos, q, 0)
+    E0 = _lj_energy(pos, vel, L, lj)
+    if integrator == "leapfrog":
+        vel -= 0.5 * dt * F   # staggered start: v at -dt/2
+        vel = np.ascontiguousarray(vel)
+    band = 0.0
+    for s in range(int(round(t_end / dt))):
+        if integrator == "baoab":
+            O.baoab_step(sysd, pos, vel, q, F, s)
+            E = _lj_energy(pos, vel, L, lj)
+        else:
+            O.leapfrog_andersen_step(sysd, 0.0, pos, vel, q, F, s)
+            # vel holds v at (s + 1/2) dt; the on-step velocity adds half a kick
+            E = _lj_energy(pos, vel + 0.5 * dt * F, L, lj)
+        band = max(band, abs(E - E0))
+    return band
+
+
+@pytest.mark.parametrize("integrator", ["baoab", "leapfrog"])
+def test_integrator_energy_error_is_second_order(integrator):
+    e = [_energy_band(dt, integrator) for dt in (0.004, 0.002, 0.001)]
+    assert e[0] < 5e-3
+    for a, b in zip(e, e[1:]):
+        assert 3.5 < a / b < 4.5, e
+
+
+def test_baoab_and_leapfrog_share_positions_without_noise():
+    """Velocity Verlet and leapfrog visit the same positions (Sec. 3.1 loop
+    body with nu = 0 against BAOAB with gamma = 0, kT = 0)."""
+    pos, vel, L = _lj_cluster(T=0.5, seed=9)
+    n, lj, dt = pos.shape[1], (1.0, 1.0, 2.5), 0.003
+    sysd = O.make_sys(n, 4, L, 1.0, 3.0, 1.0, lj, 0.0, 0.0, dt, 1.0, seed=1)
+    q = np.zeros(n)
+    pa, va = pos.copy(), vel.copy()
+    Fa = O.total_force(sysd, pa, q, 0)
+    pb, Fb = pos.copy(), Fa.copy()
+    vb = np.ascontiguousarray(vel - 0.5 * dt * Fa)
+    for s in range(50):
+        O.baoab_step(sysd, pa, va, q, Fa, s)
+        O.leapfrog_andersen_step(sysd, 0.0, pb, vb, q, Fb, s)
+    assert np.abs(pa - pb).max() < 1e-12
+    assert np.abs(va - (vb + 0.5 * dt * Fb)).max() < 1e-11
+
+
+def test_free_particle_mean_square_displacement():
+    """Free Langevin particles (Sec. 3.3 SDE with F = 0) started from the
+    Maxwell-Boltzmann distribution: MSD(t) = 6 (kT/gamma) (t - tau (1 - e^(-t/tau))),
+    tau = m/gamma (Ornstein-Uhlenbeck position process)."""
+    n, L = 2000, 200.0
+    kT, gamma, mass, dt, k = 1.0, 2.0, 1.0, 0.05, 200
+    rng = np.random.default_rng(17)
+    pos = np.ascontiguousarray(rng.random((3, n)) * L)
+    vel = np.ascontiguousarray(rng.normal(0.0, math.sqrt(kT / mass), (3, n)))
+    sysd = O.make_sys(n, 4, L, 1.0, 3.0, 1.0, (0.0, 1.0, 2.5), kT, gamma, dt, mass, seed=23)
+    F = np.zeros((3, n))
+    q = np.zeros(n)
+    disp = np.zeros((3, n))
+    for s in range(k):
+        p0 = pos.copy()
+        O.baoab_step(sysd, pos, vel, q, F, s)
+        d = pos - p0
+        disp += d - L * np.round(d / L)
+    t, tau = k * dt, mass / gamma
+    expect = 6.0 * kT / gamma * (t - tau * (1.0 - math.exp(-t / tau)))
+    msd = float((disp ** 2).sum(0).mean())
+    # |dr|^2 / (3 s^2) is chi^2_3 / 3: relative standard deviation sqrt(2/3)/sqrt(n)
+    assert msd == pytest.approx(expect, rel=5 * math.sqrt(2.0 / 3.0 / n))
+
+
+# -- linked-cell list and the offset LJ of eq. (4.1) ---------------------------------
+
+@pytest.mark.parametrize("n,lj", [(300, (1.0, 1.0, 2.5)), (3000, (1.0, 1.0, 2.5)), (2000, (0.0, 1.0, 2.5))])
+def test_cell_list_matches_direct_sum(n, lj):
+    """The oracle's own linked-cell real space against its O(N^2) direct sum
+    over every image (Sec. 2, eq. 2.11 second term): forces, half energies
+    and half virials per particle, to summation-order rounding."""
+    rng = np.random.default_rng(n)
+    L = W.box_for_density(n, 0.1)
+    pos = W.positions(n, L, rng, 0.8)
+    q = W.gaussian_charges(n, rng)
+    alpha, rc = 0.6, 3.5
+    a = O.real_force(pos, q, L, alpha, rc, 1.0, lj, virial=True)
+    b = O.real_force(pos, q, L, alpha, rc, 1.0, lj, cells=True, virial=True)
+    scale = np.abs(a[0]).max()
+    assert np.abs(a[0] - b[0]).max() <= 1e-13 * scale
+    for u, v in zip(a[1:], b[1:]):
+        assert np.abs(u - v).max() <= 1e-13 * max(np.abs(u).max(), 1e-300)
+    idx = np.array([n - 1, 0, n // 2], np.int32)
+    c = O.real_force(pos, q, L, alpha, rc, 1.0, lj, idx=idx, cells=True)
+    assert np.array_equal(c[0], b[0][:, idx])
+
+
+def test_cell_list_falls_back_to_direct_sum_in_small_boxes():
+    rng = np.random.default_rng(5)
+    L, n = 9.0, 60
+    pos = W.positions(n, L, rng, 0.8)
+    q = W.electrolyte_charges(n)
+    a = O.real_force(pos, q, L, 0.8, 3.5, 1.0, (1.0, 1.0, 2.5))
+    b = O.real_force(pos, q, L, 0.8, 3.5, 1.0, (1.0, 1.0, 2.5), cells=True)
+    assert all(np.array_equal(u, v) for u, v in zip(a, b))
+
+
+def test_offset_lj_is_zero_at_its_cutoff_and_repels_at_contact():
+    """Eq. (4.1) with r_off = (d_i + d_j)/2 - sigma: V = 0 where
+    r - r_off = R_c, and the pair repels closer in.  Colloid (d = 100) and
+    ion (d = 4) with sigma = 1 and the WCA cutoff R_c = 2^(1/6) (Sec. 4.2)."""
+    sig, rcut = 1.0, 2.0 ** (1.0 / 6.0)
+    diam = np.array([100.0, 4.0])
+    roff = 0.5 * (diam[0] + diam[1]) - sig
+    assert roff == 51.0
+    L = 300.0
+
+    def pair(r):
+        pos = np.array([[10.0, 10.0 + r], [20.0, 20.0], [20.0, 20.0]])
+        return O.real_force(pos, np.zeros(2), L, 0.01, 40.0, 1.0, (1.0, sig, rcut), diam=diam)
+
+    for eps_r in (-1e-9, 1e-9):
+        F, _, el = pair(roff + rcut + eps_r)
+        assert abs(el.sum()) < 1e-8 and np.abs(F).max() < 1e-6
+    F, _, el = pair(roff + 1.0)   # r - r_off = sigma: the unshifted LJ is zero
+    shift = -4.0 * ((sig / rcut) ** 12 - (sig / rcut) ** 6)
+    assert el.sum() == pytest.approx(shift, rel=1e-12)
+    assert F[0, 0] < 0 and F[0, 1] > 0   # pushed apart
+    # beyond the offset cutoff nothing acts even though r < r_off + 2.5 sigma
+    F, _, el = pair(roff + 1.5)
+    assert el.sum() == 0.0 and np.abs(F).max() == 0.0
+
+
+def test_offset_lj_force_is_minus_gradient():
+    """F = -grad U for a configuration of ions of two sizes around a colloid,
+    charges and the offset LJ together (central differences, h = 1e-6)."""
+    rng = np.random.default_rng(41)
+    L, n = 120.0, 40
+    diam = np.full(n, 4.0)
+    diam[0] = 100.0
+    pos = np.empty((3, n))
+    pos[:, 0] = L / 2
+    k = 1
+    while k < n:
+        x = rng.random(3) * L
+        d = x - pos[:, :k].T
+        d -= L * np.round(d / L)
+        r = np.sqrt((d ** 2).sum(1))
+        contact = 0.5 * (diam[0] + 4.0)
+        if r[0] > contact + 0.05 and (k == 1 or r[1:].min() > 4.0 + 0.05) and r[0] < contact + 3.0:
+            pos[:, k] = x
+            k += 1
+    q = np.where(np.arange(n) % 2 == 0, 3.0, -1.0)
+    q[0] = -(q[1:].sum())
+    lj = (1.0, 1.0, 2.0 ** (1.0 / 6.0))
+    alpha, rc, lb = 0.0072, 40.0, 7.1
+    F, er, el = O.real_force(pos, q, L, alpha, rc, lb, lj, diam=diam)
+    assert np.abs(F.sum(1)).max() < 1e-9 * np.abs(F).max()
+    h = 1e-6
+
+    def U(pp):
+        _, a, b = O.real_force(pp, q, L, alpha, rc, lb, lj, diam=diam)
+        return a.sum() + b.sum()
+
+    for i in (0, 1, 5, 17, 39):
+        for d in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[d, i] += h
+            pm[d, i] -= h
+            fd = -(U(pp) - U(pm)) / (2 * h)
+            assert fd == pytest.approx(F[d, i], rel=1e-6, abs=1e-6 * np.abs(F).max())
+
+
+@pytest.mark.parametrize("integrator", ["baoab", "leapfrog"])
+def test_fixed_particles_stay_in_place(integrator):
+    """The first n_fixed particles (the colloid of Sec. 4.2) keep their
+    positions and velocities while the rest move under the same forces."""
+    rng = np.random.default_rng(9)
+    n, L = 50, 20.0
+    pos = W.positions(n, L, rng, 1.0)
+    vel = np.ascontiguousarray(rng.normal(size=(3, n)))
+    vel[:, :2] = 0.0
+    q = W.electrolyte_charges(n)
+    sysd = O.make_sys(n, 8, L, 0.5, 3.5, 1.0, (1.0, 1.0, 2.5), 1.0, 1.0, 0.01, 1.0, seed=3, n_fixed=2)
+    p0 = pos.copy()
+    F = O.total_force(sysd, pos, q, 0)
+    assert np.abs(F[:, :2]).max() > 0
+    for s in range(5):
+        if integrator == "baoab":
+            O.baoab_step(sysd, pos, vel, q, F, s)
+        else:
+            O.leapfrog_andersen_step(sysd, 50.0, pos, vel, q, F, s)
+    assert np.array_equal(pos[:, :2], p0[:, :2]) and np.all(vel[:, :2] == 0.0)
+    assert np.abs(pos[:, 2:] - p0[:, 2:]).max() > 0
+
+
+def test_kinetic_energy_equipartition():
+    """Sum m |v|^2 / 2 over Maxwell-Boltzmann velocities at kT has mean
+    (3/2) N kT (equipartition, k_B = 1 as in Sec. 3.3) and variance
+    (3/2) N kT^2."""
+    n, kT, mass = 200000, 1.7, 2.5
+    vel = W.velocities(n, np.random.default_rng(3), kT, mass)
+    e = O.kinetic_energy(vel, mass)
+    assert e == pytest.approx(1.5 * n * kT, abs=5 * math.sqrt(1.5 * n) * kT)
