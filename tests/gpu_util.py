@@ -36,3 +36,39 @@ def rounded(sys, precision):
     if precision == R.RBE_FP32:
         return sys.pos.astype(np.float32).astype(np.float64), sys.q.astype(np.float32).astype(np.float64)
     return sys.pos, sys.q
+
+
+# Trajectory checks.  FP32 positions are stored in single precision after
+# every step, which alone moves a coordinate by up to half an ulp of the box
+# side per step; over the short horizons of the tests that is well below
+# 1e-3 of the distance the particles travel, the bound used for the
+# position error over the displacement from the start.  Velocities carry the
+# same relative rounding (~6e-8 per step).  The force the step leaves is
+# checked against the oracle evaluated at the GPU's own final positions, so
+# its tolerance is the force tolerance itself.
+TRAJ_TOL = {R.RBE_FP64: dict(pos=1e-9, vel=1e-10, force=1e-11),
+            R.RBE_FP32: dict(pos=1e-3, vel=2e-5, force=1e-5)}
+
+
+def min_image(d, L):
+    return d - L * np.round(d / L)
+
+
+def displacement_error(P, po, p_start, L):
+    """|| GPU - oracle || over || oracle - start || (minimum image)."""
+    dp = min_image(host(P) - po, L)
+    moved = min_image(po - p_start, L)
+    return float(np.linalg.norm(dp) / np.linalg.norm(moved))
+
+
+def check_trajectory(prec, P, V, F, po, vo, p_start, L, force_at_gpu_positions, scale=1.0):
+    """Asserts the three trajectory bounds; force_at_gpu_positions(pos) is the
+    oracle's force at the given positions with the last step's modes."""
+    tol = TRAJ_TOL[prec]
+    e_pos = displacement_error(P, po, p_start, L)
+    e_vel = rel_l2(host(V), vo)
+    e_f = rel_l2(host(F), force_at_gpu_positions(host(P)))
+    assert e_pos <= scale * tol["pos"], ("position", e_pos)
+    assert e_vel <= scale * tol["vel"], ("velocity", e_vel)
+    assert e_f <= tol["force"], ("force", e_f)
+    return e_pos, e_vel, e_f

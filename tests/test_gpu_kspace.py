@@ -178,9 +178,9 @@ def test_net_kspace_force_vanishes_fp32_full_size():
     assert np.abs(f.sum(1)).max() <= 1e-5 * np.abs(f).sum(1).max()
 
 
-def test_kspace_full_size_sampled_fp32():
+def test_kspace_full_size_every_particle_fp32():
     """N = 1e5, P = 100 at the launch shape the benchmark times: the structure
-    factor against the oracle over all particles, forces on 400 sampled ones."""
+    factor and the Fourier force against the oracle over all particles."""
     s = W.metric_system()
     ctx = make_ctx(s, R.RBE_FP32)
     P, Q, V, F = device_state(ctx, s)
@@ -189,9 +189,8 @@ def test_kspace_full_size_sampled_fp32():
     R.rbe_kspace_forces(ctx, P, Q, F)
     re, im = O.rho(pos, q, s.L, modes)
     assert rel_l2(R.rbe_get_rho(ctx), np.stack([re, im], 1)) <= 2e-6
-    idx = np.random.default_rng(0).choice(s.n, 400, replace=False).astype(np.int32)
-    Fo = O.kspace_force_subset(pos, q, s.L, modes, O.rbe_weights(s.alpha, s.L, s.p), idx)
-    assert rel_l2(host(F)[:, idx], Fo) <= 1e-5
+    Fo = O.kspace_force(pos, q, s.L, modes, O.rbe_weights(s.alpha, s.L, s.p))
+    assert rel_l2(host(F), Fo) <= 1e-5
 
 
 def test_kspace_deterministic():
