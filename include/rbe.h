@@ -10,7 +10,8 @@
  * Fourier part (eq. 2.11, first term) -- estimated by the random batch of P
  * modes drawn from exp(-k^2/4 alpha) (Sec. 3.1, eqs. 3.3 and 3.6) -- and an
  * exact real-space erfc part inside r_cut (eq. 2.11, second term), plus an
- * optional shifted Lennard-Jones repulsion (eq. 4.1 with r_off = 0).
+ * optional shifted Lennard-Jones repulsion (eq. 4.1; r_off = 0 unless
+ * per-particle diameters are given, then r_off = (d_i + d_j)/2 - sigma).
  *
  * Conventions shared by every entry point:
  *   - Arrays are device memory owned by the caller, contiguous, SoA:
@@ -50,7 +51,11 @@ typedef enum rbe_status {
     RBE_ERR_HIP = -5,          /* a HIP runtime call failed */
     RBE_ERR_NONFINITE = -6,    /* non-finite value seen by a kernel */
     RBE_ERR_STATE = -7,        /* call not valid in the current state */
-    RBE_ERR_NO_DEVICE = -8     /* no usable gfx950 device */
+    RBE_ERR_NO_DEVICE = -8,    /* no usable gfx950 device */
+    RBE_ERR_TIMEOUT = -9       /* a bounded device-side wait of a neighbour-list rebuild gave
+                                  up (or a rebuild index fell outside its system): the forces
+                                  of the steps since the last check are not valid; the
+                                  library repairs its cell state and the next step rebuilds */
 } rbe_status;
 
 enum { RBE_FP32 = 0, RBE_FP64 = 1 };
@@ -74,7 +79,8 @@ typedef struct rbe_params {
     double coulomb;      /* Coulomb prefactor: 1 (Sec. 4.1) or l_B (Sec. 4.2) */
     double lj_eps;       /* shifted LJ [epsilon] (eq. 4.1); 0 disables LJ */
     double lj_sigma;     /* [sigma] */
-    double lj_rcut;      /* LJ cutoff [R_c], <= L/2 when LJ is on */
+    double lj_rcut;      /* LJ cutoff [R_c] on r - r_off; the largest pair reach
+                            r_off + R_c must not exceed L/2 when LJ is on */
     double kT;           /* bath temperature [T], k_B = 1 (Sec. 3.3) */
     double gamma;        /* Langevin friction [gamma] (Sec. 3.3) */
     double dt;           /* time step [Delta t] */
@@ -96,6 +102,14 @@ typedef struct rbe_params {
                             a new batch (with the classical Ewald list of rbe_set_k: Ewald dynamics on
                             the same kernels); single-system contexts only */
     int32_t flags;       /* reserved, 0 */
+    int32_t n_fixed;     /* particles 0 .. n_fixed-1 of the system never move (the fixed
+                            colloid of Sec. 4.2): no kicks, drifts, noise or collisions;
+                            0 <= n_fixed <= n */
+    int32_t reserved;    /* 0 */
+    const double *diameter; /* host [n] diameters d_i of eq. (4.1), read only during creation,
+                            or NULL (every d_i = sigma, so r_off = 0).  With diameters the
+                            LJ term acts for r - r_off < R_c with r_off = (d_i + d_j)/2 - sigma;
+                            rbe_forces_vjp then refuses the real-space part (RBE_ERR_STATE) */
 } rbe_params;
 
 /* Energies of one system (all double, host memory). */
@@ -112,8 +126,8 @@ typedef struct rbe_energy_t {
                           (scaling derivative of the Fourier sum); eq. 4.3 uses
                           vir = (virial + virial_kspace) / 2 */
     double charge_sum; /* sum q_i, for the neutrality check */
-    int32_t nonfinite; /* non-zero if any kernel met a non-finite force since the last call */
-    int32_t reserved;
+    int32_t nonfinite; /* non-zero if any kernel met a non-finite force since the last check */
+    int32_t timeout;   /* non-zero if a list rebuild's bounded wait gave up since the last check */
 } rbe_energy_t;
 
 /* Tile shapes of the kernels; 0 fields mean "library default". */
@@ -215,8 +229,25 @@ rbe_status rbe_batch_step(rbe_ctx *ctx, void *pos, void *vel, const void *q, voi
  * Sec. 4.1, eqs. 4.1 and 4.3).  vel may be NULL.  out is host [R].
  * Synchronises the stream.  Returns RBE_ERR_NOT_NEUTRAL if some system has
  * |sum q| > 1e-6 sum |q| (energies are still filled in), RBE_ERR_NONFINITE if
- * a kernel met a non-finite force since the previous rbe_energy call. */
+ * a kernel met a non-finite force, RBE_ERR_TIMEOUT if a list rebuild gave up,
+ * since the previous check (see rbe_check). */
 rbe_status rbe_energy(rbe_ctx *ctx, const void *pos, const void *q, const void *vel, rbe_energy_t *out);
+
+/* Pending device-side errors since the previous check (by this call, rbe_energy or
+ * rbe_list_builds): RBE_ERR_NONFINITE if a kernel met a non-finite force,
+ * RBE_ERR_TIMEOUT if a list rebuild's bounded wait gave up (then the cell
+ * state is cleared and the next step rebuilds from scratch), else RBE_OK.
+ * Clears what it reports.  Synchronises the stream.  Time steps are
+ * asynchronous and cannot return these errors themselves. */
+rbe_status rbe_check(rbe_ctx *ctx);
+
+/* Bound on the spin iterations of each device-side wait inside a list
+ * rebuild (default 2^24, far beyond any real wait).  Every wait ends: a wait
+ * that reaches the bound gives up, raises RBE_ERR_TIMEOUT for the next
+ * check and leaves the step's forces invalid; 0 makes every wait give up at
+ * once, which exercises that path without any kernel hanging or faulting.
+ * RBE_ERR_INVALID for a negative bound.  Synchronises the stream. */
+rbe_status rbe_set_wait_limit(rbe_ctx *ctx, int32_t limit);
 
 /* Structure factors of the last Fourier evaluation: host [M_tot][2] double
  * (real, imaginary).  Synchronises the stream. */
@@ -233,7 +264,9 @@ rbe_status rbe_forces_vjp(rbe_ctx *ctx, const void *pos, const void *q, const vo
 /* Number of neighbour-list builds made by rbe_step since creation (the first
  * step after creation, after rbe_real_forces / rbe_energy / rbe_forces_vjp,
  * and whenever a particle had moved more than skin/2 or a list overflowed),
- * or -1 when the context does not use the list.  Synchronises the stream. */
+ * or -1 when the context does not use the list.  Synchronises the stream.
+ * Returns RBE_ERR_TIMEOUT (builds still written) when a rebuild gave up since
+ * the previous check (see rbe_check). */
 rbe_status rbe_list_builds(rbe_ctx *ctx, int64_t *builds);
 
 /* Time step of every system from the next rbe_step on.  anneal = 0: the

@@ -80,6 +80,25 @@ void build_cdf(double alpha, double L, std::vector<double> &out)
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// Largest centre distance at which the shifted LJ of eq. (4.1) still acts:
+// R_c without diameters (r_off = 0), else r_off + R_c of the pair of the two
+// largest diameters, r_off = (d_i + d_j)/2 - sigma.
+double lj_reach(const rbe_params &p)
+{
+    if (!p.diameter || p.n < 2) return p.lj_rcut;
+    double d1 = -1e300, d2 = -1e300;
+    for (int i = 0; i < p.n; ++i) {
+        const double d = p.diameter[i];
+        if (d > d1) {
+            d2 = d1;
+            d1 = d;
+        } else if (d > d2) {
+            d2 = d;
+        }
+    }
+    return 0.5 * (d1 + d2) - p.lj_sigma + p.lj_rcut;
+}
+
 rbe_status validate(const rbe_params &p, std::string &err)
 {
     if (p.n < 1) return err = fmt("n must be >= 1 (got %d)", p.n), RBE_ERR_INVALID;
@@ -92,12 +111,17 @@ rbe_status validate(const rbe_params &p, std::string &err)
         return err = fmt("r_cut %.6g exceeds half the box %.6g (minimum image)", p.r_cut, 0.5 * p.box),
                RBE_ERR_CUTOFF;
     if (!std::isfinite(p.lj_eps) || p.lj_eps < 0.0) return err = "lj_eps must be finite and >= 0", RBE_ERR_INVALID;
+    if (p.diameter)
+        for (int i = 0; i < p.n; ++i)
+            if (!finite_pos(p.diameter[i])) return err = fmt("diameter[%d] must be finite and > 0", i), RBE_ERR_INVALID;
     if (p.lj_eps > 0.0) {
         if (!finite_pos(p.lj_sigma) || !finite_pos(p.lj_rcut))
             return err = "lj_sigma and lj_rcut must be finite and > 0 when lj_eps > 0", RBE_ERR_INVALID;
-        if (p.lj_rcut > 0.5 * p.box)
-            return err = fmt("lj_rcut %.6g exceeds half the box", p.lj_rcut), RBE_ERR_CUTOFF;
+        if (lj_reach(p) > 0.5 * p.box)
+            return err = fmt("the LJ reach r_off + lj_rcut = %.6g exceeds half the box", lj_reach(p)), RBE_ERR_CUTOFF;
     }
+    if (p.n_fixed < 0 || p.n_fixed > p.n) return err = fmt("n_fixed must be in [0, n] (got %d)", p.n_fixed), RBE_ERR_INVALID;
+    if (p.reserved != 0) return err = "reserved must be 0", RBE_ERR_INVALID;
     if (!std::isfinite(p.kT) || p.kT < 0.0) return err = "kT must be finite and >= 0", RBE_ERR_INVALID;
     if (!std::isfinite(p.gamma) || p.gamma < 0.0) return err = "gamma must be finite and >= 0", RBE_ERR_INVALID;
     if (!std::isfinite(p.dt) || p.dt < 0.0) return err = "dt must be finite and >= 0", RBE_ERR_INVALID;
@@ -463,6 +487,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     bool all_skin = true;
     for (int r = 0; r < R; ++r) all_skin = all_skin && params[r].skin > 0.0;
     int kmax = 0;
+    bool any_diam = false;
     for (int r = 0; r < R; ++r) {
         const rbe_params &p = params[r];
         SysDev s{};
@@ -473,7 +498,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         s.cdf_off = (int32_t)cdf.size();
         s.M = table_half_width(p.alpha, p.box);
         build_cdf(p.alpha, p.box, cdf);
-        const double rmax = std::max(p.r_cut, p.lj_eps > 0.0 ? p.lj_rcut : 0.0);
+        const double rmax = std::max(p.r_cut, p.lj_eps > 0.0 ? lj_reach(p) : 0.0);
         const double rlist = rmax + p.skin;
         int nc = (int)std::floor(p.box / rlist);
         nc = std::min(nc, 128);
@@ -495,6 +520,12 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         s.lj_eps = p.lj_eps;
         s.lj_sig2 = p.lj_sigma * p.lj_sigma;
         s.lj_rc2 = p.lj_rcut * p.lj_rcut;
+        s.lj_sig = p.lj_sigma;
+        s.lj_rc = p.lj_rcut;
+        s.rsearch2 = rmax * rmax;
+        s.n_fixed = p.n_fixed;
+        s.diam_on = (p.diameter && s.lj_on) ? 1 : 0;
+        any_diam = any_diam || s.diam_on;
         if (s.lj_on) {
             const double sr6 = std::pow(p.lj_sigma / p.lj_rcut, 6.0);
             s.lj_shift = -4.0 * p.lj_eps * (sr6 * sr6 - sr6);
@@ -564,6 +595,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     g.max_cells = max_cells;
     g.max_p = c->max_p;
     g.max_table = max_table;
+    g.wait_limit = kWaitLimit;
 
     std::vector<Tile> ftiles, ptiles;
     for (int r = 0; r < R; ++r) {
@@ -626,6 +658,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     ALLOC(w.flag, sizeof(int32_t) * 4);
     ALLOC(w.lflag, sizeof(int32_t) * 8);
     ALLOC(w.step_base, sizeof(uint64_t));
+    if (any_diam) ALLOC(w.diam, sizeof(double) * ntot);
     {
         // list-pass tiles: at most one per 32 slots (the 8-lane shape)
         int64_t nl = 0;
@@ -652,7 +685,22 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
               hipMemset(w.cell_count, 0, sizeof(int32_t) * cell_off) == hipSuccess &&
               hipMemset(w.flag, 0, sizeof(int32_t) * 4) == hipSuccess &&
               hipMemset(w.lflag, 0, sizeof(int32_t) * 8) == hipSuccess &&
+              hipMemset(w.cell_start, 0, sizeof(int32_t) * (cell_off + R)) == hipSuccess &&
               hipMemset(w.modes, 0, sizeof(int32_t) * 3 * c->mcap) == hipSuccess;
+    if (ok) {
+        // every slot names a particle of its own system until the first scatter
+        std::vector<int32_t> iota(ntot);
+        for (int64_t i = 0; i < ntot; ++i) iota[i] = (int32_t)i;
+        ok = up(w.sorted_idx, iota.data(), sizeof(int32_t) * ntot);
+    }
+    if (ok && any_diam) {
+        std::vector<double> d(ntot);
+        for (int r = 0; r < R; ++r) {
+            const rbe_params &p = params[r];
+            for (int i = 0; i < p.n; ++i) d[c->sysh[r].off + i] = p.diameter ? p.diameter[i] : p.lj_sigma;
+        }
+        ok = up(w.diam, d.data(), sizeof(double) * ntot);
+    }
     if (ok) ok = upload_rho_tiles(c) == RBE_OK;
     if (ok) ok = upload_list_tiles(c) == RBE_OK;
     if (ok && g.list_on) {
@@ -897,7 +945,7 @@ static rbe_status list_step(rbe_ctx *c, void *pos, void *vel, const void *q, voi
 {
     const int par = (int)(c->list_gen & 1);
     ListStep ls{c->w.lflag + par, c->w.lflag + (1 - par), c->w.lflag + 2, c->w.lflag + 3, c->w.lflag + 4,
-                c->w.lflag + 5, c->list_valid ? 0 : 1};
+                c->w.lflag + 5, c->w.lflag + 6, c->list_valid ? 0 : 1};
     ls.step_base = base;
     ls.step_bump = bump ? base : nullptr;
     ls.bump = bump;
@@ -1118,6 +1166,54 @@ rbe_status rbe_batch_step(rbe_ctx *c, void *pos, void *vel, const void *q, void 
     return rbe_step(c, pos, vel, q, force, first_step, nsteps);
 }
 
+// Reads the device error word and clears the bits in `mask` (synchronises).
+// After a timeout the neighbour list is marked stale so that the next step
+// rebuilds from the cell counts, which the force launch of the failed step
+// cleared.
+static rbe_status take_device_errors(rbe_ctx *c, int32_t *bits, int32_t mask = -1)
+{
+    int32_t flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&flag, c->w.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flag & mask) {
+        const int32_t keep = flag & ~mask;
+        HIPCHK(c, hipMemcpy(c->w.flag, &keep, sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    if (flag & mask & (kFlagTimeout | kFlagBounds)) c->list_valid = false;
+    *bits = flag & mask;
+    return RBE_OK;
+}
+
+static rbe_status device_error_status(rbe_ctx *c, int32_t bits)
+{
+    if (bits & kFlagTimeout)
+        return set_err(c, RBE_ERR_TIMEOUT, "a bounded wait of a neighbour-list rebuild gave up; the forces of the "
+                                           "steps since the last check are not valid");
+    if (bits & kFlagBounds)
+        return set_err(c, RBE_ERR_TIMEOUT, "a neighbour-list rebuild met stale cell counts; the forces of the "
+                                           "steps since the last check are not valid");
+    if (bits & kFlagNonFinite) return set_err(c, RBE_ERR_NONFINITE, "a kernel met a non-finite force");
+    return RBE_OK;
+}
+
+rbe_status rbe_check(rbe_ctx *c)
+{
+    if (!c) return RBE_ERR_INVALID;
+    int32_t bits = 0;
+    rbe_status s = take_device_errors(c, &bits);
+    if (s != RBE_OK) return s;
+    return device_error_status(c, bits);
+}
+
+rbe_status rbe_set_wait_limit(rbe_ctx *c, int32_t limit)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (limit < 0) return set_err(c, RBE_ERR_INVALID, "the wait limit must be >= 0");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cfg.wait_limit = limit;
+    return RBE_OK;
+}
+
 rbe_status rbe_energy(rbe_ctx *c, const void *pos, const void *q, const void *vel, rbe_energy_t *out)
 {
     if (!c) return RBE_ERR_INVALID;
@@ -1136,9 +1232,11 @@ rbe_status rbe_energy(rbe_ctx *c, const void *pos, const void *q, const void *ve
     HIPCHK(c, hipMemcpyAsync(wts.data(), c->w.mode_w, sizeof(double) * wts.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(modes.data(), c->w.modes, sizeof(int32_t) * modes.size(), hipMemcpyDeviceToHost,
                              c->stream));
-    HIPCHK(c, hipMemcpyAsync(flag, c->w.flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, launch_fill_zero(c->stream, c->w.flag, sizeof(int32_t)));
+    {
+        rbe_status es = take_device_errors(c, &flag[0]);
+        if (es != RBE_OK) return es;
+    }
     std::vector<double> acc(8 * (size_t)c->R, 0.0);
     for (size_t tile = 0; tile < c->real_sys.size(); ++tile) {
         const int r = c->real_sys[tile];
@@ -1168,15 +1266,15 @@ rbe_status rbe_energy(rbe_ctx *c, const void *pos, const void *q, const void *ve
         e.virial = acc[8 * r + 2];
         e.e_kin = vel ? acc[8 * r + 3] : 0.0;
         e.charge_sum = acc[8 * r + 5];
-        e.nonfinite = flag[0];
-        e.reserved = 0;
+        e.nonfinite = (flag[0] & kFlagNonFinite) ? 1 : 0;
+        e.timeout = (flag[0] & (kFlagTimeout | kFlagBounds)) ? 1 : 0;
         if (std::fabs(acc[8 * r + 5]) > 1e-6 * acc[8 * r + 6] && ret == RBE_OK) {
             ret = set_err(c, RBE_ERR_NOT_NEUTRAL,
                           fmt("system %d is not neutral: sum q = %.6g, sum |q| = %.6g", r, acc[8 * r + 5],
                               acc[8 * r + 6]));
         }
     }
-    if (flag[0]) ret = set_err(c, RBE_ERR_NONFINITE, "a kernel met a non-finite force");
+    if (flag[0]) ret = device_error_status(c, flag[0]);
     return ret;
 }
 
@@ -1197,6 +1295,10 @@ rbe_status rbe_forces_vjp(rbe_ctx *c, const void *pos, const void *q, const void
     if (parts < 1 || parts > 3) return set_err(c, RBE_ERR_INVALID, "parts must be RBE_PART_KSPACE, _REAL or _ALL");
     if ((parts & RBE_PART_KSPACE) && !c->modes_valid)
         return set_err(c, RBE_ERR_STATE, "no active modes: call rbe_sample_k or rbe_set_k first");
+    if (parts & RBE_PART_REAL)
+        for (int r = 0; r < c->R; ++r)
+            if (c->sysh[r].diam_on)
+                return set_err(c, RBE_ERR_STATE, "the real-space adjoint does not cover per-particle diameters");
     if (parts & RBE_PART_KSPACE) {
         rbe_status s = kspace_impl(c, pos, q, nullptr, 0);
         if (s != RBE_OK) return s;
@@ -1220,7 +1322,11 @@ rbe_status rbe_list_builds(rbe_ctx *c, int64_t *builds)
     HIPCHK(c, hipMemcpyAsync(&v, c->w.lflag + 3, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *builds = c->cfg.list_on ? (int64_t)v : -1;
-    return RBE_OK;
+    // a non-finite force is left for rbe_energy / rbe_check to report
+    int32_t bits = 0;
+    rbe_status s = take_device_errors(c, &bits, kFlagTimeout | kFlagBounds);
+    if (s != RBE_OK) return s;
+    return device_error_status(c, bits);
 }
 
 rbe_status rbe_get_tiles(const rbe_ctx *c, rbe_tiles *t)

@@ -349,6 +349,13 @@ template <typename T>
 __device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i, int64_t ntot, T *pos, T *vel,
                                               const T *F, uint64_t step, bool kick, double x[3])
 {
+    if (il < S.n_fixed) {
+        // an immobile particle (the colloid of Sec. 4.2): no kick, drift,
+        // noise or collision; its stored state is left as it is
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d] = (double)pos[d * ntot + i];
+        return;
+    }
     const bool hit = S.integrator == RBE_LANGEVIN_BAOAB ? false : andersen_hit(S, il, step);
     const bool noise = S.integrator == RBE_LANGEVIN_BAOAB || hit;
     const double dt = step_dt(S, step), dt_prev = kick ? step_dt(S, step - 1) : 0.0;

@@ -18,6 +18,14 @@ constexpr uint32_t kTagLangevin = 0x02000000u;
 constexpr uint32_t kTagAndersen = 0x03000000u;
 constexpr uint32_t kTagMH = 0x04000000u;
 
+// Bits of the device error word (Workspace::flag[0]).
+constexpr int32_t kFlagNonFinite = 1;   // a kernel met a non-finite force
+constexpr int32_t kFlagTimeout = 2;     // a bounded wait of a list rebuild gave up
+constexpr int32_t kFlagBounds = 4;      // a rebuild index fell outside its system (skipped)
+
+// Default bound on the spin iterations of a device-side wait.
+constexpr int32_t kWaitLimit = 1 << 24;
+
 // Per-system constants, resident in device memory and read by every kernel.
 struct SysDev {
     int32_t n;          // particles
@@ -35,12 +43,16 @@ struct SysDev {
     int32_t use_list;      // neighbour list in rbe_step (skin > 0 and nc >= 3)
     int32_t hi_bits;       // FP32 phases: box fractions split as hi (multiple of 2^-hi_bits) + lo
     float hi_scale, hi_inv;  // 2^hi_bits, 2^-hi_bits
+    int32_t n_fixed;       // particles 0 .. n_fixed-1 never move
+    int32_t diam_on;       // per-particle diameters: LJ with r_off = (d_i + d_j)/2 - sigma
     double L, invL;
     double alpha, beta;     // beta = sqrt(alpha)
     double rc2;             // r_cut^2
     double coulomb;
     double S;               // normaliser H^3 - 1
     double lj_eps, lj_sig2, lj_rc2, lj_shift;  // sigma^2, cutoff^2, V_shift
+    double lj_sig, lj_rc;   // sigma and the cutoff R_c on r - r_off
+    double rsearch2;        // largest pair reach squared: max(r_cut, max_pairs r_off + R_c)^2
     double kT, gamma, dt, mass;
     double c1, c2;          // Ornstein-Uhlenbeck factors exp(-gamma dt/m), sqrt((1-c1^2) kT/m)
     double nu_dt;           // Andersen collision probability per step
@@ -137,7 +149,7 @@ struct Workspace {
     int32_t *modes_alt;    // the next step's modes and weights when the totals launch draws them
     double *mode_w_alt;
     double *energy_part;   // [real tiles][8]
-    int32_t *flag;         // [4] bit 0: non-finite force
+    int32_t *flag;         // [4] word 0: kFlag* error bits
     // neighbour list of rbe_step (allocated when some system uses it)
     Tile *list_tiles;      // list-pass tiles (aux 2: cell-sorted slots, 1: all pairs)
     int32_t *slot_of;      // [Ntot] sorted slot of each particle at the last build
@@ -145,10 +157,12 @@ struct Workspace {
     int32_t *nbr;          // [kmax][Ntot] partner slots, column k of slot s at k * Ntot + s
     int32_t *nnb;          // [Ntot] partners of each slot
     int32_t *lflag;        // [8]: rebuild request for even / odd steps, list overflow, builds, scan ready,
-                           //      binning blocks done
+                           //      binning blocks done, poison (a rebuild gave up: the cell counts are
+                           //      stale until the force launch clears them, and the next step rebuilds)
     uint64_t *step_base;   // [1]: step number of a graph replay (see ListStep)
     void *fpart;           // [kMaxModeSplit][3][Ntot] partial forces of mode-split force passes (long
                            // mode lists only; NULL until rbe_reserve_modes raises the capacity)
+    double *diam;          // [Ntot] per-particle diameters (original order), or NULL
 };
 
 struct LaunchCfg {
@@ -166,6 +180,7 @@ struct LaunchCfg {
     int list_on;     // some system uses the neighbour list
     int kmax;        // list capacity per particle
     int n_list_tiles;
+    int wait_limit;  // spin bound of the device-side waits of a list rebuild
 };
 
 // Device view of the neighbour-list state for one step.
@@ -176,6 +191,7 @@ struct ListStep {
     int32_t *rebuilds;       // count of list builds
     int32_t *ready;          // rebuild: cell scan done (raised in the totals launch, reset by the staging launch)
     int32_t *bins_done;      // rebuild: binning blocks finished (same)
+    int32_t *poison;         // a rebuild gave up (see Workspace::lflag)
     int force_rebuild;
     // graph replays: the step numbers passed to the launches are offsets
     // from *step_base (device), which the force launch advances by `bump`

@@ -319,7 +319,9 @@ __global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T>
         // one request per block; block 0 adds the host's and the overflow's
         const int any = __syncthreads_or(moved ? 1 : 0);
         if (tid == 0) {
-            const bool req = any || (blockIdx.x == 0 && (a.ls.force_rebuild || *a.ls.overflow != 0));
+            // a rebuild that gave up in the step before is redone
+            const bool req =
+                any || (blockIdx.x == 0 && (a.ls.force_rebuild || *a.ls.overflow != 0 || *a.ls.poison != 0));
             if (req) atomicOr(a.ls.rebuild, 1);
         }
     } else {
@@ -558,7 +560,7 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
     fx *= -qi;
     fy *= -qi;
     fz *= -qi;
-    if (!isfinite(fx + fy + fz)) atomicOr(a.flag, 1);
+    if (!isfinite(fx + fy + fz)) atomicOr(a.flag, kFlagNonFinite);
     if (a.accumulate) {
         fx += a.F[i];
         fy += a.F[a.ntot + i];
@@ -569,6 +571,11 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
     a.F[2 * a.ntot + i] = fz;
     if (a.do_scatter) {
         const int slot = a.start[a.cellid[i] + sysi] + a.rank[i];
+        const SysDev &S = a.sys[sysi];
+        if (slot < S.off || slot >= S.off + S.n) {
+            atomicOr(a.flag, kFlagBounds);
+            return;
+        }
         a.sorted_idx[slot] = (int32_t)i;
         if constexpr (sizeof(T) == 4)
             reinterpret_cast<PackF *>(a.sorted)[slot] = reinterpret_cast<const PackF *>(a.packed)[i];
@@ -590,7 +597,7 @@ __global__ __launch_bounds__(256) void k_fsum(const T *__restrict__ fpart, int y
         for (int d = 0; d < 3; ++d) f[d] += fpart[((int64_t)y * 3 + d) * ntot + i];
     const T qi = q[i];
     for (int d = 0; d < 3; ++d) f[d] *= -qi;
-    if (!isfinite(f[0] + f[1] + f[2])) atomicOr(flag, 1);
+    if (!isfinite(f[0] + f[1] + f[2])) atomicOr(flag, kFlagNonFinite);
     for (int d = 0; d < 3; ++d) F[d * ntot + i] = accumulate ? F[d * ntot + i] + f[d] : f[d];
 }
 
@@ -602,9 +609,61 @@ __global__ __launch_bounds__(256) void k_fsum(const T *__restrict__ fpart, int y
 // k_l = 2 pi m_l / L.  The (A, B) reduction has the shape of the structure
 // factor and reuses its tiling; the gather has the shape of the force pass.
 // ---------------------------------------------------------------------------
-struct alignas(16) PartG {
-    double x, y, z, gx, gy, gz;   // fractional position and q_i G_i
+// LDS record of the adjoint reduction: the particle's phase inputs and
+// q_i G_i.  Single precision takes the phase from the exact split of the box
+// fraction (the same phases as the forward passes), double the fraction.
+template <typename T>
+struct VjpRec;
+template <>
+struct VjpRec<float> {
+    struct alignas(16) type {
+        float hx, hy, hz, lx, ly, lz, gx, gy, gz, pad[3];
+    };
 };
+template <>
+struct VjpRec<double> {
+    struct alignas(16) type {
+        double x, y, z, gx, gy, gz;
+    };
+};
+
+__device__ __forceinline__ void vjp_record(const SysDev &S, double sx, double sy, double sz, float gx, float gy,
+                                           float gz, VjpRec<float>::type &v)
+{
+    split_frac(sx, S, v.hx, v.lx);
+    split_frac(sy, S, v.hy, v.ly);
+    split_frac(sz, S, v.hz, v.lz);
+    v.gx = gx;
+    v.gy = gy;
+    v.gz = gz;
+    v.pad[0] = v.pad[1] = v.pad[2] = 0.0f;
+}
+
+__device__ __forceinline__ void vjp_record(const SysDev &, double sx, double sy, double sz, double gx, double gy,
+                                           double gz, VjpRec<double>::type &v)
+{
+    v.x = sx;
+    v.y = sy;
+    v.z = sz;
+    v.gx = gx;
+    v.gy = gy;
+    v.gz = gz;
+}
+
+// sin and cos of a record's phase for mode m.
+__device__ __forceinline__ void vjp_sincos(const VjpRec<float>::type &v, float mx, float my, float mz, float &sn,
+                                           float &cs)
+{
+    const float rf = phase_split(mx, my, mz, v.hx, v.hy, v.hz, v.lx, v.ly, v.lz);
+    sn = __builtin_amdgcn_sinf(rf);
+    cs = __builtin_amdgcn_cosf(rf);
+}
+
+__device__ __forceinline__ void vjp_sincos(const VjpRec<double>::type &v, double mx, double my, double mz,
+                                           double &sn, double &cs)
+{
+    sincospi(2.0 * wrap_rev(fma(mx, v.x, fma(my, v.y, mz * v.z))), &sn, &cs);
+}
 
 template <typename T, typename KM, int BS>
 __global__ __launch_bounds__(BS) void k_vjp_reduce(const SysDev *__restrict__ sys, const Tile *__restrict__ tiles,
@@ -613,23 +672,21 @@ __global__ __launch_bounds__(BS) void k_vjp_reduce(const SysDev *__restrict__ sy
                                                    const KM *__restrict__ km, double *__restrict__ partial,
                                                    const int32_t *__restrict__ part_off)
 {
+    using VR = typename VjpRec<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const SysDev S = sys[t.sys];
-    PartG *sp = reinterpret_cast<PartG *>(smem);
-    double2 *red = reinterpret_cast<double2 *>(smem + sizeof(PartG) * t.count);
+    VR *sp = reinterpret_cast<VR *>(smem);
+    double2 *red = reinterpret_cast<double2 *>(smem + sizeof(VR) * t.count);
     const int tid = threadIdx.x;
     const int count = t.count;
     for (int j = tid; j < count; j += BS) {
         const int64_t i = S.off + t.start + j;
-        const double qi = (double)q[i];
-        PartG v;
-        v.x = frac01((double)pos[i] * S.invL);
-        v.y = frac01((double)pos[ntot + i] * S.invL);
-        v.z = frac01((double)pos[2 * ntot + i] * S.invL);
-        v.gx = qi * (double)gF[i];
-        v.gy = qi * (double)gF[ntot + i];
-        v.gz = qi * (double)gF[2 * ntot + i];
+        const T qi = q[i];
+        VR v;
+        vjp_record(S, frac01((double)pos[i] * S.invL), frac01((double)pos[ntot + i] * S.invL),
+                   frac01((double)pos[2 * ntot + i] * S.invL), qi * gF[i], qi * gF[ntot + i],
+                   qi * gF[2 * ntot + i], v);
         sp[j] = v;
     }
     __syncthreads();
@@ -644,6 +701,7 @@ __global__ __launch_bounds__(BS) void k_vjp_reduce(const SysDev *__restrict__ sy
         double A = 0.0, B = 0.0;
         if (act) {
             const KM k = km[S.moff + l];
+            const T mx = (T)k.m[0], my = (T)k.m[1], mz = (T)k.m[2];
             const T ax = (T)k.a[0], ay = (T)k.a[1], az = (T)k.a[2];
             for (int j0 = g; j0 < count; j0 += 8 * G) {
                 T a8 = 0, b8 = 0;
@@ -651,11 +709,10 @@ __global__ __launch_bounds__(BS) void k_vjp_reduce(const SysDev *__restrict__ sy
                 for (int u = 0; u < 8; ++u) {
                     const int j = j0 + u * G;
                     if (j < count) {
-                        const PartG v = sp[j];
-                        const double ph = wrap_rev(fma(k.m[0], v.x, fma(k.m[1], v.y, k.m[2] * v.z)));
+                        const VR v = sp[j];
                         T sn, cs;
-                        sincos_rev(ph, &sn, &cs);
-                        const T w = fma((T)v.gx, ax, fma((T)v.gy, ay, (T)v.gz * az));
+                        vjp_sincos(v, mx, my, mz, sn, cs);
+                        const T w = fma(v.gx, ax, fma(v.gy, ay, v.gz * az));
                         a8 = fma(w, cs, a8);
                         b8 = fma(w, sn, b8);
                     }
@@ -756,12 +813,13 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const SysDev *__restrict__ s
         const int64_t nparts = (int64_t)SPLIT * gridDim.y, gp = (int64_t)blockIdx.y * SPLIT + part;
         const int l0 = (int)((S.p * gp) / nparts), l1 = (int)((S.p * (gp + 1)) / nparts);
         const KV *kk = kv + S.moff;
+        typename VjpRec<T>::type rec;
+        vjp_record(S, sx, sy, sz, (T)0, (T)0, (T)0, rec);
 #pragma unroll 2
         for (int l = l0; l < l1; ++l) {
             const KV k = kk[l];
-            const double ph = wrap_rev(fma(k.m[0], sx, fma(k.m[1], sy, k.m[2] * sz)));
             T sn, cs;
-            sincos_rev(ph, &sn, &cs);
+            vjp_sincos(rec, (T)k.m[0], (T)k.m[1], (T)k.m[2], sn, cs);
             const T w = fma(gx, (T)k.a[0], fma(gy, (T)k.a[1], gz * (T)k.a[2]));
             const T Ck = (T)k.C, Sk = (T)k.S, Ak = (T)k.A, Bk = (T)k.B;
             dq -= fma(w, cs * Sk - sn * Ck, Ak * sn - Bk * cs);
@@ -956,6 +1014,8 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
         r.flag = w.flag;
         r.bins_done = ls->bins_done;
         r.n_bin = a.n_bin_blocks;
+        r.poison = ls->poison;
+        r.wait_limit = c.wait_limit;
     }
     const size_t sm = a.table_lds ? sizeof(double) * c.max_table : 0;
     const int nb = a.n_final_blocks + a.n_bin_blocks + a.n_sample_blocks + (do_scan ? c.R : 0) +
@@ -1032,7 +1092,7 @@ template <typename T, typename KM>
 static hipError_t vjp_reduce_dispatch(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q,
                                       const void *gF)
 {
-    const size_t sm = sizeof(PartG) * c.rho_chunk + sizeof(double2) * c.rho_block;
+    const size_t sm = sizeof(typename VjpRec<T>::type) * c.rho_chunk + sizeof(double2) * c.rho_block;
     const T *p = (const T *)pos, *qq = (const T *)q, *g = (const T *)gF;
     const KM *km = (const KM *)w.kmode;
     dim3 gr(c.n_rho_tiles);

@@ -2,7 +2,8 @@
 //
 // Paper: Jin, Li, Xu & Zhao, arXiv:2010.01559: the truncated erfc sum of
 // eq. (2.9) and the second term of eq. (2.11); the shifted Lennard-Jones
-// repulsion of eq. (4.1) with r_off = 0.  The paper leaves the neighbour
+// repulsion of eq. (4.1), with r_off = 0 or, from per-particle diameters,
+// r_off = (d_i + d_j)/2 - sigma (Sec. 4.2).  The paper leaves the neighbour
 // search open; here it is a cell list with cells of side >= the largest
 // cutoff (+ skin), rebuilt for every stand-alone evaluation, and inside
 // rbe_step a Verlet list of the pairs within cutoff + skin, rebuilt on the
@@ -63,26 +64,26 @@ struct PairE {
     double e_real, e_lj;
 };
 
-// Single-precision pair terms are added on a fixed grid of 2^-40 (as integers
+// Single-precision pair terms are added on a fixed grid of 2^-32 (as integers
 // held in double): every partial sum is exact, so a particle's real-space
 // force does not depend on the order in which its partners are visited (cell
 // ranks come from atomic counters; list and cell passes order partners
-// differently).  This holds while partial sums stay below 2^13 in magnitude,
-// far above the pair forces of these systems; the grid is far below
-// single-precision rounding.
+// differently).  This holds while partial sums stay below 2^21 in magnitude
+// (an LJ wall at r = 0.45 sigma, far inside anything these systems reach);
+// the grid is far below single-precision rounding of the forces.
 // A pair's force component phi * d on that grid.  In single precision the
-// scale is applied to phi first (a power of two, so (phi 2^40) d rounds to
-// the same float as (phi d) 2^40), and the rounding to an integer is done in
+// scale is applied to phi first (a power of two, so (phi 2^32) d rounds to
+// the same float as (phi d) 2^32), and the rounding to an integer is done in
 // single precision, where it is exact: the same values as
-// rint((double)(phi d) * 2^40) with fewer double-precision instructions.
-__device__ __forceinline__ float qphi(float phi) { return phi * 0x1p40f; }
+// rint((double)(phi d) * 2^32) with fewer double-precision instructions.
+__device__ __forceinline__ float qphi(float phi) { return phi * 0x1p32f; }
 __device__ __forceinline__ double qphi(double phi) { return phi; }
 __device__ __forceinline__ double qterm(float scaled) { return (double)rintf(scaled); }
 __device__ __forceinline__ double qterm(double v) { return v; }
 template <typename T>
 __device__ __forceinline__ double qscale()
 {
-    return sizeof(T) == 4 ? 0x1p-40 : 1.0;
+    return sizeof(T) == 4 ? 0x1p-32 : 1.0;
 }
 
 // Single-precision constants of one system's pair terms, held in registers.
@@ -103,7 +104,7 @@ __device__ __forceinline__ PairConstF pair_const_f(const SysDev &S)
     c.lj_sig2 = (float)S.lj_sig2;
     c.eps4 = (float)(4.0 * S.lj_eps);
     c.lj_shift = (float)S.lj_shift;
-    c.lj_on = S.lj_on;
+    c.lj_on = S.lj_on && !S.diam_on;   // with diameters the LJ term is formed in double (lj_offset)
     return c;
 }
 
@@ -164,13 +165,50 @@ __device__ __forceinline__ double pair_phi(const SysDev &S, double qi, double qj
         phi = -cq * g;
         if constexpr (ENERGY) e.e_real += 0.5 * cq * ec / r;
     }
-    if (S.lj_on && r2 < S.lj_rc2) {
+    if (S.lj_on && !S.diam_on && r2 < S.lj_rc2) {
         const double sr2 = S.lj_sig2 / r2;
         const double sr6 = sr2 * sr2 * sr2;
         phi += 4.0 * S.lj_eps * (6.0 * sr6 - 12.0 * sr6 * sr6) / r2;
         if constexpr (ENERGY) e.e_lj += 0.5 * (4.0 * S.lj_eps * (sr6 * sr6 - sr6) + S.lj_shift);
     }
     return phi;
+}
+
+// Shifted LJ of eq. (4.1) with r_off = (d_i + d_j)/2 - sigma from the two
+// diameters, in double: s = r - r_off is a small difference of two
+// distances that can be fifty times larger (a colloid against an ion), so r
+// comes from the exact displacement and s is formed in double.  Returns
+// dV/dr / r (the coefficient of d in the force on i) and adds half the pair
+// energy when ENERGY.
+template <bool ENERGY>
+__device__ __forceinline__ double lj_offset(const SysDev &S, double di, double dj, double r2, PairE &e)
+{
+    const double r = sqrt(r2);
+    const double sv = r - (0.5 * (di + dj) - S.lj_sig);
+    if (!(sv < S.lj_rc)) return 0.0;
+    const double sr2 = S.lj_sig2 / (sv * sv);
+    const double sr6 = sr2 * sr2 * sr2;
+    if constexpr (ENERGY) e.e_lj += 0.5 * (4.0 * S.lj_eps * (sr6 * sr6 - sr6) + S.lj_shift);
+    return 4.0 * S.lj_eps * (6.0 * sr6 - 12.0 * sr6 * sr6) / (sv * r);
+}
+
+// |d|^2 of two records in double: exact wrapped integer differences for
+// PackF, the wrapped double difference for PartD.
+__device__ __forceinline__ double r2_double(const PackF &a, const PackF &b, double L)
+{
+    const double u = L * (1.0 / 4294967296.0);
+    const double dx = (double)(int32_t)(b.x - a.x) * u, dy = (double)(int32_t)(b.y - a.y) * u,
+                 dz = (double)(int32_t)(b.z - a.z) * u;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ __forceinline__ double r2_double(const PartD &a, const PartD &b, double L)
+{
+    double sx = b.x - a.x, sy = b.y - a.y, sz = b.z - a.z;
+    sx = (sx - rint(sx)) * L;
+    sy = (sy - rint(sy)) * L;
+    sz = (sz - rint(sz)) * L;
+    return sx * sx + sy * sy + sz * sz;
 }
 
 // Displacement between two records.  rmax2 is the largest cutoff squared in
@@ -186,7 +224,7 @@ template <typename T>
 __device__ __forceinline__ Geo make_geo(const SysDev &S)
 {
     Geo g;
-    const double rmax2 = S.lj_on ? fmax(S.rc2, S.lj_rc2) : S.rc2;
+    const double rmax2 = S.rsearch2;
     g.scale = (float)(S.L * (1.0 / 4294967296.0));
     g.rmax2u = (float)(rmax2 / ((double)g.scale * (double)g.scale));
     g.rmax2 = rmax2;
@@ -271,7 +309,8 @@ struct RowScan {
 
 template <typename Rec>
 __device__ __forceinline__ void row_scan(const Rec &pa, int self, int cx, int yy, int zz, int nc,
-                                         const int32_t *st, const Rec *gs, const Geo &geo, RowScan &rs)
+                                         const int32_t *st, const Rec *gs, const Geo &geo, RowScan &rs, int lo,
+                                         int hi)
 {
     const int base = (zz * nc + yy) * nc;
     if (cx >= 1 && cx + 1 < nc) {
@@ -293,7 +332,14 @@ __device__ __forceinline__ void row_scan(const Rec &pa, int self, int cx, int yy
     }
     rs.walk = false;
     rs.m[0] = rs.m[1] = 0;
-    if (rs.nseg == 1) rs.b0[1] = rs.b1[1] = 0;
+    if (rs.nseg == 1) rs.b0[1] = rs.b1[1] = lo;
+    // cell starts come from the last complete scan; clamped to the system's
+    // slots [lo, hi) every range stays in bounds whatever they hold
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        rs.b0[s] = min(max(rs.b0[s], lo), hi);
+        rs.b1[s] = min(max(rs.b1[s], rs.b0[s]), hi);
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int b0 = rs.b0[s], b1 = rs.b1[s];
@@ -357,11 +403,14 @@ struct RealArgs {
     double *epart;           // ENERGY: [tiles][8]
     const void *km;          // per-mode force constants (KModeF / KModeD) for the fused Fourier force
     uint64_t kick_step;      // index of the step whose closing half kick is applied (its time step)
+    const double *diam;      // per-particle diameters (original order) when some system has them
 };
 
 // Neighbour-list state seen by the real-space pass of a step.
 struct ListArgs {
     ListStep ls;
+    int32_t *count;          // cell counts, cleared here after a rebuild gave up
+    int ncell_tot;
     const Tile *list_tiles;
     int n_rows, n_list;      // tiles of the cell pass and of the list pass
     int32_t *nbr;            // [kmax][Ntot] partner slots, column k of slot s at k * Ntot + s
@@ -386,8 +435,13 @@ __device__ __forceinline__ void finish_particle(const RealArgs<T> &a, const SysD
         ev[6] += fabs(qq);
         return;
     }
+    if (i < S.off || i >= (int64_t)S.off + S.n) {
+        // the slot's particle index is stale (a rebuild gave up before its scatter)
+        atomicOr(a.flag, kFlagBounds);
+        return;
+    }
     T fx = (T)fxd, fy = (T)fyd, fz = (T)fzd;
-    if (!isfinite(fx + fy + fz)) atomicOr(a.flag, 1);
+    if (!isfinite(fx + fy + fz)) atomicOr(a.flag, kFlagNonFinite);
     if (a.accumulate) {
         fx += a.F[i];
         fy += a.F[a.ntot + i];
@@ -396,7 +450,7 @@ __device__ __forceinline__ void finish_particle(const RealArgs<T> &a, const SysD
     a.F[i] = fx;
     a.F[a.ntot + i] = fy;
     a.F[2 * a.ntot + i] = fz;
-    if (a.vel) {
+    if (a.vel && i - S.off >= S.n_fixed) {
         // the same rounding as the deferred kick of the integrator
         const double h = 0.5 * step_dt(S, a.kick_step) / S.mass;
         a.vel[i] = (T)fma(h, (double)fx, (double)a.vel[i]);
@@ -509,6 +563,7 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
     if ((int)threadIdx.x >= t.count) return;
     const int il = t.start + threadIdx.x;
     const Rec pa = pk[il];
+    const double da = S.diam_on ? a.diam[S.off + il] : 0.0;
     double fx = 0, fy = 0, fz = 0;
     PairE e{0, 0};
     for (int j = 0; j < S.n; ++j) {
@@ -517,7 +572,8 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
         if (!near_test(pa, pb, geo)) continue;
         T dx, dy, dz, r2;
         displacement(pa, pb, geo, dx, dy, dz, r2);
-        const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
+        T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
+        if (S.diam_on) phi += (T)lj_offset<ENERGY>(S, da, a.diam[S.off + j], r2_double(pa, pb, S.L), e);
         const T ph = qphi(phi);
         fx += qterm(ph * dx);
         fy += qterm(ph * dy);
@@ -570,8 +626,9 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
         cell_coords<T>(pa, nc, cx, cy, cz);
         const int zz = (cz + r / 3 - 1 + nc) % nc, yy = (cy + r % 3 - 1 + nc) % nc;
         const int32_t *st = a.start + S.cell_off + t.sys;
-        row_scan(pa, slot, cx, yy, zz, nc, st, gs, geo, rs);
+        row_scan(pa, slot, cx, yy, zz, nc, st, gs, geo, rs, S.off, S.off + S.n);
     }
+    const double da = act && S.diam_on ? a.diam[a.sorted_idx[slot]] : 0.0;
     int pos = 0, total = 0;
     if constexpr (BUILD) {
         const int cnt = __builtin_popcountll(rs.m[0]) + __builtin_popcountll(rs.m[1]);
@@ -590,7 +647,8 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
         row_visit(pa, slot, rs, gs, geo, [&](const Rec &pb, int b) {
             T dx, dy, dz, r2;
             displacement(pa, pb, geo, dx, dy, dz, r2);
-            const T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
+            T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
+            if (S.diam_on) phi += (T)lj_offset<ENERGY>(S, da, a.diam[a.sorted_idx[b]], r2_double(pa, pb, S.L), e);
             const T ph = qphi(phi);
             fx += qterm(ph * dx);
             fy += qterm(ph * dy);
@@ -690,6 +748,7 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
         const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
         const Rec pa = gs[slot];
         qi = (T)pa.q;
+        const double da = S.diam_on ? a.diam[a.sorted_idx[slot]] : 0.0;
         const int n = la.nnb[slot];
         const int32_t *nb = la.nbr + slot;
         PairE e{0, 0};
@@ -711,7 +770,9 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
                 if (j + u * LPP < n) {
                     T dx, dy, dz, r2;
                     displacement(pa, pb[u], geo, dx, dy, dz, r2);
-                    const T phi = pair_phi<false>(pc, (T)pa.q, (T)pb[u].q, r2, e);
+                    T phi = pair_phi<false>(pc, (T)pa.q, (T)pb[u].q, r2, e);
+                    if (S.diam_on)
+                        phi += (T)lj_offset<false>(S, da, a.diam[a.sorted_idx[b[u]]], r2_double(pa, pb[u], S.L), e);
                     const T ph = qphi(phi);
                     fx += qterm(ph * dx);
                     fy += qterm(ph * dy);
@@ -746,6 +807,10 @@ __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
     // no launch of this kernel reads the step number: advance the replay's
     // base for the next steps
     if (la.ls.step_bump && blockIdx.x == 0 && threadIdx.x == 0) *la.ls.step_bump += la.ls.bump;
+    if (*la.ls.poison) {
+        // this step's rebuild gave up before its scan cleared the cell counts
+        for (int k = blockIdx.x * RL_BS + threadIdx.x; k < la.ncell_tot; k += gridDim.x * RL_BS) la.count[k] = 0;
+    }
     const int rebuild = *la.ls.rebuild;
     const int nb = rebuild ? la.n_rows : la.n_list;
     if ((int)blockIdx.x >= nb) return;
@@ -885,7 +950,7 @@ __global__ __launch_bounds__(RL_BS) void k_vjp_real(RealArgs<T> a, const T *__re
         const int zz = (cz + r / 3 - 1 + nc) % nc, yy = (cy + r % 3 - 1 + nc) % nc;
         const int32_t *st = a.start + S.cell_off + t.sys;
         RowScan rs;
-        row_scan(pa, slot, cx, yy, zz, nc, st, gs, geo, rs);
+        row_scan(pa, slot, cx, yy, zz, nc, st, gs, geo, rs, S.off, S.off + S.n);
         row_visit(pa, slot, rs, gs, geo, [&](const Rec &pb, int b) {
             T dx, dy, dz, r2;
             displacement(pa, pb, geo, dx, dy, dz, r2);
@@ -961,6 +1026,7 @@ static RealArgs<T> real_args(const LaunchCfg &c, const Workspace &w, void *force
     a.flag = w.flag;
     a.epart = w.energy_part;
     a.km = w.kmode;
+    a.diam = w.diam;
     return a;
 }
 
@@ -1013,6 +1079,8 @@ hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListSt
     la.nbr = w.nbr;
     la.nnb = w.nnb;
     la.kmax = c.kmax;
+    la.count = w.cell_count;
+    la.ncell_tot = c.ncell_tot;
     if (c.prec == RBE_FP64)
         real_step_dispatch<double>(c, real_args<double>(c, w, force, 0, vel_kick, nullptr, kick_step), la);
     else

@@ -62,6 +62,8 @@ struct RebuildArgs {
     int32_t *flag;
     int32_t *bins_done;     // binning blocks finished (reset by the staging launch)
     int n_bin;              // binning blocks of the launch
+    int32_t *poison;        // raised when a wait gives up, cleared by a complete scan
+    int wait_limit;         // spin bound of every wait
 };
 
 template <typename KM>
@@ -286,25 +288,33 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
 // over the 256-particle tiles, moving records into cell order.  The launch
 // has a few dozen 1024-thread blocks, all resident at once, and a block only
 // waits for blocks of lower index, so every wait ends; the waits are bounded
-// anyway and raise the error flag if the bound is reached.  The staging
+// anyway.  A wait that reaches its bound gives up: it raises the timeout bit
+// of the error word and the poison flag, and its block skips its work.  The
+// force launch of that step then clears the cell counts (the scan that would
+// have cleared them did not run) and the next step's staging launch asks for
+// a rebuild; the cell pass of the failed step reads the previous cell starts,
+// clamped to the system, so every access stays in bounds.  The staging
 // launch of each step resets bins_done and ready.
 // ---------------------------------------------------------------------------
 
-// Thread 0 waits (bounded) until *p reaches want; the block learns the
-// outcome.  A timeout sets bit 2 of the error flag.
-__device__ bool block_wait(int32_t *p, int want, int32_t *flag)
+// Thread 0 waits (at most `limit` polls) until *p reaches want; the block
+// learns the outcome.
+__device__ bool block_wait(int32_t *p, int want, int limit, int32_t *flag, int32_t *poison)
 {
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
         int ok = 0;
-        for (int it = 0; it < (1 << 24); ++it) {
+        for (int it = 0; it < limit; ++it) {
             if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) {
                 ok = 1;
                 break;
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        if (!ok) atomicOr(flag, 2);
+        if (!ok) {
+            atomicOr(flag, kFlagTimeout);
+            atomicOr(poison, 1);
+        }
         s_ok = ok;
     }
     __syncthreads();
@@ -318,12 +328,13 @@ __device__ bool block_wait(int32_t *p, int want, int32_t *flag)
 template <int NW, int NCH = kScanChunks>
 __device__ void rebuild_scan(const RebuildArgs &a)
 {
-    if (!block_wait(a.bins_done, a.n_bin, a.flag)) return;
+    if (!block_wait(a.bins_done, a.n_bin, a.wait_limit, a.flag, a.poison)) return;
     for (int r = 0; r < a.R; ++r) mid_scan<NW, NCH>(a.sys[r], r, a.count, a.start);
     __syncthreads();
     if (threadIdx.x == 0) {
         *a.overflow = 0;
         *a.builds += 1;
+        *a.poison = 0;
     }
     __threadfence();
     __syncthreads();
@@ -339,7 +350,7 @@ constexpr int kScatBatch = 4;
 template <typename Rec>
 __device__ void rebuild_scatter(const RebuildArgs &a, int b, int nb)
 {
-    if (!block_wait(a.ready, 1, a.flag)) return;
+    if (!block_wait(a.ready, 1, a.wait_limit, a.flag, a.poison)) return;
     const int k = threadIdx.x & 255;
     const int tpb = (int)(blockDim.x >> 8);
     const int stride = tpb * nb;
@@ -376,6 +387,12 @@ __device__ void rebuild_scatter(const RebuildArgs &a, int b, int nb)
 #pragma unroll
         for (int u = 0; u < kScatBatch; ++u)
             if (idx[u] >= 0) {
+                // a slot outside the system can only come from stale counts
+                const SysDev &S = a.sys[sys[u]];
+                if (slot[u] < S.off || slot[u] >= S.off + S.n) {
+                    atomicOr(a.flag, kFlagBounds);
+                    continue;
+                }
                 a.sorted_idx[slot[u]] = idx[u];
                 a.slot_of[idx[u]] = slot[u];
 #pragma unroll

@@ -30,6 +30,7 @@ RBE_ERR_HIP = -5
 RBE_ERR_NONFINITE = -6
 RBE_ERR_STATE = -7
 RBE_ERR_NO_DEVICE = -8
+RBE_ERR_TIMEOUT = -9
 RBE_FP32, RBE_FP64 = 0, 1
 RBE_LANGEVIN_BAOAB, RBE_LEAPFROG_ANDERSEN = 0, 1
 RBE_SAMPLER_EXACT, RBE_SAMPLER_MH, RBE_SAMPLER_FIXED = 0, 1, 2
@@ -37,13 +38,13 @@ RBE_PART_KSPACE, RBE_PART_REAL, RBE_PART_ALL = 1, 2, 3
 
 STATUS_NAMES = {0: "RBE_OK", -1: "RBE_ERR_INVALID", -2: "RBE_ERR_NOT_NEUTRAL", -3: "RBE_ERR_CUTOFF",
                 -4: "RBE_ERR_OOM", -5: "RBE_ERR_HIP", -6: "RBE_ERR_NONFINITE", -7: "RBE_ERR_STATE",
-                -8: "RBE_ERR_NO_DEVICE"}
+                -8: "RBE_ERR_NO_DEVICE", -9: "RBE_ERR_TIMEOUT"}
 
 # every symbol the header declares
 EXPORTED = ["rbe_normalizer", "rbe_create", "rbe_batch_create", "rbe_destroy", "rbe_last_error",
             "rbe_num_systems", "rbe_num_particles", "rbe_num_modes", "rbe_sample_k", "rbe_set_k",
             "rbe_reserve_modes", "rbe_kspace_forces", "rbe_real_forces", "rbe_step", "rbe_batch_step",
-            "rbe_energy", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_pair_histogram", "rbe_set_dt", "rbe_use_graphs", "rbe_get_tiles",
+            "rbe_energy", "rbe_check", "rbe_set_wait_limit", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_pair_histogram", "rbe_set_dt", "rbe_use_graphs", "rbe_get_tiles",
             "rbe_set_tiles", "rbe_autotune", "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name",
             "rbe_profile_count"]
 
@@ -59,14 +60,15 @@ class rbe_params(C.Structure):
                 ("r_cut", C.c_double), ("coulomb", C.c_double), ("lj_eps", C.c_double), ("lj_sigma", C.c_double),
                 ("lj_rcut", C.c_double), ("kT", C.c_double), ("gamma", C.c_double), ("dt", C.c_double),
                 ("mass", C.c_double), ("nu", C.c_double), ("skin", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
-                ("integrator", C.c_int32), ("sampler", C.c_int32), ("flags", C.c_int32)]
+                ("integrator", C.c_int32), ("sampler", C.c_int32), ("flags", C.c_int32),
+                ("n_fixed", C.c_int32), ("reserved", C.c_int32), ("diameter", C.c_void_p)]
 
 
 class rbe_energy_t(C.Structure):
     _fields_ = [("e_kspace", C.c_double), ("e_self", C.c_double), ("e_real", C.c_double), ("e_lj", C.c_double),
                 ("e_kin", C.c_double), ("virial", C.c_double), ("virial_kspace", C.c_double),
                 ("charge_sum", C.c_double),
-                ("nonfinite", C.c_int32), ("reserved", C.c_int32)]
+                ("nonfinite", C.c_int32), ("timeout", C.c_int32)]
 
 
 class rbe_tiles(C.Structure):
@@ -108,6 +110,8 @@ def lib():
     L.rbe_batch_step.argtypes = [vp, vp, vp, vp, vp, u64, i32]
     L.rbe_energy.argtypes = [vp, vp, vp, vp, C.POINTER(rbe_energy_t)]
     L.rbe_get_rho.argtypes = [vp, vp]
+    L.rbe_check.argtypes = [vp]
+    L.rbe_set_wait_limit.argtypes = [vp, i32]
     L.rbe_forces_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32]
     L.rbe_list_builds.argtypes = [vp, C.POINTER(i64)]
     L.rbe_use_graphs.argtypes = [vp, i32]
@@ -159,11 +163,20 @@ class Params:
     integrator: int = RBE_LANGEVIN_BAOAB
     sampler: int = RBE_SAMPLER_EXACT
     flags: int = 0
+    n_fixed: int = 0
+    diameter: np.ndarray | None = None   # [n] diameters of eq. (4.1), read at creation
 
     def to_c(self):
+        dp = None
+        if self.diameter is not None:
+            self.diameter = np.ascontiguousarray(self.diameter, dtype=np.float64)
+            if self.diameter.shape != (self.n,):
+                raise ValueError("diameter must have shape (n,)")
+            dp = self.diameter.ctypes.data
         return rbe_params(self.n, self.p, self.box, self.alpha, self.r_cut, self.coulomb, self.lj_eps,
                           self.lj_sigma, self.lj_rcut, self.kT, self.gamma, self.dt, self.mass, self.nu,
-                          self.skin, self.seed, self.precision, self.integrator, self.sampler, self.flags)
+                          self.skin, self.seed, self.precision, self.integrator, self.sampler, self.flags,
+                          self.n_fixed, 0, dp)
 
 
 DEFAULT_SKIN_FRACTION = 0.14
@@ -172,11 +185,14 @@ DEFAULT_SKIN_FRACTION = 0.14
 def params_from_system(s, precision=RBE_FP32, **over):
     """Params for a workloads.System; the neighbour-list skin defaults to
     0.14 of the largest cutoff (the fastest N = 1e5 electrolyte step: a
-    thinner skin rebuilds more often, a thicker one lists more pairs)."""
+    thinner skin rebuilds more often, a thicker one lists more pairs).
+    Per-particle diameters and immobile leading particles come from
+    ``s.extra`` ("diameter", "n_fixed") when present."""
     rmax = max(s.r_cut, s.lj[2] if s.lj[0] > 0 else 0.0)
     kw = dict(n=s.n, p=s.p, box=s.L, alpha=s.alpha, r_cut=s.r_cut, coulomb=s.coulomb, lj_eps=s.lj[0],
               lj_sigma=s.lj[1], lj_rcut=s.lj[2], kT=s.kT, gamma=s.gamma, dt=s.dt, mass=s.mass, seed=s.seed,
-              skin=DEFAULT_SKIN_FRACTION * rmax, precision=precision)
+              skin=DEFAULT_SKIN_FRACTION * rmax, precision=precision,
+              n_fixed=int(s.extra.get("n_fixed", 0)), diameter=s.extra.get("diameter"))
     kw.update(over)
     return Params(**kw)
 
@@ -332,6 +348,22 @@ def rbe_energy(ctx, pos, q, vel=None, allow_status=(RBE_OK,)):
     return st, res
 
 
+def rbe_check(ctx):
+    """Raises RBEError for a pending device error (non-finite force, or a list
+    rebuild whose bounded wait gave up); clears it.  Synchronises."""
+    _check(lib().rbe_check(ctx.handle), ctx.handle)
+
+
+def rbe_check_status(ctx):
+    """The status rbe_check would raise for (RBE_OK if none); clears it."""
+    return lib().rbe_check(ctx.handle)
+
+
+def rbe_set_wait_limit(ctx, limit):
+    """Spin bound of the device-side waits of a list rebuild (0: give up at once)."""
+    _check(lib().rbe_set_wait_limit(ctx.handle, int(limit)), ctx.handle)
+
+
 def rbe_get_rho(ctx):
     n = ctx.nmodes
     buf = np.zeros((n, 2), np.float64)
@@ -345,11 +377,14 @@ def rbe_forces_vjp(ctx, pos, q, grad_force, grad_pos, grad_q, parts=RBE_PART_ALL
                                 _scal(ctx, grad_q, "grad_q"), parts), ctx.handle)
 
 
-def rbe_list_builds(ctx):
-    """Neighbour-list builds made by rbe_step so far (-1: no list)."""
+def rbe_list_builds(ctx, allow_status=(RBE_OK,)):
+    """Neighbour-list builds made by rbe_step so far (-1: no list).  With
+    RBE_ERR_TIMEOUT in allow_status, returns (status, builds) instead."""
     v = C.c_int64()
-    _check(lib().rbe_list_builds(ctx.handle, C.byref(v)), ctx.handle)
-    return v.value
+    st = lib().rbe_list_builds(ctx.handle, C.byref(v))
+    if st not in allow_status:
+        _check(st, ctx.handle)
+    return (st, v.value) if len(allow_status) > 1 else v.value
 
 
 def rbe_pair_histogram(ctx, pos, q, r_max, nbins, counts):

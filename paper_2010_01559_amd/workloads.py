@@ -174,3 +174,47 @@ def gaussian_charge_system(n: int = 30000, seed: int = DEFAULT_SEED + 4, p: int 
     q = gaussian_charges(n, rng, 0.5)
     vel = velocities(n, rng)
     return System(f"gaussq-n{n}-p{p}", n, L, alpha, 3.5, p, pos, q, vel, seed, lj=(0.0, 1.0, 2.5))
+
+
+def colloid_system(n_salt: int = 0, seed: int = DEFAULT_SEED + 5, p: int = 100) -> System:
+    """The charge-inversion setup of Sec. 4.2 (after Lenz and Holm), lengths
+    in Angstrom and energies in k_B T: one colloid of diameter 100 with a
+    central charge -300 fixed at the centre of a periodic box of side 225.8,
+    200 trivalent counterions (+3), 300 + n_salt monovalent coions (-1) and
+    n_salt monovalent counterions (+1), all ions of diameter 4; Coulomb
+    prefactor l_B = 7.1; shifted LJ with sigma = 1, epsilon = 1 and the cutoff
+    R_c = 2^(1/6) on r - r_off, r_off = (d_i + d_j)/2 - sigma; alpha = 0.0072,
+    r_c = 40, p = 100 (the random batch row of Table 4).  n_salt = 1300 is
+    the 196 mM case.  The colloid is particle 0 and does not move; ions are
+    uniform in the box, redrawn while closer than 52.5 to the colloid centre
+    or 4 to a lower-indexed ion (periodic minimum image)."""
+    L, d_col, d_ion = 225.8, 100.0, 4.0
+    n_ion = 200 + (300 + n_salt) + n_salt
+    n = 1 + n_ion
+    rng = np.random.default_rng(seed)
+    centre = np.full(3, 0.5 * L)
+    pts = np.empty((n, 3))
+    pts[0] = centre
+    contact = 0.5 * (d_col + d_ion) + 0.5
+    todo = np.arange(1, n)
+    while todo.size:
+        pts[todo] = rng.random((todo.size, 3)) * L
+        d = pts[todo] - centre
+        d -= L * np.round(d / L)
+        bad = np.sqrt((d * d).sum(1)) < contact
+        tree = cKDTree(pts[1:], boxsize=L)
+        pairs = tree.query_pairs(d_ion, output_type="ndarray") + 1
+        redo = set(todo[bad].tolist())
+        if pairs.size:
+            redo |= set(np.maximum(pairs[:, 0], pairs[:, 1]).tolist())
+        todo = np.array(sorted(redo), dtype=int)
+    pts[pts >= L] = 0.0
+    q = np.concatenate([[-300.0], np.full(200, 3.0), np.full(300 + n_salt, -1.0), np.full(n_salt, 1.0)])
+    assert abs(q.sum()) < 1e-9
+    diam = np.full(n, d_ion)
+    diam[0] = d_col
+    vel = velocities(n, rng)
+    vel[:, 0] = 0.0
+    return System(f"colloid-n{n}-p{p}", n, L, 0.0072, 40.0, p, np.ascontiguousarray(pts.T), q, vel, seed,
+                  coulomb=7.1, lj=(1.0, 1.0, 2.0 ** (1.0 / 6.0)), dt=0.002,
+                  extra={"diameter": diam, "n_fixed": 1})

