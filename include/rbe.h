@@ -199,6 +199,26 @@ rbe_status rbe_reserve_modes(rbe_ctx *ctx, int32_t cap);
  * rbe_energy and rbe_forces_vjp. */
 rbe_status rbe_kspace_forces(rbe_ctx *ctx, const void *pos, const void *q, void *force, int32_t accumulate);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * Fourier-space force of rbe_kspace_forces for one system described by
+ * params (n, p, box, alpha, coulomb, precision; other fields ignored) and
+ * the caller's modes (device [3][p] int32, no zero vector), each with the
+ * random batch weight S/p, enqueued on `stream` (a hipStream_t, NULL = the
+ * default stream) without a context.  pos [3][n], q [n] and force [3][n]
+ * are the caller's device arrays in the precision of params; force is
+ * overwritten or accumulated.  Same kernels and tile shapes as a context,
+ * so the result equals rbe_set_k + rbe_kspace_forces bit for bit.
+ * The workspace is a fixed device array inside the library, one per GPU,
+ * held until the process ends (about 17 MB); calls never allocate.  Limits:
+ * n <= 2^20, p <= 512 (RBE_ERR_INVALID beyond, with the limit in the
+ * message of rbe_last_error(NULL)).  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (concurrent streams or threads) race
+ * and must be ordered by the caller.  Non-finite forces are not reported
+ * (there is no context to hold the state). */
+rbe_status rbe_kspace_forces_noalloc(const rbe_params *params, const int32_t *modes, const void *pos,
+                                     const void *q, void *force, int32_t accumulate, void *stream);
+
 /* Real-space force (eq. 2.11, second term, pairs with |r_ij + nL| <= r_cut,
  * minimum image) plus shifted LJ (eq. 4.1), on a cell list built on the fly
  * (all pairs when fewer than 3 cells fit along the box).  force is

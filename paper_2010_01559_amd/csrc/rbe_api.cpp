@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,7 +21,28 @@ using namespace rbe;
 
 namespace {
 
-thread_local std::string g_create_error = "no error";
+// Message of the last failed call that has no context (creation, or the
+// no-allocation entry point), in a fixed buffer so that setting it from the
+// no-allocation path allocates nothing.
+struct NullError {
+    char buf[512] = "no error";
+    NullError &operator=(const std::string &m) { return *this = m.c_str(); }
+    NullError &operator=(const char *m)
+    {
+        std::snprintf(buf, sizeof buf, "%s", m);
+        return *this;
+    }
+    const char *c_str() const { return buf; }
+};
+thread_local NullError g_create_error;
+
+void null_errf(const char *f, ...)
+{
+    va_list ap;
+    va_start(ap, f);
+    std::vsnprintf(g_create_error.buf, sizeof g_create_error.buf, f, ap);
+    va_end(ap);
+}
 
 const char *kKernelNames[K_COUNT] = {"sample", "stage",      "mid",        "kforce",   "scatter", "real",
                                      "energy", "vjp_reduce", "vjp_gather", "vjp_real", "misc"};
@@ -79,6 +101,40 @@ void build_cdf(double alpha, double L, std::vector<double> &out)
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// The constants of one system that the Fourier passes read: sizes, box,
+// splitting, normaliser S = H^3 - 1 (eqs. 3.1-3.2), the mode table bound and
+// the single-precision phase split (|m| <= 2M must satisfy |m| < 2^(22 - hi_bits)).
+void fourier_constants(const rbe_params &p, SysDev &s)
+{
+    s.n = p.n;
+    s.p = p.p;
+    s.M = table_half_width(p.alpha, p.box);
+    s.L = p.box;
+    s.invL = 1.0 / p.box;
+    s.alpha = p.alpha;
+    s.beta = std::sqrt(p.alpha);
+    s.coulomb = p.coulomb;
+    const double H = normaliser_H(p.alpha, p.box);
+    s.S = H * H * H - 1.0;
+    int bm = 0;
+    while ((1 << bm) <= 2 * s.M) ++bm;
+    s.hi_bits = std::min(14, 22 - bm);
+    s.hi_scale = std::ldexp(1.0f, s.hi_bits);
+    s.hi_inv = std::ldexp(1.0f, -s.hi_bits);
+}
+
+// Default tile shapes for ntot particles: one structure-factor block per
+// compute unit when the particles allow (the block's registers leave room
+// for one 1024-thread block per CU); four waves share a 64-particle tile in
+// the force pass while the tiles alone would not fill the chip several
+// times over, two beyond.
+int default_rho_chunk(int64_t ntot)
+{
+    return (int)std::min<int64_t>(512, std::max<int64_t>(64, ((ntot + 255) / 256 + 7) / 8 * 8));
+}
+
+int default_force_split(int64_t ntot) { return ntot >= 500000 ? 2 : 4; }
 
 // Largest centre distance at which the shifted LJ of eq. (4.1) still acts:
 // R_c without diameters (r_off = 0), else r_off + R_c of the pair of the two
@@ -491,12 +547,10 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     for (int r = 0; r < R; ++r) {
         const rbe_params &p = params[r];
         SysDev s{};
-        s.n = p.n;
-        s.p = p.p;
+        fourier_constants(p, s);
         s.off = (int32_t)off;
         s.moff = moff;
         s.cdf_off = (int32_t)cdf.size();
-        s.M = table_half_width(p.alpha, p.box);
         build_cdf(p.alpha, p.box, cdf);
         const double rmax = std::max(p.r_cut, p.lj_eps > 0.0 ? lj_reach(p) : 0.0);
         const double rlist = rmax + p.skin;
@@ -509,14 +563,7 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         s.lj_on = p.lj_eps > 0.0 ? 1 : 0;
         s.integrator = p.integrator;
         s.mh_state_off = 3 * r;
-        s.L = p.box;
-        s.invL = 1.0 / p.box;
-        s.alpha = p.alpha;
-        s.beta = std::sqrt(p.alpha);
         s.rc2 = p.r_cut * p.r_cut;
-        s.coulomb = p.coulomb;
-        const double H = normaliser_H(p.alpha, p.box);
-        s.S = H * H * H - 1.0;
         s.lj_eps = p.lj_eps;
         s.lj_sig2 = p.lj_sigma * p.lj_sigma;
         s.lj_rc2 = p.lj_rcut * p.lj_rcut;
@@ -540,14 +587,6 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         s.nu = p.nu;
         s.anneal = 0.0;
         s.seed = p.seed;
-        // split of FP32 phases: |m| <= 2M must satisfy |m| < 2^(22 - hi_bits)
-        {
-            int bm = 0;
-            while ((1 << bm) <= 2 * s.M) ++bm;
-            s.hi_bits = std::min(14, 22 - bm);
-            s.hi_scale = std::ldexp(1.0f, s.hi_bits);
-            s.hi_inv = std::ldexp(1.0f, -s.hi_bits);
-        }
         s.use_list = (all_skin && nc >= 3) ? 1 : 0;
         s.rlist2 = rlist * rlist;
         s.half_skin2 = 0.25 * p.skin * p.skin;
@@ -580,13 +619,9 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     g.prec = c->prec;
     g.ntot = ntot;
     g.mcap = c->mcap;
-    // one structure-factor block per compute unit when the particles allow:
-    // the block's registers leave room for one 1024-thread block per CU
-    g.rho_chunk = (int)std::min<int64_t>(512, std::max<int64_t>(64, ((ntot + 255) / 256 + 7) / 8 * 8));
+    g.rho_chunk = default_rho_chunk(ntot);
     g.rho_block = 1024;
-    // waves sharing a 64-particle tile in the force pass: four while the
-    // tiles alone would not fill the chip several times over, two beyond
-    g.force_split = ntot >= 500000 ? 2 : 4;
+    g.force_split = default_force_split(ntot);
     g.real_split = 4;
     g.kmax = std::min((kmax + 7) & ~7, 1024);
     g.list_on = 0;
@@ -1466,6 +1501,156 @@ rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps
     if (s != RBE_OK) return s;
     if ((s = rbe_set_tiles(c, &win)) != RBE_OK) return s;
     if (best) *best = win;
+    return RBE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Fourier force without allocation.  Its workspace (system constants, tiles,
+// structure-factor partials and totals, per-mode constants) is one
+// file-scope device array of fixed size: each GPU the library runs on holds
+// its own copy until the process ends.  Host code never uses the array's
+// name as an address; each device's address is taken once, with that device
+// current, by hipGetSymbolAddress, and only that pointer reaches kernels.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kStaticMaxN = 1 << 20;     // particles
+constexpr int kStaticMaxP = 512;             // modes
+constexpr int kStaticMaxRhoTiles = 2048;     // structure-factor tiles of default_rho_chunk up to kStaticMaxN
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kOffSys = 0;
+constexpr size_t kOffPartOff = kOffSys + align256(sizeof(SysDev));
+constexpr size_t kOffFlag = kOffPartOff + 256;
+constexpr size_t kOffRhoTiles = kOffFlag + 256;
+constexpr size_t kOffForceTiles = kOffRhoTiles + align256(sizeof(Tile) * kStaticMaxRhoTiles);
+constexpr size_t kOffModeW = kOffForceTiles + align256(sizeof(Tile) * (kStaticMaxN / 64));
+constexpr size_t kOffRho = kOffModeW + align256(sizeof(double) * kStaticMaxP);
+constexpr size_t kOffKmode = kOffRho + align256(sizeof(double) * 2 * kStaticMaxP);
+constexpr size_t kOffPartial = kOffKmode + align256(sizeof(KModeD) * kStaticMaxP);
+constexpr size_t kStaticBytes = kOffPartial + sizeof(double) * 2 * (size_t)kStaticMaxRhoTiles * kStaticMaxP;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch` (the device must be current).  The first
+// call on a device checks that it is a gfx950 and takes the address.
+rbe_status scratch_of_device(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        null_errf("device %d is beyond the %d devices this entry point tracks", dev, kMaxDevices);
+        return RBE_ERR_NO_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            (void)hipGetLastError();
+            null_errf("device %d is not gfx950", dev);
+            return RBE_ERR_NO_DEVICE;
+        }
+        unsigned char *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            null_errf("hipGetSymbolAddress of the static workspace failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return RBE_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RBE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rbe_status rbe_kspace_forces_noalloc(const rbe_params *params, const int32_t *modes, const void *pos,
+                                     const void *q, void *force, int32_t accumulate, void *stream)
+{
+    if (!params || !modes || !pos || !q || !force) {
+        g_create_error = "params, modes, pos, q and force must be non-NULL";
+        return RBE_ERR_INVALID;
+    }
+    const rbe_params &p = *params;
+    if (p.n < 1 || p.n > kStaticMaxN) {
+        null_errf("n = %d is outside [1, %lld], the size of this entry point's fixed workspace", p.n,
+                  (long long)kStaticMaxN);
+        return RBE_ERR_INVALID;
+    }
+    if (p.p < 1 || p.p > kStaticMaxP) {
+        null_errf("p = %d is outside [1, %d], the size of this entry point's fixed workspace", p.p, kStaticMaxP);
+        return RBE_ERR_INVALID;
+    }
+    if (!finite_pos(p.box) || !finite_pos(p.alpha) || !std::isfinite(p.coulomb)) {
+        null_errf("box and alpha must be finite and > 0, coulomb finite");
+        return RBE_ERR_INVALID;
+    }
+    if (p.precision != RBE_FP32 && p.precision != RBE_FP64) {
+        null_errf("unknown precision %d", p.precision);
+        return RBE_ERR_INVALID;
+    }
+    const double H = normaliser_H(p.alpha, p.box);
+    if (1.0 / (H * H * H) > 0.5 || (p.precision == RBE_FP32 && table_half_width(p.alpha, p.box) > 4095)) {
+        null_errf("alpha L^2 = %.3g is outside the range of the mode table", p.alpha * p.box * p.box);
+        return RBE_ERR_INVALID;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        null_errf("no HIP device available");
+        return RBE_ERR_NO_DEVICE;
+    }
+    unsigned char *base = nullptr;
+    rbe_status st = scratch_of_device(dev, &base);
+    if (st != RBE_OK) return st;
+
+    SysDev sys{};
+    fourier_constants(p, sys);
+    LaunchCfg c{};
+    c.stream = (hipStream_t)stream;
+    c.R = 1;
+    c.prec = p.precision;
+    c.ntot = p.n;
+    c.mcap = p.p;
+    c.max_p = p.p;
+    c.rho_chunk = default_rho_chunk(p.n);
+    c.rho_block = 1024;
+    c.force_split = default_force_split(p.n);
+    c.n_rho_tiles = (p.n + c.rho_chunk - 1) / c.rho_chunk;
+    c.n_force_tiles = (p.n + 63) / 64;
+    if (c.n_rho_tiles > kStaticMaxRhoTiles) {
+        null_errf("internal: %d structure-factor tiles exceed the fixed workspace", c.n_rho_tiles);
+        return RBE_ERR_INVALID;
+    }
+    Workspace w{};
+    w.sys = reinterpret_cast<SysDev *>(base + kOffSys);
+    w.partial_off = reinterpret_cast<int32_t *>(base + kOffPartOff);
+    w.flag = reinterpret_cast<int32_t *>(base + kOffFlag);
+    w.rho_tiles = reinterpret_cast<Tile *>(base + kOffRhoTiles);
+    w.force_tiles = reinterpret_cast<Tile *>(base + kOffForceTiles);
+    w.mode_w = reinterpret_cast<double *>(base + kOffModeW);
+    w.rho = reinterpret_cast<double *>(base + kOffRho);
+    w.kmode = base + kOffKmode;
+    w.partial = reinterpret_cast<double *>(base + kOffPartial);
+    w.modes = const_cast<int32_t *>(modes);
+
+    auto hip_err = [](hipError_t e, const char *what) {
+        null_errf("%s: %s", what, hipGetErrorString(e));
+        return RBE_ERR_HIP;
+    };
+    hipError_t e = launch_static_setup(c, w, sys);
+    if (e != hipSuccess) return hip_err(e, "static workspace set-up");
+    StageRequest rq{const_cast<void *>(pos), nullptr, nullptr, q, 0, 0, 0, 0, 0, 1};
+    rq.mode_split = mode_split(c.n_rho_tiles, p.p, 256);
+    if ((e = launch_stage(c, w, rq)) != hipSuccess) return hip_err(e, "structure-factor launch");
+    if ((e = launch_mid(c, w, 1, 0)) != hipSuccess) return hip_err(e, "totals launch");
+    if ((e = launch_kforce(c, w, pos, q, force, accumulate, 0, 1)) != hipSuccess) return hip_err(e, "force launch");
     return RBE_OK;
 }
 

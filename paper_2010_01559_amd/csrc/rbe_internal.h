@@ -241,6 +241,7 @@ hipError_t launch_vjp_gather(const LaunchCfg &c, const Workspace &w, const void 
 hipError_t launch_vjp_real(const LaunchCfg &c, const Workspace &w, const void *gF, void *gpos, void *gq,
                            int accumulate);
 hipError_t launch_fill_zero(hipStream_t s, void *ptr, int64_t nbytes);
+hipError_t launch_static_setup(const LaunchCfg &c, const Workspace &w, const SysDev &sys);
 int real_rows_per_tile();
 int real_allpairs_per_tile();
 

@@ -1164,3 +1164,37 @@ hipError_t launch_vjp_gather(const LaunchCfg &c, const Workspace &w, const void 
 }
 
 }  // namespace rbe
+
+namespace rbe {
+
+// ---------------------------------------------------------------------------
+// Context-free Fourier force (the no-allocation entry point): the system
+// constants, the tiles of both passes, the partial offsets and the weights
+// S/p are written by this kernel into the workspace the caller points to
+// (kernel arguments are copied at launch, so no host buffer outlives the
+// call).  Tiles follow the same rules as a context's.
+// ---------------------------------------------------------------------------
+__global__ void k_static_setup(SysDev sys, int chunk, int nrho, int nforce, SysDev *sysp, Tile *rho_tiles,
+                               Tile *force_tiles, int32_t *part_off, double *mode_w)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *sysp = sys;
+        part_off[0] = 0;
+        part_off[1] = nrho;
+    }
+    if (i < nrho) rho_tiles[i] = Tile{0, i * chunk, min(chunk, sys.n - i * chunk), i};
+    if (i < nforce) force_tiles[i] = Tile{0, i * 64, min(64, sys.n - i * 64), 0};
+    if (i < sys.p) mode_w[i] = sys.S / (double)sys.p;
+}
+
+hipError_t launch_static_setup(const LaunchCfg &c, const Workspace &w, const SysDev &sys)
+{
+    const int most = std::max(std::max(c.n_rho_tiles, c.n_force_tiles), std::max(sys.p, 1));
+    k_static_setup<<<(most + 255) / 256, 256, 0, c.stream>>>(sys, c.rho_chunk, c.n_rho_tiles, c.n_force_tiles,
+                                                             w.sys, w.rho_tiles, w.force_tiles, w.partial_off,
+                                                             w.mode_w);
+    return hipGetLastError();
+}
+
+}  // namespace rbe

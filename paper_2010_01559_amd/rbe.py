@@ -46,7 +46,7 @@ EXPORTED = ["rbe_normalizer", "rbe_create", "rbe_batch_create", "rbe_destroy", "
             "rbe_reserve_modes", "rbe_kspace_forces", "rbe_real_forces", "rbe_step", "rbe_batch_step",
             "rbe_energy", "rbe_check", "rbe_set_wait_limit", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_pair_histogram", "rbe_set_dt", "rbe_use_graphs", "rbe_get_tiles",
             "rbe_set_tiles", "rbe_autotune", "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name",
-            "rbe_profile_count"]
+            "rbe_profile_count", "rbe_kspace_forces_noalloc"]
 
 
 class RBEError(RuntimeError):
@@ -111,6 +111,7 @@ def lib():
     L.rbe_energy.argtypes = [vp, vp, vp, vp, C.POINTER(rbe_energy_t)]
     L.rbe_get_rho.argtypes = [vp, vp]
     L.rbe_check.argtypes = [vp]
+    L.rbe_kspace_forces_noalloc.argtypes = [C.POINTER(rbe_params), vp, vp, vp, vp, i32, vp]
     L.rbe_set_wait_limit.argtypes = [vp, i32]
     L.rbe_forces_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32]
     L.rbe_list_builds.argtypes = [vp, C.POINTER(i64)]
@@ -318,6 +319,29 @@ def rbe_reserve_modes(ctx, cap):
 def rbe_kspace_forces(ctx, pos, q, force, accumulate=False):
     _check(lib().rbe_kspace_forces(ctx.handle, _vec3(ctx, pos, "pos"), _scal(ctx, q, "q"),
                                    _vec3(ctx, force, "force"), int(accumulate)), ctx.handle)
+
+
+def rbe_kspace_forces_noalloc(params, modes, pos, q, force, accumulate=False, stream=None):
+    """Context-free Fourier force with the caller's modes ([3, p] int32 on the
+    GPU); nothing is allocated (the library's fixed workspace is used)."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    dt = torch.float64 if params.precision == RBE_FP64 else torch.float32
+    n = params.n
+
+    def ptr(t, shape, dtype, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != dtype or \
+                tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} GPU tensor of shape {tuple(shape)}")
+        return C.c_void_p(t.data_ptr())
+
+    cp = params.to_c()
+    st = lib().rbe_kspace_forces_noalloc(C.byref(cp), ptr(modes, (3, params.p), torch.int32, "modes"),
+                                         ptr(pos, (3, n), dt, "pos"), ptr(q, (n,), dt, "q"),
+                                         ptr(force, (3, n), dt, "force"), int(accumulate),
+                                         C.c_void_p(stream.cuda_stream))
+    _check(st)
 
 
 def rbe_real_forces(ctx, pos, q, force, accumulate=False):
