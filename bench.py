@@ -3,23 +3,26 @@
 Workload: N = 1e5 ions (+-1) at density 0.1 (L = 100), r_c = 3.5, P = 100
 modes per step, alpha from the 1e-4 real-space error estimate, shifted LJ
 (eps = 1, sigma = 1, cut 2.5), Langevin kT = 1, gamma = 1, dt = 1e-3, float32
-arithmetic with double phases.  Inputs are synthetic and resident on the GPU
-before timing starts.
+arithmetic with phases split exactly and double-precision reductions.
+Inputs are synthetic and resident on the GPU before timing starts.
 
 A timed "step" is one pass of the whole hot path: a fresh batch of P modes,
 structure factors, the Fourier force, the neighbour list (rebuilt on the
 device when particles have moved far enough), the real-space + LJ force and
 the Langevin update; the K timed steps are one rbe_step call.  The headline
-value is N*P*steps / elapsed seconds over those full steps.  The JSON line also reports MD steps/s, the
+value is N*P*steps / elapsed seconds over those full steps.  The JSON line
+also reports MD steps/s, the list builds inside the timed window, the
 Fourier-only pair rate (sample + structure factor + force), per-kernel
-durations from HIP events on the library's stream, the ALU roofline of every
-kernel of the step (the longest one as "roofline"), and the FP64 CPU oracle
-timed on the host.
+durations (events carried by the kernels' own dispatches, the same steps
+again), the ALU roofline of each kernel from algorithmic operation counts
+(the longest one per step as "roofline"), the same work against bounds
+calibrated on this device, and the FP64 CPU oracle timed on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--autotune] [--calibrate-copy] [--graphs]
-       python bench.py --suite PATH   (N x P sweep, batched vs loop,
-                                       forward vs backward, classical Ewald)
+       python bench.py --calibrate      (device micro-benchmarks only)
+       python bench.py --suite PATH     (N x P sweep, batched vs loop,
+                                         forward vs backward, classical Ewald)
 """
 from __future__ import annotations
 
@@ -37,39 +40,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "k-space particle–mode pairs/s (N·P) + MD steps/s at N=1e5, P=100, 1 GPU"
 
-# Algorithmic work in FP32 VALU issue slots (an FP64 add/mul/FMA takes 2, a
-# transcendental op 4) and the chip's FP32 vector peak: 256 CUs x 128 FP32
-# lanes/clock x 2 flop x 2.4 GHz.  One slot counts as 2 flop.
-# Per particle-mode pair, with the phase of the exact-wrap FP32 scheme
-# (theta = fract(m . s_hi) + m . s_lo: 3 products, 1 fract, 3 FMA, 1 add):
-SLOTS_PHASE = 8
-SLOTS_RHO = SLOTS_PHASE + 2 * 4 + 2           # phase, sin+cos, 2 FMA into (C, S)
-SLOTS_FORCE = SLOTS_PHASE + 2 * 4 + 2 + 3     # phase, sin+cos, cos S - sin C, 3 FMA into F
-# Real space, per neighbour-list entry (3 integer differences, 3
-# conversions, |d|^2, compare) and per pair inside the cutoff (displacement,
-# rsqrt, exp, the erfc rational form with its reciprocal, Coulomb and LJ
-# factors, force accumulation); both counted over ordered pairs.
-SLOTS_CHECK = 10
-SLOTS_PAIR = 6 + 3 + 3 * 4 + 3 + 5 + 9 + 4 + 3 + 6 + 6
-PEAK_FP32_TFLOPS = 157.3
+# Algorithmic work, in FP32 lane operations (an add, multiply, fused
+# multiply-add or hardware transcendental each counts one), split into
+# (VALU, transcendental).  Per particle-mode pair and pass the phase m.s is
+# three multiply-adds and a wrap; the structure factor adds two multiply-adds
+# into (C, S), the force cos(th) S - sin(th) C and three multiply-adds into F
+# (paper Sec. 3.1, eq. 3.6, with rho of eq. 2.7).  Real space: every list
+# entry is a distance test (3 differences, |d|^2, compare, select); a pair
+# inside the cutoff adds rsqrt, exp and a reciprocal, r and beta r, the
+# erfc polynomial, G(r), the charge product, the LJ term and three force
+# components (eq. 2.11, eq. 4.1).  Implementation extras (the exact phase
+# split, fixed-point sums) are not counted.
+OPS = {
+    "rho_pair": (6, 2),
+    "force_pair": (9, 2),
+    "list_entry": (8, 0),
+    "cutoff_pair": (22, 3),
+}
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (published)
+PEAK_HBM_GBS = 8000.0
 
 # HBM traffic per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch, averaged over the launches of the profiled
 # run), each multiplied by the ratio of the true size of a 256 MiB device
 # copy to what the same counter reads for it.  Valid only for the kernel
 # source it was taken on (sha256 prefix); otherwise reported as null.
-# "stage" is the time-step variant of k_stage_rho, "stage_fourier" the
-# variant of force calls that also draws the modes recorded by rbe_sample_k.
-TRAFFIC = {
-    "real": {"fetch_kib": 9011.6, "write_kib": 7812.9, "fetch_scale": 2.0, "write_scale": 1.0,
-             "src": "bb2bd7dfd861268b"},
-    "stage": {"fetch_kib": 3155.2, "write_kib": 7168.7, "fetch_scale": 2.0, "write_scale": 1.0,
-              "src": "aefb4ec43f9b949a"},
-    "stage_fourier": {"fetch_kib": 916.8, "write_kib": 402.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                      "src": "aefb4ec43f9b949a"},
-    "kforce": {"fetch_kib": 940.9, "write_kib": 1171.9, "fetch_scale": 2.0, "write_scale": 1.0,
-               "src": "aefb4ec43f9b949a"},
-}
+TRAFFIC = {}
 
 
 def parse():
@@ -81,24 +77,70 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true", help="pick the Fourier tile shapes by timing")
     ap.add_argument("--suite", metavar="PATH", help="run the sweep/batched/gradient/Ewald suite into PATH instead")
+    ap.add_argument("--calibrate", action="store_true", help="print the device micro-benchmarks and exit")
     ap.add_argument("--graphs", action="store_true", help="replay the steady-state steps from hipGraphs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(s, modes, budget_s):
-    """Time the FP64 oracle's Fourier evaluation (structure factor + force) on
-    the metric workload: whole evaluations at N = 1e5, P = 100 repeated until
-    the budget is spent, with every host thread, then single-threaded."""
+def calibration(R, reps=5):
+    """Device micro-benchmarks of the library (rbe_calibrate): rates of the
+    hardware sine/cosine, non-packed FP32 and FP64 FMA, and a device copy."""
+    return {name: R.rbe_calibrate(k, reps) for k, name in R.CALIBRATION_KINDS.items()}
+
+
+def kspace_bound_pairs_per_s(cal):
+    """Pairs/s of one Fourier evaluation (structure factor + force) if its
+    algorithmic work ran at the calibrated rates, transcendental and VALU
+    issue not overlapping."""
+    valu = OPS["rho_pair"][0] + OPS["force_pair"][0]
+    trans = OPS["rho_pair"][1] + OPS["force_pair"][1]
+    return 1.0 / (trans / cal["sin_cos_lane_ops_per_s"] + valu / cal["fp32_fma_lane_ops_per_s"])
+
+
+def alu_roofline(units, us, cal=None, traffic=None):
+    """units: {OPS key: count per launch}; us: average launch duration."""
+    valu = sum(OPS[k][0] * n for k, n in units.items())
+    trans = sum(OPS[k][1] * n for k, n in units.items())
+    ops = valu + trans
+    ach = ops / (us * 1e-6) / 1e12
+    out = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "avg_launch_us": round(us, 2),
+           "ops_per_launch": int(ops), "units": {k: int(n) for k, n in units.items()}}
+    if cal:
+        bound_us = 1e6 * (trans / cal["sin_cos_lane_ops_per_s"] + valu / cal["fp32_fma_lane_ops_per_s"])
+        out["calibrated"] = {"bound_us": round(bound_us, 2), "frac": round(bound_us / us, 4)}
+    return out
+
+
+def cpu_baseline(s, budget_s):
+    """Time the FP64 oracle on the metric workload: whole MD steps (a fresh
+    mode sample, structure factor and Fourier force, real space on the
+    oracle's linked cells, BAOAB) repeated until the budget is spent, with
+    every host thread, then single-threaded; and the Fourier evaluation
+    alone."""
     import oracle as O
     O.build()
     pos = s.pos.astype(np.float32).astype(np.float64)
-    q = s.q
-    w = O.rbe_weights(s.alpha, s.L, s.p)
-    O.rbe_kspace_force(pos[:, :1000], q[:1000], s.L, s.alpha, modes)  # load + warm
+    vel = s.vel.astype(np.float32).astype(np.float64)
+    q = s.q.astype(np.float64)
+    sysd = O.make_sys(s.n, s.p, s.L, s.alpha, s.r_cut, s.coulomb, s.lj, s.kT, s.gamma, s.dt, s.mass, s.seed)
+    F = O.total_force(sysd, pos, q, 0)
 
-    def rate(budget):
+    def md_rate(budget, first):
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            O.baoab_step(sysd, pos, vel, q, F, first + steps)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > budget or steps >= 500:
+                return s.n * s.p * steps / el, steps, el
+
+    modes, _ = O.sample_modes(s.alpha, s.L, s.p, s.seed, 0)
+    w = O.rbe_weights(s.alpha, s.L, s.p)
+
+    def fourier_rate(budget):
         reps, t0 = 0, time.perf_counter()
         while True:
             O.kspace_force(pos, q, s.L, modes, w)
@@ -108,15 +150,18 @@ def cpu_baseline(s, modes, budget_s):
                 return s.n * s.p * reps / el, reps, el
 
     threads = O.set_threads(0)
-    v, reps, el = rate(budget_s)
+    v, steps, el = md_rate(budget_s, 1)
+    vf, reps, elf = fourier_rate(budget_s / 3)
     O.set_threads(1)
-    v1, reps1, el1 = rate(budget_s / 2)
+    v1, steps1, el1 = md_rate(budget_s / 3, 1 + steps)
     O.set_threads(threads)
     return {"value": v, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} full Fourier evaluations (structure factor + force, FP64) of the N={s.n}, "
-                      f"P={s.p} workload in {el:.1f} s on {threads} threads; single-threaded {reps1} "
-                      f"in {el1:.1f} s",
-            "single_thread_value": v1, "host_cpu": _cpu_model()}
+            "sample": f"{steps} full MD steps (mode sample, structure factor and Fourier force, linked-cell "
+                      f"real space + LJ, BAOAB; FP64) of the N={s.n}, P={s.p} workload in {el:.1f} s on "
+                      f"{threads} threads; single-threaded {steps1} steps in {el1:.1f} s; Fourier evaluation "
+                      f"alone {reps} times in {elf:.1f} s on {threads} threads",
+            "single_thread_value": v1, "fourier_only_value": vf, "md_steps_per_s": steps / el,
+            "host_cpu": _cpu_model()}
 
 
 def _cpu_model():
@@ -187,13 +232,7 @@ def _kernel_us(R, ctx, fn, reps):
     R.rbe_profile_enable(ctx, False)
     return {name: 1e3 * ms / n for name, (ms, n) in prof.items() if n}
 
-
-def _frac(slots, us):
-    ach = slots * 2 / (us * 1e-6) / 1e12
-    return {"achieved": round(ach, 3), "frac": round(ach / PEAK_FP32_TFLOPS, 4), "avg_launch_us": round(us, 2)}
-
-
-def suite_np_sweep(torch, R, W, log):
+def suite_np_sweep(torch, R, W, log, cal):
     """N in {1e4, 1e5, 1e6} x P in {50, 100, 200, 500}: Fourier-only pairs/s
     (sample + structure factor + force), MD steps/s, and the ALU roofline of
     the structure-factor and force launches."""
@@ -221,8 +260,10 @@ def suite_np_sweep(torch, R, W, log):
             st_ms = _timed(torch, ctx.stream, lambda k: R.rbe_step(ctx, P, V, Q, F, 21 + 100 * k, 100), 1) / 100
             pairs = n * p
             row = {"n": n, "p": p, "kspace_pairs_per_s": pairs * 1e3 / k_ms, "kspace_ms": k_ms,
+                   "kspace_frac_of_calibrated_bound": pairs * 1e3 / k_ms / kspace_bound_pairs_per_s(cal),
                    "md_steps_per_s": 1e3 / st_ms, "md_pairs_per_s": pairs * 1e3 / st_ms, "md_ms": st_ms,
-                   "stage": _frac(pairs * SLOTS_RHO, kus["stage"]), "kforce": _frac(pairs * SLOTS_FORCE, kus["kforce"])}
+                   "stage": alu_roofline({"rho_pair": pairs}, kus["stage"], cal),
+                   "kforce": alu_roofline({"force_pair": pairs}, kus["kforce"], cal)}
             log(f"sweep n={n} p={p}: kspace {row['kspace_pairs_per_s']:.3e} pairs/s, "
                 f"step {1e3 * st_ms:.1f} us, stage {row['stage']['frac']}, kforce {row['kforce']['frac']}")
             out.append(row)
@@ -322,6 +363,14 @@ def suite_ewald(torch, R, W, log, tol=1e-4):
         row = {"n": n, "box": s.L, "ewald_modes": int(m.shape[1]), "ewald_kspace_ms": ew_ms,
                "ewald_pairs_per_s": n * m.shape[1] * 1e3 / ew_ms, "rbe_kspace_ms": rbe_ms,
                "real_space_ms": real_ms, "ewald_over_rbe": ew_ms / rbe_ms}
+        if n in (1000, 10000):
+            # the FP64 oracle's classical Ewald Fourier force on the host, same modes
+            import oracle as O
+            pos, q = s.pos.astype(np.float32).astype(np.float64), s.q
+            t0 = time.perf_counter()
+            O.kspace_force(pos, q, s.L, m, w)
+            row["oracle_ewald_kspace_ms"] = 1e3 * (time.perf_counter() - t0)
+            row["oracle_threads"] = O.set_threads(0)
         log(f"ewald n={n}: {m.shape[1]} modes {ew_ms:.3f} ms vs rbe {rbe_ms:.4f} ms")
         out.append(row)
         del ctx, P, Q, F
@@ -339,7 +388,9 @@ def run_suite(path):
         print(msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    res = {"sweep": suite_np_sweep(torch, R, W, log)}
+    cal = calibration(R)
+    log(f"calibration: {cal}")
+    res = {"calibration": cal, "sweep": suite_np_sweep(torch, R, W, log, cal)}
     res["batched"] = suite_batched(torch, R, W, log)
     res["gradient"] = suite_gradient(torch, R, W, log)
     res["ewald"] = suite_ewald(torch, R, W, log)
@@ -363,6 +414,9 @@ def main():
     from paper_2010_01559_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate:
+        print(json.dumps({"device": torch.cuda.get_device_name(0), "calibration": calibration(R)}))
+        return
     if args.calibrate_copy:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -387,7 +441,7 @@ def main():
 
     # ---- full MD steps (one rbe_step call advances all K steps) ----
     R.rbe_step(ctx, P, V, Q, F, 1, args.warmup)
-    torch.cuda.synchronize()
+    builds0 = R.rbe_list_builds(ctx)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     base = 1 + args.warmup
     torch.cuda.synchronize()
@@ -397,6 +451,8 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    builds_window = R.rbe_list_builds(ctx) - builds0
+    R.rbe_check(ctx)
     step_ms = e0.elapsed_time(e1) / args.steps
     ms_per_step = max(step_ms, 1e3 * wall / args.steps)
 
@@ -414,15 +470,17 @@ def main():
     torch.cuda.synchronize()
     k_ms = e0.elapsed_time(e1) / nk
 
-    # ---- per-kernel durations with HIP events on the library stream ----
+    # ---- per-kernel durations: events on the kernels' own dispatches ----
+    # (the same number of steps again, continuing the trajectory)
     R.rbe_profile_enable(ctx, True)
+    b1 = R.rbe_list_builds(ctx)
     R.rbe_step(ctx, P, V, Q, F, base + args.steps, args.steps)
     prof = R.rbe_profile_read(ctx)
+    builds_prof = R.rbe_list_builds(ctx) - b1
     R.rbe_profile_enable(ctx, False)
-    kern = {name: {"avg_us": 1e3 * ms / n, "launches": n} for name, (ms, n) in prof.items() if n}
-    step_kernel_us = sum(v["avg_us"] * v["launches"] for v in kern.values()) / args.steps
-    # the Fourier kernels alone (structure factor without the fused
-    # integrator/binning, and the force pass without the scatter)
+    kern = {name: {"avg_us": 1e3 * ms / n, "launches": n, "us_per_step": 1e3 * ms / args.steps}
+            for name, (ms, n) in prof.items() if n}
+    step_kernel_us = sum(v["us_per_step"] for v in kern.values())
     R.rbe_profile_enable(ctx, True)
     for k in range(nk):
         R.rbe_sample_k(ctx, 3 * 10 ** 6 + k)
@@ -431,37 +489,24 @@ def main():
     R.rbe_profile_enable(ctx, False)
     kkern = {name: {"avg_us": 1e3 * ms / n, "launches": n} for name, (ms, n) in kprof.items() if n}
 
+    cal = calibration(R)
     n, p = s.n, s.p
     pairs = n * p
-    cand, nb = real_space_counts(s, params.skin)
-    # the force launch of a step also evaluates the Fourier force
-    work = {"stage": pairs * SLOTS_RHO, "kforce": pairs * SLOTS_FORCE,
-            "real": cand * SLOTS_CHECK + nb * SLOTS_PAIR + pairs * SLOTS_FORCE}
-    rooflines = {}
-    for name, slots in work.items():
-        if name not in kern:
-            continue
-        us = kern[name]["avg_us"]
-        ach = slots * 2 / (us * 1e-6) / 1e12
-        rooflines[name] = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
-                           "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                           "traffic": traffic_for(name), "avg_launch_us": round(us, 2),
-                           "slots_per_launch": int(slots)}
-    dom = max(rooflines, key=lambda k: kern[k]["avg_us"])
-    roofline = dict(rooflines[dom], kernel=dom)
-    fourier = {}
-    for name, slots in (("kforce", pairs * SLOTS_FORCE), ("stage", pairs * SLOTS_RHO)):
-        us = kkern[name]["avg_us"]
-        ach = slots * 2 / (us * 1e-6) / 1e12
-        fourier[name] = {"achieved": round(ach, 3), "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                         "avg_launch_us": round(us, 2),
-                         "traffic": traffic_for("stage_fourier" if name == "stage" else name)}
+    entries, nb = real_space_counts(s, params.skin)
+    # work of one launch of each kernel of the step; the force launch of a
+    # step also evaluates the Fourier force
+    work = {"stage": {"rho_pair": pairs},
+            "real": {"force_pair": pairs, "list_entry": entries, "cutoff_pair": nb}}
+    rooflines = {name: alu_roofline(units, kern[name]["avg_us"], cal, traffic_for(name))
+                 for name, units in work.items() if name in kern}
+    dom = max(kern, key=lambda k: kern[k]["us_per_step"])
+    roofline = dict(rooflines[dom], kernel=dom) if dom in rooflines else None
+    fourier = {"stage": alu_roofline({"rho_pair": pairs}, kkern["stage"]["avg_us"], cal,
+                                     traffic_for("stage_fourier")),
+               "kforce": alu_roofline({"force_pair": pairs}, kkern["kforce"]["avg_us"], cal, traffic_for("kforce"))}
+    kbound = kspace_bound_pairs_per_s(cal)
 
-    cpu = None
-    if not args.no_cpu:
-        m = torch.zeros((3, p), dtype=torch.int32, device="cuda")
-        R.rbe_sample_k(ctx, 0, m)
-        cpu = cpu_baseline(s, m.cpu().numpy(), args.cpu_seconds)
+    cpu = None if args.no_cpu else cpu_baseline(s, args.cpu_seconds)
 
     out = {
         "metric": METRIC,
@@ -477,16 +522,21 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": s.name, "n": n, "p": p, "box": s.L, "alpha": round(s.alpha, 6),
-                   "r_cut": s.r_cut, "lj": list(s.lj), "dt": s.dt, "precision": "fp32 (fp64 phases)",
-                   "tiles": tiles},
+                   "r_cut": s.r_cut, "lj": list(s.lj), "dt": s.dt,
+                   "precision": "fp32 (exact split phases, fp64 reductions)", "tiles": tiles},
         "md_steps_per_s": 1e3 / ms_per_step,
+        "list_builds": {"timed_window": builds_window, "profiled_window": builds_prof, "steps": args.steps},
         "kspace_pairs_per_s": pairs * 1e3 / k_ms,
         "kspace_ms": k_ms,
+        "kspace_bound_pairs_per_s": kbound,
+        "kspace_frac_of_calibrated_bound": pairs * 1e3 / k_ms / kbound,
         "step_kernel_us": step_kernel_us,
-        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]} for k, v in kern.items()},
+        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
+                        "us_per_step": round(v["us_per_step"], 2)} for k, v in kern.items()},
         "kspace_kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
                            for k, v in kkern.items()},
-        "real_space": {"list_entries": cand, "pairs_in_cutoff": nb},
+        "real_space": {"list_entries": entries, "pairs_in_cutoff": nb},
+        "calibration": cal,
         "roofline": roofline,
         "rooflines": rooflines,
         "fourier_only_rooflines": fourier,

@@ -334,8 +334,10 @@ rbe_status rbe_set_tiles(rbe_ctx *ctx, const rbe_tiles *tiles);
  * and return it in *best (may be NULL).  Not a hot call. */
 rbe_status rbe_autotune(rbe_ctx *ctx, const void *pos, const void *q, int32_t reps, rbe_tiles *best);
 
-/* Per-kernel timing with hipEvents recorded around every launch on the
- * context stream while enabled (adds a little overhead). */
+/* Per-kernel timing while enabled: each logical kernel's launches carry
+ * hipEvents on their own dispatches (hipExtLaunchKernel), so the elapsed
+ * time is the kernels' execution as a kernel trace reports it, with no
+ * packets added between launches. */
 rbe_status rbe_profile_enable(rbe_ctx *ctx, int32_t enable);
 /* Accumulated milliseconds and launch count of kernel `id` since enabling;
  * synchronises.  Returns RBE_ERR_INVALID for an unknown id. */
@@ -343,6 +345,18 @@ rbe_status rbe_profile_read(rbe_ctx *ctx, int32_t id, double *total_ms, int64_t 
 /* Name of kernel `id` (0 .. rbe_profile_count()-1), NULL if out of range. */
 const char *rbe_profile_name(int32_t id);
 int32_t rbe_profile_count(void);
+
+/* Throughput micro-benchmarks of the current device, for the rooflines of
+ * the kernels (the paper's cost model counts operations per particle-mode
+ * pair, Sec. 3.1): compiled with the library's own flags (no packed FP32
+ * instructions).  kind 0: hardware sine/cosine of revolutions (v_sin_f32 and
+ * v_cos_f32 alternating), lane operations per second; 1: FP32 fused
+ * multiply-add, lane operations per second; 2: FP64 fused multiply-add, lane
+ * operations per second; 3: device-to-device copy, bytes read plus written
+ * per second.  *rate receives the best of `reps` timed launches (reps >= 1).
+ * Allocates and frees a scratch buffer (kind 3: 2 x 256 MiB); not a hot call.
+ * Synchronises the device.  RBE_ERR_INVALID for an unknown kind. */
+rbe_status rbe_calibrate(int32_t kind, int32_t reps, double *rate);
 
 #ifdef __cplusplus
 }

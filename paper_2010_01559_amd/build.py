@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librbe.so")
-SOURCES = ["rbe_kspace.hip", "rbe_real.hip", "rbe_analysis.hip", "rbe_api.cpp"]
+SOURCES = ["rbe_kspace.hip", "rbe_real.hip", "rbe_analysis.hip", "rbe_calibrate.hip", "rbe_api.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -84,11 +84,11 @@ hipError_t launch_pair_hist(const LaunchCfg &c, const Workspace &w, const void *
 {
     const size_t sm = sizeof(unsigned int) * 3 * (size_t)nbins;
     if (c.prec == RBE_FP64)
-        k_pair_hist<double><<<c.n_part_tiles, kHistTile, sm, c.stream>>>(
+        launch_k(k_pair_hist<double>, c.n_part_tiles, kHistTile, sm, c.stream, 
             w.sys, w.part_tiles, (const double *)pos, (const double *)q, c.ntot, r_max, nbins,
             reinterpret_cast<unsigned long long *>(counts));
     else
-        k_pair_hist<float><<<c.n_part_tiles, kHistTile, sm, c.stream>>>(
+        launch_k(k_pair_hist<float>, c.n_part_tiles, kHistTile, sm, c.stream, 
             w.sys, w.part_tiles, (const float *)pos, (const float *)q, c.ntot, r_max, nbins,
             reinterpret_cast<unsigned long long *>(counts));
     return hipGetLastError();

@@ -19,6 +19,14 @@
 
 using namespace rbe;
 
+namespace rbe {
+LaunchEvents &launch_events()
+{
+    thread_local LaunchEvents e;
+    return e;
+}
+}  // namespace rbe
+
 namespace {
 
 // Message of the last failed call that has no context (creation, or the
@@ -295,10 +303,18 @@ rbe_status run(rbe_ctx *c, int id, F &&f)
             HIPCHK(c, hipEventCreate(&a));
             HIPCHK(c, hipEventCreate(&b));
         }
-        HIPCHK(c, hipEventRecord(a, c->stream));
+        // the launches of f record a and b themselves (launch_k)
+        LaunchEvents &le = launch_events();
+        le = LaunchEvents{a, b, false};
         hipError_t e = f();
+        const bool launched = le.started;
+        le = LaunchEvents{};
         if (e != hipSuccess) return hip_fail(c, e, kKernelNames[id]);
-        HIPCHK(c, hipEventRecord(b, c->stream));
+        if (!launched) {
+            c->pool.push_back(a);
+            c->pool.push_back(b);
+            return RBE_OK;
+        }
         c->pend.push_back({id, a, b});
         if (c->pend.size() > 4096) {
             HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -2,12 +2,34 @@
 // librbe.  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "rbe.h"
 
 namespace rbe {
+
+// Events of the kernel being timed (set by the host around one logical
+// kernel while per-kernel timing is on, null otherwise).  Every launch goes
+// through launch_k, which attaches them to the dispatch itself: the first
+// launch of the logical kernel records the start, each launch the stop, so
+// the elapsed time is the kernels' execution, as a kernel trace reports it,
+// with no extra packets between launches.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool started = false;
+};
+LaunchEvents &launch_events();
+
+template <typename F, typename... Args>
+inline void launch_k(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t stream, Args... args)
+{
+    LaunchEvents &e = launch_events();
+    hipEvent_t a = (e.start && !e.started) ? e.start : nullptr;
+    if (a) e.started = true;
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, a, e.stop, 0u, args...);
+}
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 

@@ -411,7 +411,7 @@ __global__ void k_set_step(uint64_t *base, uint64_t step)
 // offsets (a kernel, so that no memset or copy node is needed).
 hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step)
 {
-    k_set_step<<<1, 64, 0, c.stream>>>(w.step_base, step);
+    launch_k(k_set_step, 1, 64, 0, c.stream, w.step_base, step);
     return hipGetLastError();
 }
 
@@ -856,12 +856,12 @@ __global__ __launch_bounds__(256) void k_vjp_gather(const SysDev *__restrict__ s
 hipError_t launch_sample(const LaunchCfg &c, const Workspace &w, uint64_t step, int use_mh)
 {
     if (use_mh) {
-        k_sample_mh<<<dim3(c.R), dim3(64), 0, c.stream>>>(w.sys, w.mh_state, w.modes, w.mode_w, c.mcap, step);
+        launch_k(k_sample_mh, dim3(c.R), dim3(64), 0, c.stream, w.sys, w.mh_state, w.modes, w.mode_w, c.mcap, step);
     } else {
         const int table_lds = c.max_table <= 8192 ? 1 : 0;
         const size_t sm = table_lds ? sizeof(double) * c.max_table : 0;
         dim3 g((c.max_p + 255) / 256, c.R);
-        k_sample_exact<<<g, dim3(256), sm, c.stream>>>(w.sys, w.cdf, w.modes, w.mode_w, c.mcap, step, table_lds);
+        launch_k(k_sample_exact, g, dim3(256), sm, c.stream, w.sys, w.cdf, w.modes, w.mode_w, c.mcap, step, table_lds);
     }
     return hipGetLastError();
 }
@@ -922,27 +922,27 @@ static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const S
     switch (c.rho_block) {
     case 256:
         if (var == 2)
-            k_stage_rho<T, 256, 2><<<g, 256, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 256, 2>, g, 256, sm, c.stream, a);
         else if (var == 1)
-            k_stage_rho<T, 256, 1><<<g, 256, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 256, 1>, g, 256, sm, c.stream, a);
         else
-            k_stage_rho<T, 256, 0><<<g, 256, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 256, 0>, g, 256, sm, c.stream, a);
         break;
     case 512:
         if (var == 2)
-            k_stage_rho<T, 512, 2><<<g, 512, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 512, 2>, g, 512, sm, c.stream, a);
         else if (var == 1)
-            k_stage_rho<T, 512, 1><<<g, 512, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 512, 1>, g, 512, sm, c.stream, a);
         else
-            k_stage_rho<T, 512, 0><<<g, 512, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 512, 0>, g, 512, sm, c.stream, a);
         break;
     default:
         if (var == 2)
-            k_stage_rho<T, 1024, 2><<<g, 1024, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 1024, 2>, g, 1024, sm, c.stream, a);
         else if (var == 1)
-            k_stage_rho<T, 1024, 1><<<g, 1024, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 1024, 1>, g, 1024, sm, c.stream, a);
         else
-            k_stage_rho<T, 1024, 0><<<g, 1024, sm, c.stream>>>(a);
+            launch_k(k_stage_rho<T, 1024, 0>, g, 1024, sm, c.stream, a);
         break;
     }
     return hipGetLastError();
@@ -1023,9 +1023,9 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     if (nb == 0) return hipSuccess;
     const bool lean = !do_scan && !a.n_bin_blocks && !a.n_sample_blocks && !a.reb && !clear_flag;
     if (lean)
-        k_mid<KM, true><<<nb, 1024, sm, c.stream>>>(a);
+        launch_k(k_mid<KM, true>, nb, 1024, sm, c.stream, a);
     else
-        k_mid<KM, false><<<nb, 1024, sm, c.stream>>>(a);
+        launch_k(k_mid<KM, false>, nb, 1024, sm, c.stream, a);
     return hipGetLastError();
 }
 
@@ -1066,17 +1066,17 @@ static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const 
     const int ys = mode_split > 1 && w.fpart ? mode_split : 1;
     switch (c.force_split) {
     case 1:
-        k_kforce<T, KM, 1><<<dim3((n + 3) / 4, ys), 256, 0, c.stream>>>(a);
+        launch_k(k_kforce<T, KM, 1>, dim3((n + 3) / 4, ys), 256, 0, c.stream, a);
         break;
     case 2:
-        k_kforce<T, KM, 2><<<dim3((n + 1) / 2, ys), 256, 0, c.stream>>>(a);
+        launch_k(k_kforce<T, KM, 2>, dim3((n + 1) / 2, ys), 256, 0, c.stream, a);
         break;
     default:
-        k_kforce<T, KM, 4><<<dim3(n, ys), 256, 0, c.stream>>>(a);
+        launch_k(k_kforce<T, KM, 4>, dim3(n, ys), 256, 0, c.stream, a);
         break;
     }
     if (ys > 1)
-        k_fsum<T><<<(int)((c.ntot + 255) / 256), 256, 0, c.stream>>>((const T *)w.fpart, ys, (const T *)q, c.ntot,
+        launch_k(k_fsum<T>, (int)((c.ntot + 255) / 256), 256, 0, c.stream, (const T *)w.fpart, ys, (const T *)q, c.ntot,
                                                                       (T *)F, acc, w.flag);
     return hipGetLastError();
 }
@@ -1098,15 +1098,15 @@ static hipError_t vjp_reduce_dispatch(const LaunchCfg &c, const Workspace &w, co
     dim3 gr(c.n_rho_tiles);
     switch (c.rho_block) {
     case 256:
-        k_vjp_reduce<T, KM, 256><<<gr, 256, sm, c.stream>>>(w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
+        launch_k(k_vjp_reduce<T, KM, 256>, gr, 256, sm, c.stream, w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
                                                             w.partial_off);
         break;
     case 512:
-        k_vjp_reduce<T, KM, 512><<<gr, 512, sm, c.stream>>>(w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
+        launch_k(k_vjp_reduce<T, KM, 512>, gr, 512, sm, c.stream, w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
                                                             w.partial_off);
         break;
     default:
-        k_vjp_reduce<T, KM, 1024><<<gr, 1024, sm, c.stream>>>(w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
+        launch_k(k_vjp_reduce<T, KM, 1024>, gr, 1024, sm, c.stream, w.sys, w.rho_tiles, p, qq, g, c.ntot, km, w.partial,
                                                               w.partial_off);
         break;
     }
@@ -1124,10 +1124,10 @@ hipError_t launch_vjp_final(const LaunchCfg &c, const Workspace &w)
 {
     dim3 g(c.max_p, c.R);
     if (c.prec == RBE_FP64)
-        k_vjp_final<KModeD, KVjpD><<<g, 64, 0, c.stream>>>(w.sys, w.partial, w.partial_off, c.R,
+        launch_k(k_vjp_final<KModeD, KVjpD>, g, 64, 0, c.stream, w.sys, w.partial, w.partial_off, c.R,
                                                            (const KModeD *)w.kmode, w.ab, (KVjpD *)w.kvjp);
     else
-        k_vjp_final<KModeF, KVjpF><<<g, 64, 0, c.stream>>>(w.sys, w.partial, w.partial_off, c.R,
+        launch_k(k_vjp_final<KModeF, KVjpF>, g, 64, 0, c.stream, w.sys, w.partial, w.partial_off, c.R,
                                                            (const KModeF *)w.kmode, w.ab, (KVjpF *)w.kvjp);
     return hipGetLastError();
 }
@@ -1141,15 +1141,15 @@ static hipError_t vjp_gather_dispatch(const LaunchCfg &c, const Workspace &w, co
     const int n = c.n_force_tiles;
     switch (c.force_split) {
     case 1:
-        k_vjp_gather<T, KV, 1><<<(n + 3) / 4, 256, 0, c.stream>>>(w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv,
+        launch_k(k_vjp_gather<T, KV, 1>, (n + 3) / 4, 256, 0, c.stream, w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv,
                                                                   (T *)gpos, (T *)gq);
         break;
     case 2:
-        k_vjp_gather<T, KV, 2><<<(n + 1) / 2, 256, 0, c.stream>>>(w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv,
+        launch_k(k_vjp_gather<T, KV, 2>, (n + 1) / 2, 256, 0, c.stream, w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv,
                                                                   (T *)gpos, (T *)gq);
         break;
     default:
-        k_vjp_gather<T, KV, 4><<<n, 256, 0, c.stream>>>(w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv, (T *)gpos,
+        launch_k(k_vjp_gather<T, KV, 4>, n, 256, 0, c.stream, w.sys, w.force_tiles, n, p, qq, g, c.ntot, kv, (T *)gpos,
                                                         (T *)gq);
         break;
     }
@@ -1191,7 +1191,7 @@ __global__ void k_static_setup(SysDev sys, int chunk, int nrho, int nforce, SysD
 hipError_t launch_static_setup(const LaunchCfg &c, const Workspace &w, const SysDev &sys)
 {
     const int most = std::max(std::max(c.n_rho_tiles, c.n_force_tiles), std::max(sys.p, 1));
-    k_static_setup<<<(most + 255) / 256, 256, 0, c.stream>>>(sys, c.rho_chunk, c.n_rho_tiles, c.n_force_tiles,
+    launch_k(k_static_setup, (most + 255) / 256, 256, 0, c.stream, sys, c.rho_chunk, c.n_rho_tiles, c.n_force_tiles,
                                                              w.sys, w.rho_tiles, w.force_tiles, w.partial_off,
                                                              w.mode_w);
     return hipGetLastError();

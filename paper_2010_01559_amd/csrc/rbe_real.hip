@@ -989,18 +989,18 @@ hipError_t launch_fill_zero(hipStream_t s, void *ptr, int64_t nbytes)
 {
     const int64_t n = nbytes / 4;
     if (n <= 0) return hipSuccess;
-    k_fill_zero<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>((uint32_t *)ptr, n);
+    launch_k(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t *)ptr, n);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter(const LaunchCfg &c, const Workspace &w)
 {
     if (c.prec == RBE_FP64)
-        k_scatter<PartD><<<c.n_part_tiles, 256, 0, c.stream>>>(w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
+        launch_k(k_scatter<PartD>, c.n_part_tiles, 256, 0, c.stream, w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
                                                                (const PartD *)w.packed, w.sorted_idx,
                                                                (PartD *)w.sorted);
     else
-        k_scatter<PackF><<<c.n_part_tiles, 256, 0, c.stream>>>(w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
+        launch_k(k_scatter<PackF>, c.n_part_tiles, 256, 0, c.stream, w.sys, w.part_tiles, w.cell_start, w.cellid, w.rank,
                                                                (const PackF *)w.packed, w.sorted_idx,
                                                                (PackF *)w.sorted);
     return hipGetLastError();
@@ -1034,10 +1034,10 @@ hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int 
                        uint64_t kick_step)
 {
     if (c.prec == RBE_FP64)
-        k_real_rows<double, false><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
+        launch_k(k_real_rows<double, false>, c.n_real_tiles, RL_BS, 0, c.stream, 
             real_args<double>(c, w, force, accumulate, vel_kick, nullptr, kick_step));
     else
-        k_real_rows<float, false><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
+        launch_k(k_real_rows<float, false>, c.n_real_tiles, RL_BS, 0, c.stream, 
             real_args<float>(c, w, force, accumulate, vel_kick, nullptr, kick_step));
     return hipGetLastError();
 }
@@ -1046,7 +1046,7 @@ template <typename T, int LPP>
 static void real_step_launch(const LaunchCfg &c, const RealArgs<T> &a, const ListArgs &la)
 {
     const int nb = la.n_rows > la.n_list ? la.n_rows : la.n_list;
-    k_real_step<T, LPP><<<nb, RL_BS, 0, c.stream>>>(a, la);
+    launch_k(k_real_step<T, LPP>, nb, RL_BS, 0, c.stream, a, la);
 }
 
 template <typename T>
@@ -1091,10 +1091,10 @@ hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListSt
 hipError_t launch_energy(const LaunchCfg &c, const Workspace &w, const void *q, const void *vel)
 {
     if (c.prec == RBE_FP64)
-        k_real_rows<double, true><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
+        launch_k(k_real_rows<double, true>, c.n_real_tiles, RL_BS, 0, c.stream, 
             real_args<double>(c, w, nullptr, 0, (void *)vel, q));
     else
-        k_real_rows<float, true><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(
+        launch_k(k_real_rows<float, true>, c.n_real_tiles, RL_BS, 0, c.stream, 
             real_args<float>(c, w, nullptr, 0, (void *)vel, q));
     return hipGetLastError();
 }
@@ -1103,12 +1103,12 @@ hipError_t launch_vjp_real(const LaunchCfg &c, const Workspace &w, const void *g
                            int accumulate)
 {
     if (c.prec == RBE_FP64)
-        k_vjp_real<double><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(real_args<double>(c, w, nullptr, 0, nullptr,
+        launch_k(k_vjp_real<double>, c.n_real_tiles, RL_BS, 0, c.stream, real_args<double>(c, w, nullptr, 0, nullptr,
                                                                                      nullptr),
                                                                    (const double *)gF, (double *)gpos,
                                                                    (double *)gq, accumulate);
     else
-        k_vjp_real<float><<<c.n_real_tiles, RL_BS, 0, c.stream>>>(real_args<float>(c, w, nullptr, 0, nullptr,
+        launch_k(k_vjp_real<float>, c.n_real_tiles, RL_BS, 0, c.stream, real_args<float>(c, w, nullptr, 0, nullptr,
                                                                                    nullptr),
                                                                   (const float *)gF, (float *)gpos, (float *)gq,
                                                                   accumulate);

@@ -46,7 +46,7 @@ EXPORTED = ["rbe_normalizer", "rbe_create", "rbe_batch_create", "rbe_destroy", "
             "rbe_reserve_modes", "rbe_kspace_forces", "rbe_real_forces", "rbe_step", "rbe_batch_step",
             "rbe_energy", "rbe_check", "rbe_set_wait_limit", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_pair_histogram", "rbe_set_dt", "rbe_use_graphs", "rbe_get_tiles",
             "rbe_set_tiles", "rbe_autotune", "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name",
-            "rbe_profile_count", "rbe_kspace_forces_noalloc"]
+            "rbe_profile_count", "rbe_kspace_forces_noalloc", "rbe_calibrate"]
 
 
 class RBEError(RuntimeError):
@@ -111,6 +111,7 @@ def lib():
     L.rbe_energy.argtypes = [vp, vp, vp, vp, C.POINTER(rbe_energy_t)]
     L.rbe_get_rho.argtypes = [vp, vp]
     L.rbe_check.argtypes = [vp]
+    L.rbe_calibrate.argtypes = [i32, i32, C.POINTER(d)]
     L.rbe_kspace_forces_noalloc.argtypes = [C.POINTER(rbe_params), vp, vp, vp, vp, i32, vp]
     L.rbe_set_wait_limit.argtypes = [vp, i32]
     L.rbe_forces_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32]
@@ -461,6 +462,17 @@ def rbe_profile_read(ctx):
         _check(lib().rbe_profile_read(ctx.handle, k, C.byref(ms), C.byref(n)), ctx.handle)
         out[lib().rbe_profile_name(k).decode()] = (ms.value, n.value)
     return out
+
+
+CALIBRATION_KINDS = {0: "sin_cos_lane_ops_per_s", 1: "fp32_fma_lane_ops_per_s", 2: "fp64_fma_lane_ops_per_s",
+                     3: "copy_bytes_per_s"}
+
+
+def rbe_calibrate(kind, reps=5):
+    """Device throughput micro-benchmark (see include/rbe.h); returns the rate."""
+    r = C.c_double()
+    _check(lib().rbe_calibrate(int(kind), int(reps), C.byref(r)))
+    return r.value
 
 
 # -- conveniences ------------------------------------------------------------------
