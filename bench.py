@@ -29,6 +29,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -77,6 +78,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true", help="pick the Fourier tile shapes by timing")
     ap.add_argument("--suite", metavar="PATH", help="run the sweep/batched/gradient/Ewald suite into PATH instead")
+    ap.add_argument("--suite-parts", default="sweep,batched,gradient,ewald,n_t",
+                    help="comma-separated parts of the suite to run")
     ap.add_argument("--calibrate", action="store_true", help="print the device micro-benchmarks and exit")
     ap.add_argument("--graphs", action="store_true", help="replay the steady-state steps from hipGraphs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -378,7 +381,77 @@ def suite_ewald(torch, R, W, log, tol=1e-4):
     return out
 
 
-def run_suite(path):
+def suite_nt(torch, R, W, log, s_acc=3.0, reps=3):
+    """Per-evaluation force time against N (the paper's per-step timing
+    figure, Sec. 4.1), on the GPU.  Classical Ewald runs on the same kernels
+    with alpha re-balanced as the box grows (Sec. 2: r_c = s/sqrt(alpha),
+    k_c = 2 s sqrt(alpha), and sqrt(alpha) ~ N^(1/6)/L balances the real and
+    Fourier costs for O(N^(3/2)) in all): s = 3 (exp(-s^2) ~ 1e-4), the
+    constant of alpha ~ N^(-1/3) at density 0.1 fixed by the fastest total
+    over a scan at N = 1e4.  The random batch evaluation keeps alpha = 0.6633,
+    r_c = 3.5 and P = 100 (a fresh sample each time).  Coulomb only, cell
+    list rebuilt per call (no skin), FP32."""
+    from paper_2010_01559_amd.ewald import ewald_modes
+
+    def ewald_parts(sy, alpha):
+        rc = s_acc / math.sqrt(alpha)
+        mc = s_acc * math.sqrt(alpha) * sy.L / math.pi   # k_c L / (2 pi)
+        m, w = ewald_modes(alpha, sy.L, int(math.floor(mc * mc)))
+        ctx = R.rbe_create(R.params_from_system(sy, R.RBE_FP32, alpha=alpha, r_cut=rc, lj_eps=0.0, skin=0.0))
+        P = R.to_device(sy.pos, ctx)
+        Q = R.to_device(sy.q, ctx)
+        F = torch.zeros_like(P)
+        R.rbe_real_forces(ctx, P, Q, F)
+        real_ms = _timed(torch, ctx.stream, lambda k: R.rbe_real_forces(ctx, P, Q, F), reps)
+        R.rbe_reserve_modes(ctx, m.shape[1])
+        R.rbe_set_k(ctx, m, w)
+        R.rbe_kspace_forces(ctx, P, Q, F)
+        four_ms = _timed(torch, ctx.stream, lambda k: R.rbe_kspace_forces(ctx, P, Q, F), reps)
+        ctx.close()
+        del P, Q, F
+        torch.cuda.empty_cache()
+        return {"alpha": alpha, "r_cut": rc, "modes": int(m.shape[1]), "real_ms": real_ms, "kspace_ms": four_ms,
+                "total_ms": real_ms + four_ms}
+
+    n0 = 10000
+    s0 = W.scaling_system(n0, 100)
+    scan = [ewald_parts(s0, a) for a in (0.05, 0.07, 0.1, 0.14, 0.2)]
+    a0 = min(scan, key=lambda r: r["total_ms"])["alpha"]
+    log(f"n-t: alpha scan at N = {n0}: " + ", ".join(f"{r['alpha']}: {r['total_ms']:.3f} ms" for r in scan))
+    rows = []
+    for n in (1000, 3000, 10000, 30000, 100000, 300000, 1000000):
+        sy = W.metric_system() if n == 100000 else W.scaling_system(n, 100)
+        alpha = max(a0 * (n / n0) ** (-1.0 / 3.0), 4.0 * s_acc * s_acc / (sy.L * sy.L))   # r_c <= L/2
+        ew = ewald_parts(sy, alpha)
+        ctx = R.rbe_create(R.params_from_system(sy, R.RBE_FP32, lj_eps=0.0, skin=0.0))
+        P = R.to_device(sy.pos, ctx)
+        Q = R.to_device(sy.q, ctx)
+        F = torch.zeros_like(P)
+
+        def rbe(k):
+            R.rbe_sample_k(ctx, 100 + k)
+            R.rbe_kspace_forces(ctx, P, Q, F)
+            R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
+
+        rbe(0)
+        rbe_ms = _timed(torch, ctx.stream, rbe, max(reps, 10))
+        ctx.close()
+        del P, Q, F
+        torch.cuda.empty_cache()
+        row = {"n": n, "box": sy.L, "ewald": ew, "rbe_ms": rbe_ms, "ewald_over_rbe": ew["total_ms"] / rbe_ms}
+        log(f"n-t n={n}: ewald {ew['total_ms']:.3f} ms (alpha {alpha:.4f}, {ew['modes']} modes, r_c "
+            f"{ew['r_cut']:.2f}) vs rbe {rbe_ms:.4f} ms")
+        rows.append(row)
+    big = [r for r in rows if r["n"] >= 10000]
+    ln = np.log([r["n"] for r in big])
+    slope_e = float(np.polyfit(ln, np.log([r["ewald"]["total_ms"] for r in big]), 1)[0])
+    slope_r = float(np.polyfit(ln, np.log([r["rbe_ms"] for r in big]), 1)[0])
+    log(f"n-t slopes over N >= 1e4: ewald {slope_e:.3f}, rbe {slope_r:.3f}")
+    return {"alpha_scan": scan, "alpha_at_1e4": a0, "rows": rows,
+            "slope_ewald": slope_e, "slope_rbe": slope_r, "fit_range": "N >= 1e4"}
+
+
+def run_suite(path, parts):
     import torch
 
     import paper_2010_01559_amd.rbe as R
@@ -390,13 +463,50 @@ def run_suite(path):
     torch.cuda.set_device(0)
     cal = calibration(R)
     log(f"calibration: {cal}")
-    res = {"calibration": cal, "sweep": suite_np_sweep(torch, R, W, log, cal)}
-    res["batched"] = suite_batched(torch, R, W, log)
-    res["gradient"] = suite_gradient(torch, R, W, log)
-    res["ewald"] = suite_ewald(torch, R, W, log)
+    res = {"calibration": cal}
+    if "sweep" in parts:
+        res["sweep"] = suite_np_sweep(torch, R, W, log, cal)
+    if "batched" in parts:
+        res["batched"] = suite_batched(torch, R, W, log)
+    if "gradient" in parts:
+        res["gradient"] = suite_gradient(torch, R, W, log)
+    if "ewald" in parts:
+        res["ewald"] = suite_ewald(torch, R, W, log)
+    if "n_t" in parts:
+        res["n_t"] = suite_nt(torch, R, W, log)
     with open(path, "w") as f:
         json.dump(res, f, indent=1)
     log(f"suite written to {path}")
+
+
+def kspace_at_scale(torch, R, W, cal, n=1000000, p=200, reps=30):
+    """Fourier evaluations (sample + structure factor + force) at N = 1e6,
+    P = 200, the largest sweep size, where the launch and tail latencies that
+    dominate N = 1e5 are amortised: pairs/s against the calibrated bound and
+    the ALU roofline of its two passes (durations from dispatch events)."""
+    s = W.scaling_system(n, p)
+    ctx = R.rbe_create(R.params_from_system(s, R.RBE_FP32))
+    P = R.to_device(s.pos, ctx)
+    Q = R.to_device(s.q, ctx)
+    F = torch.zeros_like(P)
+
+    def four(k):
+        R.rbe_sample_k(ctx, 5000 + k)
+        R.rbe_kspace_forces(ctx, P, Q, F)
+
+    four(0)
+    ms = _timed(torch, ctx.stream, four, reps)
+    kus = _kernel_us(R, ctx, four, reps)
+    pairs = n * p
+    out = {"n": n, "p": p, "kspace_ms": ms, "kspace_pairs_per_s": pairs * 1e3 / ms,
+           "kspace_frac_of_calibrated_bound": pairs * 1e3 / ms / kspace_bound_pairs_per_s(cal),
+           "kernels_us": {k: round(v, 2) for k, v in kus.items()},
+           "stage": alu_roofline({"rho_pair": pairs}, kus["stage"], cal),
+           "kforce": alu_roofline({"force_pair": pairs}, kus["kforce"], cal)}
+    ctx.close()
+    del P, Q, F
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -406,7 +516,7 @@ def main():
               f"single MI355X and has no multi-GPU sharding", file=sys.stderr)
         sys.exit(2)
     if args.suite:
-        run_suite(args.suite)
+        run_suite(args.suite, set(args.suite_parts.split(",")))
         return
     import torch
 
@@ -506,6 +616,7 @@ def main():
                "kforce": alu_roofline({"force_pair": pairs}, kkern["kforce"]["avg_us"], cal, traffic_for("kforce"))}
     kbound = kspace_bound_pairs_per_s(cal)
 
+    at_scale = kspace_at_scale(torch, R, W, cal)
     cpu = None if args.no_cpu else cpu_baseline(s, args.cpu_seconds)
 
     out = {
@@ -540,6 +651,7 @@ def main():
         "roofline": roofline,
         "rooflines": rooflines,
         "fourier_only_rooflines": fourier,
+        "kspace_at_scale": at_scale,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
