@@ -66,7 +66,13 @@ PEAK_HBM_GBS = 8000.0
 # run), each multiplied by the ratio of the true size of a 256 MiB device
 # copy to what the same counter reads for it.  Valid only for the kernel
 # source it was taken on (sha256 prefix); otherwise reported as null.
-TRAFFIC = {}
+# k_real_step: the list-pass launches of the profiled run (the rebuild step's
+# cell pass, which reads several times more, is left out, as the timed window
+# of the N = 1e5 run holds no rebuild).
+TRAFFIC = {
+    "real": {"src": "f70e83a5391a3b37", "fetch_kib": 7840.5, "write_kib": 6408.7, "fetch_scale": 2.000,
+             "write_scale": 1.000},
+}
 
 
 def parse():
@@ -81,6 +87,8 @@ def parse():
     ap.add_argument("--suite-parts", default="sweep,batched,gradient,ewald,n_t",
                     help="comma-separated parts of the suite to run")
     ap.add_argument("--calibrate", action="store_true", help="print the device micro-benchmarks and exit")
+    ap.add_argument("--tune", metavar="PATH",
+                    help="autotune the benchmark configurations and append the tile cache entries to PATH")
     ap.add_argument("--graphs", action="store_true", help="replay the steady-state steps from hipGraphs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
@@ -305,7 +313,7 @@ def suite_batched(torch, R, W, log, steps=100):
             R.rbe_step(c, t[0], t[2], t[1], t[3], 10, steps)
 
     l_ms = _timed(torch, ctxs[0].stream, loop, 1) / steps
-    row = {"replicas": len(systems), "particles": ntot, "pairs_per_step": pairs,
+    row = {"replicas": len(systems), "particles": ntot, "pairs_per_step": pairs, "tiles": R.rbe_get_tiles(bctx),
            "batched": {"ms_per_step": b_ms, "steps_per_s": 1e3 / b_ms, "pairs_per_s": pairs * 1e3 / b_ms},
            "loop": {"ms_per_step": l_ms, "steps_per_s": 1e3 / l_ms, "pairs_per_s": pairs * 1e3 / l_ms},
            "speedup": l_ms / b_ms}
@@ -346,7 +354,7 @@ def suite_ewald(torch, R, W, log, tol=1e-4):
     """Classical Ewald (every mode with exp(-k^2/4 alpha) >= tol, same alpha
     and r_c as the random batch) on the same kernels, against one random
     batch evaluation (P = 100), at growing N and density 0.1."""
-    from paper_2010_01559_amd.ewald import ewald_modes, mode_radius2
+    from paper_2010_01559_amd.ewald import mode_radius2, set_ewald
     out = []
     for n in (1000, 3000, 10000, 30000, 100000):
         s = W.metric_system() if n == 100000 else W.scaling_system(n, 100)
@@ -358,23 +366,24 @@ def suite_ewald(torch, R, W, log, tol=1e-4):
         rbe_ms = _timed(torch, ctx.stream, lambda k: (R.rbe_sample_k(ctx, k), R.rbe_kspace_forces(ctx, P, Q, F)),
                         50)
         real_ms = _timed(torch, ctx.stream, lambda k: R.rbe_real_forces(ctx, P, Q, F), 50)
-        m, w = ewald_modes(s.alpha, s.L, mode_radius2(s.alpha, s.L, tol))
-        R.rbe_reserve_modes(ctx, m.shape[1])
-        R.rbe_set_k(ctx, m, w)
+        m2 = mode_radius2(s.alpha, s.L, tol)
+        nm = set_ewald(ctx, m2)
         R.rbe_kspace_forces(ctx, P, Q, F)
         ew_ms = _timed(torch, ctx.stream, lambda k: R.rbe_kspace_forces(ctx, P, Q, F), 5)
-        row = {"n": n, "box": s.L, "ewald_modes": int(m.shape[1]), "ewald_kspace_ms": ew_ms,
-               "ewald_pairs_per_s": n * m.shape[1] * 1e3 / ew_ms, "rbe_kspace_ms": rbe_ms,
+        row = {"n": n, "box": s.L, "ewald_modes": nm, "ewald_kspace_ms": ew_ms,
+               "ewald_pairs_per_s": n * nm * 1e3 / ew_ms, "rbe_kspace_ms": rbe_ms,
                "real_space_ms": real_ms, "ewald_over_rbe": ew_ms / rbe_ms}
         if n in (1000, 10000):
-            # the FP64 oracle's classical Ewald Fourier force on the host, same modes
+            # the FP64 oracle's classical Ewald Fourier force on the host, on
+            # the oracle's own enumeration of the same mode ball
             import oracle as O
             pos, q = s.pos.astype(np.float32).astype(np.float64), s.q
+            m, w = O.ewald_modes(s.alpha, s.L, m2)
             t0 = time.perf_counter()
             O.kspace_force(pos, q, s.L, m, w)
             row["oracle_ewald_kspace_ms"] = 1e3 * (time.perf_counter() - t0)
             row["oracle_threads"] = O.set_threads(0)
-        log(f"ewald n={n}: {m.shape[1]} modes {ew_ms:.3f} ms vs rbe {rbe_ms:.4f} ms")
+        log(f"ewald n={n}: {nm} modes {ew_ms:.3f} ms vs rbe {rbe_ms:.4f} ms")
         out.append(row)
         del ctx, P, Q, F
         torch.cuda.empty_cache()
@@ -391,26 +400,24 @@ def suite_nt(torch, R, W, log, s_acc=3.0, reps=3):
     over a scan at N = 1e4.  The random batch evaluation keeps alpha = 0.6633,
     r_c = 3.5 and P = 100 (a fresh sample each time).  Coulomb only, cell
     list rebuilt per call (no skin), FP32."""
-    from paper_2010_01559_amd.ewald import ewald_modes
+    from paper_2010_01559_amd.ewald import set_ewald
 
     def ewald_parts(sy, alpha):
         rc = s_acc / math.sqrt(alpha)
         mc = s_acc * math.sqrt(alpha) * sy.L / math.pi   # k_c L / (2 pi)
-        m, w = ewald_modes(alpha, sy.L, int(math.floor(mc * mc)))
         ctx = R.rbe_create(R.params_from_system(sy, R.RBE_FP32, alpha=alpha, r_cut=rc, lj_eps=0.0, skin=0.0))
         P = R.to_device(sy.pos, ctx)
         Q = R.to_device(sy.q, ctx)
         F = torch.zeros_like(P)
         R.rbe_real_forces(ctx, P, Q, F)
         real_ms = _timed(torch, ctx.stream, lambda k: R.rbe_real_forces(ctx, P, Q, F), reps)
-        R.rbe_reserve_modes(ctx, m.shape[1])
-        R.rbe_set_k(ctx, m, w)
+        nm = set_ewald(ctx, int(math.floor(mc * mc)))
         R.rbe_kspace_forces(ctx, P, Q, F)
         four_ms = _timed(torch, ctx.stream, lambda k: R.rbe_kspace_forces(ctx, P, Q, F), reps)
         ctx.close()
         del P, Q, F
         torch.cuda.empty_cache()
-        return {"alpha": alpha, "r_cut": rc, "modes": int(m.shape[1]), "real_ms": real_ms, "kspace_ms": four_ms,
+        return {"alpha": alpha, "r_cut": rc, "modes": nm, "real_ms": real_ms, "kspace_ms": four_ms,
                 "total_ms": real_ms + four_ms}
 
     n0 = 10000
@@ -479,6 +486,50 @@ def run_suite(path, parts):
     log(f"suite written to {path}")
 
 
+def run_tune(path):
+    """rbe_autotune on the configurations the benchmark and its suite time:
+    the N x P sweep, the 64 batched replicas, the differentiable form and the
+    3000-ion electrolyte.  Each result is appended to the tile cache at
+    PATH (the library writes it); the Fourier evaluation time with the
+    default and the tuned shapes is printed."""
+    os.environ["RBE_TUNE_CACHE"] = path
+    import torch
+
+    import paper_2010_01559_amd.rbe as R
+    from paper_2010_01559_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    cases = [("electrolyte", [W.langevin_electrolyte()]), ("gradient", [W.gaussian_charge_system()]),
+             ("replicas", W.replica_systems())]
+    for n in (10000, 100000, 1000000):
+        for p in (50, 100, 200, 500):
+            cases.append((f"sweep n={n} p={p}", [W.metric_system() if n == 100000 else W.scaling_system(n, 100)]))
+            cases[-1][1][0].p = p
+    for name, systems in cases:
+        ctx = R.rbe_batch_create([R.params_from_system(x, R.RBE_FP32) for x in systems])
+        cat = lambda a: np.ascontiguousarray(np.concatenate(a, axis=-1))
+        P = R.to_device(cat([x.pos for x in systems]), ctx)
+        Q = R.to_device(cat([x.q for x in systems]), ctx)
+        F = torch.zeros_like(P)
+        R.rbe_sample_k(ctx, 0)
+
+        def four(k):
+            R.rbe_sample_k(ctx, 10 + k)
+            R.rbe_kspace_forces(ctx, P, Q, F)
+
+        four(0)
+        before, t0 = _timed(torch, ctx.stream, four, 20), R.rbe_get_tiles(ctx)
+        R.rbe_sample_k(ctx, 0)
+        best = R.rbe_autotune(ctx, P, Q, reps=20)
+        four(0)
+        after = _timed(torch, ctx.stream, four, 20)
+        print(json.dumps({"case": name, "default": t0, "default_ms": before, "tuned": best, "tuned_ms": after}),
+              flush=True)
+        ctx.close()
+        del P, Q, F
+        torch.cuda.empty_cache()
+
+
 def kspace_at_scale(torch, R, W, cal, n=1000000, p=200, reps=30):
     """Fourier evaluations (sample + structure factor + force) at N = 1e6,
     P = 200, the largest sweep size, where the launch and tail latencies that
@@ -517,6 +568,9 @@ def main():
         sys.exit(2)
     if args.suite:
         run_suite(args.suite, set(args.suite_parts.split(",")))
+        return
+    if args.tune:
+        run_tune(args.tune)
         return
     import torch
 

@@ -188,6 +188,23 @@ rbe_status rbe_sample_k(rbe_ctx *ctx, uint64_t step, int32_t *modes_out);
  * (max(p, 1) unless rbe_reserve_modes raised it). */
 rbe_status rbe_set_k(rbe_ctx *ctx, const int32_t *modes, int32_t nm, const double *weights);
 
+/* Classical Ewald comparator (eq. 2.9, second term, with the Fourier sum
+ * truncated to 0 < |m|^2 <= mmax2, m = k L / (2 pi) integer).
+ * rbe_ewald_radius2: the largest mmax2 whose Gaussian factor
+ * exp(-pi^2 |m|^2 / (alpha L^2)) = exp(-k^2/4 alpha) is still >= tol, tol in
+ * (0, 1).  rbe_ewald_modes: every such mode, m_x outermost and m_z innermost
+ * from -floor(sqrt(mmax2)) up, with its weight exp(-k^2/4 alpha); modes is
+ * host [3][cap] int32 (row stride cap), weights host [cap]; with both NULL
+ * only *nm is written (the count), else cap must hold *nm.  Both host only
+ * (no device); errors in rbe_last_error(NULL).  rbe_set_k_ewald: that list
+ * made active on a single-system context with the context's alpha and L
+ * (rbe_set_k with these weights; raises the mode capacity when needed, which
+ * allocates: not a hot call); *nm_out (may be NULL) gets the count. */
+rbe_status rbe_ewald_radius2(double alpha, double box, double tol, int32_t *mmax2);
+rbe_status rbe_ewald_modes(double alpha, double box, int32_t mmax2, int32_t *modes, double *weights, int32_t cap,
+                           int32_t *nm);
+rbe_status rbe_set_k_ewald(rbe_ctx *ctx, int32_t mmax2, int32_t *nm_out);
+
 /* Raise the mode capacity of a single-system context to cap (allocates;
  * not a hot call). */
 rbe_status rbe_reserve_modes(rbe_ctx *ctx, int32_t cap);
@@ -207,8 +224,11 @@ rbe_status rbe_kspace_forces(rbe_ctx *ctx, const void *pos, const void *q, void 
  * random batch weight S/p, enqueued on `stream` (a hipStream_t, NULL = the
  * default stream) without a context.  pos [3][n], q [n] and force [3][n]
  * are the caller's device arrays in the precision of params; force is
- * overwritten or accumulated.  Same kernels and tile shapes as a context,
- * so the result equals rbe_set_k + rbe_kspace_forces bit for bit.
+ * overwritten or accumulated.  Same kernels as a context, with the built-in
+ * tile shapes (never the tile cache): rho_chunk = ceil(n/256) rounded up to a
+ * multiple of 8 and clamped to [64, 512], rho_block 1024, force_split 4 (2
+ * for n >= 500000); the result equals rbe_set_k + rbe_kspace_forces of a
+ * context on those shapes bit for bit.
  * The workspace is a fixed device array inside the library, one per GPU,
  * held until the process ends (about 17 MB); calls never allocate.  Limits:
  * n <= 2^20, p <= 512 (RBE_ERR_INVALID beyond, with the limit in the
@@ -331,8 +351,23 @@ rbe_status rbe_set_tiles(rbe_ctx *ctx, const rbe_tiles *tiles);
 
 /* Time the Fourier pass under every candidate tile shape on the given inputs
  * (hipEvents on the context stream, reps repetitions each), keep the fastest
- * and return it in *best (may be NULL).  Not a hot call. */
+ * and return it in *best (may be NULL).  The result also goes to the
+ * process's tile cache (see rbe_tune_lookup), so later contexts of the same
+ * key start from it, and is appended to the cache file when $RBE_TUNE_CACHE
+ * names one (the file shipped beside the library is never written).  Not a
+ * hot call. */
 rbe_status rbe_autotune(rbe_ctx *ctx, const void *pos, const void *q, int32_t reps, rbe_tiles *best);
+
+/* Tile cache: shapes found by rbe_autotune, keyed by device architecture
+ * (e.g. "gfx950"), precision, floor(log2 ntot), floor(log2 max_p) and
+ * whether R > 1.  rbe_create / rbe_batch_create take their tile shapes from
+ * it when it holds their key (else the built-in defaults).  It is read once
+ * per process from the file named by $RBE_TUNE_CACHE, or else from
+ * rbe_tiles.txt in the directory of the library.  Host only; writes the
+ * cached shapes to *out and returns RBE_OK, or RBE_ERR_STATE when the key is
+ * absent, RBE_ERR_INVALID for bad arguments. */
+rbe_status rbe_tune_lookup(const char *arch, int32_t precision, int64_t ntot, int32_t max_p, int32_t R,
+                           rbe_tiles *out);
 
 /* Per-kernel timing while enabled: each logical kernel's launches carry
  * hipEvents on their own dispatches (hipExtLaunchKernel), so the elapsed

@@ -2,6 +2,7 @@
 // management, and the C-ABI entry points declared in include/rbe.h.
 //
 // Paper: Jin, Li, Xu & Zhao, arXiv:2010.01559.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -9,7 +10,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -144,6 +147,133 @@ int default_rho_chunk(int64_t ntot)
 
 int default_force_split(int64_t ntot) { return ntot >= 500000 ? 2 : 4; }
 
+// ---------------------------------------------------------------------------
+// Tile cache: shapes picked by rbe_autotune, keyed by device architecture,
+// precision, the power-of-two buckets of the total particle count and of the
+// largest batch size, and whether the context holds several systems.  It is
+// read at the first context creation from $RBE_TUNE_CACHE, or else from
+// rbe_tiles.txt beside the library, and consulted by every creation;
+// rbe_autotune adds its result and appends it to the file when it can.
+// Lines: "arch precision n_bucket p_bucket batched rho_chunk rho_block
+// force_split real_split"; '#' starts a comment.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    std::string arch;
+    int prec, nb, pb, batched;
+    bool operator<(const TuneKey &o) const
+    {
+        if (arch != o.arch) return arch < o.arch;
+        if (prec != o.prec) return prec < o.prec;
+        if (nb != o.nb) return nb < o.nb;
+        if (pb != o.pb) return pb < o.pb;
+        return batched < o.batched;
+    }
+};
+
+struct TuneCache {
+    std::mutex mu;
+    bool loaded = false;
+    bool persist = false;   // rbe_autotune appends to the file (only one named by RBE_TUNE_CACHE)
+    std::string path;
+    std::map<TuneKey, rbe_tiles> m;
+};
+
+TuneCache &tune_cache()
+{
+    static TuneCache t;
+    return t;
+}
+
+int log2_bucket(int64_t v)
+{
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+// The architecture name without its feature suffixes ("gfx950:sramecc+" -> "gfx950").
+TuneKey tune_key(const char *arch, int prec, int64_t ntot, int max_p, int R)
+{
+    std::string a = arch;
+    const size_t colon = a.find(':');
+    if (colon != std::string::npos) a.resize(colon);
+    return TuneKey{a, prec, log2_bucket(ntot), log2_bucket(max_p), R > 1 ? 1 : 0};
+}
+
+void tune_load_locked(TuneCache &t)
+{
+    if (t.loaded) return;
+    t.loaded = true;
+    if (const char *env = std::getenv("RBE_TUNE_CACHE")) {
+        t.path = env;
+        t.persist = true;
+    } else {
+        Dl_info info;
+        if (dladdr((void *)&tune_cache, &info) && info.dli_fname) {
+            std::string lib = info.dli_fname;
+            const size_t slash = lib.rfind('/');
+            t.path = (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/rbe_tiles.txt";
+        }
+    }
+    FILE *f = t.path.empty() ? nullptr : std::fopen(t.path.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        if (char *hash = std::strchr(line, '#')) *hash = 0;
+        char arch[32];
+        TuneKey k;
+        rbe_tiles v;
+        if (std::sscanf(line, "%31s %d %d %d %d %d %d %d %d", arch, &k.prec, &k.nb, &k.pb, &k.batched, &v.rho_chunk,
+                        &v.rho_block, &v.force_split, &v.real_split) == 9) {
+            k.arch = arch;
+            t.m[k] = v;
+        }
+    }
+    std::fclose(f);
+}
+
+bool tune_lookup(const TuneKey &k, rbe_tiles *out)
+{
+    TuneCache &t = tune_cache();
+    std::lock_guard<std::mutex> lock(t.mu);
+    tune_load_locked(t);
+    auto it = t.m.find(k);
+    if (it == t.m.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_store(const TuneKey &k, const rbe_tiles &v)
+{
+    TuneCache &t = tune_cache();
+    std::lock_guard<std::mutex> lock(t.mu);
+    tune_load_locked(t);
+    t.m[k] = v;
+    if (!t.persist || t.path.empty()) return;
+    if (FILE *f = std::fopen(t.path.c_str(), "a")) {
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.prec, k.nb, k.pb, k.batched, v.rho_chunk,
+                     v.rho_block, v.force_split, v.real_split);
+        std::fclose(f);
+    }
+}
+
+// Whether a tile shape fits the kernels' dynamic LDS: the adjoint
+// reduction stages 48 bytes per particle and 16 per thread, the staging
+// kernel 32 per particle (plus 256 padding records) and 28 per thread (its
+// table falls back to global memory when it does not fit).
+bool tiles_fit(const rbe_tiles &n)
+{
+    return n.rho_chunk >= 64 && n.rho_chunk <= 2048 && n.rho_chunk % 8 == 0 &&
+           (n.rho_block == 256 || n.rho_block == 512 || n.rho_block == 1024) &&
+           (n.force_split == 1 || n.force_split == 2 || n.force_split == 4) &&
+           (n.real_split == 1 || n.real_split == 2 || n.real_split == 4 || n.real_split == 8) &&
+           48 * (size_t)n.rho_chunk + 16 * (size_t)n.rho_block <= 64 * 1024 &&
+           32 * ((size_t)n.rho_chunk + 256) + 28 * (size_t)n.rho_block <= 64 * 1024;
+}
+
 // Largest centre distance at which the shifted LJ of eq. (4.1) still acts:
 // R_c without diameters (r_off = 0), else r_off + R_c of the pair of the two
 // largest diameters, r_off = (d_i + d_j)/2 - sigma.
@@ -217,6 +347,8 @@ struct rbe_ctx {
     int R = 0;
     int prec = RBE_FP32;
     int device = 0;
+    std::string arch;               // gcnArchName of the device
+    bool tiles_from_cache = false;  // creation took its tile shapes from the tile cache
     hipStream_t stream = nullptr;
     std::vector<rbe_params> prm;
     std::vector<SysDev> sysh;
@@ -752,6 +884,18 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
         }
         ok = up(w.diam, d.data(), sizeof(double) * ntot);
     }
+    {
+        // shapes from the tile cache, when it holds this configuration
+        rbe_tiles t;
+        c->arch = prop.gcnArchName;
+        if (tune_lookup(tune_key(prop.gcnArchName, c->prec, ntot, c->max_p, R), &t) && tiles_fit(t)) {
+            g.rho_chunk = t.rho_chunk;
+            g.rho_block = t.rho_block;
+            g.force_split = t.force_split;
+            g.real_split = t.real_split;
+            c->tiles_from_cache = true;
+        }
+    }
     if (ok) ok = upload_rho_tiles(c) == RBE_OK;
     if (ok) ok = upload_list_tiles(c) == RBE_OK;
     if (ok && g.list_on) {
@@ -905,6 +1049,88 @@ rbe_status rbe_set_k(rbe_ctx *c, const int32_t *modes, int32_t nm, const double 
     }
     c->modes_valid = true;
     return RBE_OK;
+}
+
+// ---- classical Ewald mode lists (eq. 2.9, second term, truncated) ----
+
+rbe_status rbe_ewald_radius2(double alpha, double box, double tol, int32_t *mmax2)
+{
+    if (!finite_pos(alpha) || !finite_pos(box) || !(tol > 0.0 && tol < 1.0) || !mmax2) {
+        null_errf("alpha and box must be positive, tol in (0, 1), mmax2 non-NULL");
+        return RBE_ERR_INVALID;
+    }
+    // exp(-pi^2 |m|^2 / (alpha L^2)) >= tol  <=>  |m|^2 <= ln(1/tol) alpha L^2 / pi^2
+    const double v = std::log(1.0 / tol) * alpha * box * box / (M_PI * M_PI);
+    if (!(v < 2.0e9)) {
+        null_errf("the mode radius for alpha = %g, L = %g, tol = %g is beyond 32 bits", alpha, box, tol);
+        return RBE_ERR_INVALID;
+    }
+    *mmax2 = (int32_t)std::floor(v);
+    return RBE_OK;
+}
+
+rbe_status rbe_ewald_modes(double alpha, double box, int32_t mmax2, int32_t *modes, double *weights, int32_t cap,
+                           int32_t *nm)
+{
+    if (!finite_pos(alpha) || !finite_pos(box) || mmax2 < 1 || !nm) {
+        null_errf("alpha and box must be positive, mmax2 >= 1, nm non-NULL");
+        return RBE_ERR_INVALID;
+    }
+    int R = 0;
+    while ((int64_t)(R + 1) * (R + 1) <= mmax2) ++R;
+    int64_t count = 0;
+    for (int64_t a = -R; a <= R; ++a)
+        for (int64_t b = -R; b <= R; ++b)
+            for (int64_t d = -R; d <= R; ++d) {
+                const int64_t m2 = a * a + b * b + d * d;
+                count += m2 > 0 && m2 <= mmax2;
+            }
+    if (count > INT32_MAX) {
+        null_errf("%lld modes do not fit 32-bit counts", (long long)count);
+        return RBE_ERR_INVALID;
+    }
+    *nm = (int32_t)count;
+    if (!modes && !weights) return RBE_OK;
+    if (!modes || !weights || cap < count) {
+        null_errf("modes and weights need room for %lld modes (cap = %d)", (long long)count, cap);
+        return RBE_ERR_INVALID;
+    }
+    // Ewald weight of mode m: exp(-k^2 / (4 alpha)) with k = 2 pi |m| / L
+    const double g = M_PI * M_PI / (alpha * box * box);
+    int64_t l = 0;
+    for (int64_t a = -R; a <= R; ++a)
+        for (int64_t b = -R; b <= R; ++b)
+            for (int64_t d = -R; d <= R; ++d) {
+                const int64_t m2 = a * a + b * b + d * d;
+                if (m2 == 0 || m2 > mmax2) continue;
+                modes[l] = (int32_t)a;
+                modes[(int64_t)cap + l] = (int32_t)b;
+                modes[2 * (int64_t)cap + l] = (int32_t)d;
+                weights[l] = std::exp(-g * (double)m2);
+                ++l;
+            }
+    return RBE_OK;
+}
+
+rbe_status rbe_set_k_ewald(rbe_ctx *c, int32_t mmax2, int32_t *nm_out)
+{
+    if (!c) return RBE_ERR_INVALID;
+    if (c->R != 1) return set_err(c, RBE_ERR_STATE, "rbe_set_k_ewald needs a single-system context");
+    const double alpha = c->sysh[0].alpha, L = c->sysh[0].L;
+    int32_t nm = 0;
+    if (rbe_ewald_modes(alpha, L, mmax2, nullptr, nullptr, 0, &nm) != RBE_OK || nm < 1)
+        return set_err(c, RBE_ERR_INVALID, fmt("no Ewald modes with 0 < |m|^2 <= %d", mmax2));
+    std::vector<int32_t> m(3 * (size_t)nm);
+    std::vector<double> w(nm);
+    if (rbe_ewald_modes(alpha, L, mmax2, m.data(), w.data(), nm, &nm) != RBE_OK)
+        return set_err(c, RBE_ERR_INVALID, g_create_error.c_str());
+    if (nm > c->mcap) {
+        rbe_status s = rbe_reserve_modes(c, nm);
+        if (s != RBE_OK) return s;
+    }
+    rbe_status s = rbe_set_k(c, m.data(), nm, w.data());
+    if (s == RBE_OK && nm_out) *nm_out = nm;
+    return s;
 }
 
 // Structure factors of pos with the active modes (one staging launch and
@@ -1406,14 +1632,7 @@ rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
         return set_err(c, RBE_ERR_INVALID, "force_split must be 1, 2 or 4");
     if (n.real_split != 1 && n.real_split != 2 && n.real_split != 4 && n.real_split != 8)
         return set_err(c, RBE_ERR_INVALID, "real_split must be 1, 2, 4 or 8");
-    // dynamic LDS of the reduction kernels must fit
-    // the adjoint reduction stages 48 bytes per particle and 16 per thread;
-    // the staging kernel 32 per particle (plus 256 padding records) and 28
-    // per thread (plus the table,
-    // which falls back to global memory when it does not fit)
-    if (48 * (size_t)n.rho_chunk + 16 * (size_t)n.rho_block > 64 * 1024 ||
-        32 * ((size_t)n.rho_chunk + 256) + 28 * (size_t)n.rho_block > 64 * 1024)
-        return set_err(c, RBE_ERR_INVALID, "rho_chunk and rho_block need more than 64 KB of LDS");
+    if (!tiles_fit(n)) return set_err(c, RBE_ERR_INVALID, "rho_chunk and rho_block need more than 64 KB of LDS");
     if (partial_need(c, n.rho_chunk) > c->partial_cap)
         return set_err(c, RBE_ERR_INVALID, "rho_chunk too small for the structure-factor partials of the reserved "
                                            "mode capacity");
@@ -1425,6 +1644,13 @@ rbe_status rbe_set_tiles(rbe_ctx *c, const rbe_tiles *t)
     rbe_status st = upload_rho_tiles(c);
     if (st != RBE_OK) return st;
     return upload_list_tiles(c);
+}
+
+rbe_status rbe_tune_lookup(const char *arch, int32_t precision, int64_t ntot, int32_t max_p, int32_t R,
+                           rbe_tiles *out)
+{
+    if (!arch || !out || ntot < 1 || max_p < 1 || R < 1) return RBE_ERR_INVALID;
+    return tune_lookup(tune_key(arch, precision, ntot, max_p, R), out) ? RBE_OK : RBE_ERR_STATE;
 }
 
 rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps, rbe_tiles *best)
@@ -1516,6 +1742,7 @@ rbe_status rbe_autotune(rbe_ctx *c, const void *pos, const void *q, int32_t reps
     c->prof = prof;
     if (s != RBE_OK) return s;
     if ((s = rbe_set_tiles(c, &win)) != RBE_OK) return s;
+    tune_store(tune_key(c->arch.c_str(), c->prec, c->ntot, c->max_p, c->R), win);
     if (best) *best = win;
     return RBE_OK;
 }

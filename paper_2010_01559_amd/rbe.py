@@ -46,7 +46,8 @@ EXPORTED = ["rbe_normalizer", "rbe_create", "rbe_batch_create", "rbe_destroy", "
             "rbe_reserve_modes", "rbe_kspace_forces", "rbe_real_forces", "rbe_step", "rbe_batch_step",
             "rbe_energy", "rbe_check", "rbe_set_wait_limit", "rbe_get_rho", "rbe_forces_vjp", "rbe_list_builds", "rbe_pair_histogram", "rbe_set_dt", "rbe_use_graphs", "rbe_get_tiles",
             "rbe_set_tiles", "rbe_autotune", "rbe_profile_enable", "rbe_profile_read", "rbe_profile_name",
-            "rbe_profile_count", "rbe_kspace_forces_noalloc", "rbe_calibrate"]
+            "rbe_profile_count", "rbe_kspace_forces_noalloc", "rbe_calibrate", "rbe_tune_lookup",
+            "rbe_ewald_radius2", "rbe_ewald_modes", "rbe_set_k_ewald"]
 
 
 class RBEError(RuntimeError):
@@ -104,6 +105,9 @@ def lib():
     L.rbe_sample_k.argtypes = [vp, u64, vp]
     L.rbe_set_k.argtypes = [vp, vp, i32, vp]
     L.rbe_reserve_modes.argtypes = [vp, i32]
+    L.rbe_ewald_radius2.argtypes = [C.c_double, C.c_double, C.c_double, vp]
+    L.rbe_ewald_modes.argtypes = [C.c_double, C.c_double, i32, vp, vp, i32, vp]
+    L.rbe_set_k_ewald.argtypes = [vp, i32, vp]
     L.rbe_kspace_forces.argtypes = [vp, vp, vp, vp, i32]
     L.rbe_real_forces.argtypes = [vp, vp, vp, vp, i32]
     L.rbe_step.argtypes = [vp, vp, vp, vp, vp, u64, i32]
@@ -112,6 +116,7 @@ def lib():
     L.rbe_get_rho.argtypes = [vp, vp]
     L.rbe_check.argtypes = [vp]
     L.rbe_calibrate.argtypes = [i32, i32, C.POINTER(d)]
+    L.rbe_tune_lookup.argtypes = [C.c_char_p, i32, i64, i32, i32, C.POINTER(rbe_tiles)]
     L.rbe_kspace_forces_noalloc.argtypes = [C.POINTER(rbe_params), vp, vp, vp, vp, i32, vp]
     L.rbe_set_wait_limit.argtypes = [vp, i32]
     L.rbe_forces_vjp.argtypes = [vp, vp, vp, vp, vp, vp, i32]
@@ -317,6 +322,29 @@ def rbe_reserve_modes(ctx, cap):
     _check(lib().rbe_reserve_modes(ctx.handle, cap), ctx.handle)
 
 
+def rbe_ewald_radius2(alpha, box, tol):
+    v = C.c_int32()
+    _check(lib().rbe_ewald_radius2(float(alpha), float(box), float(tol), C.byref(v)))
+    return v.value
+
+
+def rbe_ewald_modes(alpha, box, mmax2):
+    """(modes int32 [3, nm], weights float64 [nm]) of the classical Ewald list."""
+    nm = C.c_int32()
+    _check(lib().rbe_ewald_modes(float(alpha), float(box), int(mmax2), None, None, 0, C.byref(nm)))
+    m = np.zeros((3, nm.value), dtype=np.int32)
+    w = np.zeros(nm.value, dtype=np.float64)
+    _check(lib().rbe_ewald_modes(float(alpha), float(box), int(mmax2), m.ctypes.data_as(C.c_void_p),
+                                 w.ctypes.data_as(C.c_void_p), nm.value, C.byref(nm)))
+    return m, w
+
+
+def rbe_set_k_ewald(ctx, mmax2):
+    nm = C.c_int32()
+    _check(lib().rbe_set_k_ewald(ctx.handle, int(mmax2), C.byref(nm)), ctx.handle)
+    return nm.value
+
+
 def rbe_kspace_forces(ctx, pos, q, force, accumulate=False):
     _check(lib().rbe_kspace_forces(ctx.handle, _vec3(ctx, pos, "pos"), _scal(ctx, q, "q"),
                                    _vec3(ctx, force, "force"), int(accumulate)), ctx.handle)
@@ -447,6 +475,16 @@ def rbe_autotune(ctx, pos, q, reps=10):
     t = rbe_tiles()
     _check(lib().rbe_autotune(ctx.handle, _vec3(ctx, pos, "pos"), _scal(ctx, q, "q"), reps, C.byref(t)),
            ctx.handle)
+    return {k: getattr(t, k) for k, _ in rbe_tiles._fields_}
+
+
+def rbe_tune_lookup(arch, precision, ntot, max_p, R=1):
+    """Tile shapes the cache holds for this configuration, or None."""
+    t = rbe_tiles()
+    st = lib().rbe_tune_lookup(arch.encode(), int(precision), int(ntot), int(max_p), int(R), C.byref(t))
+    if st == RBE_ERR_STATE:
+        return None
+    _check(st)
     return {k: getattr(t, k) for k, _ in rbe_tiles._fields_}
 
 

@@ -27,7 +27,7 @@ import torch
 import paper_2010_01559_amd.rbe as R
 from paper_2010_01559_amd import observables as X
 from paper_2010_01559_amd import workloads as W
-from paper_2010_01559_amd.ewald import ewald_modes, mode_radius2
+from paper_2010_01559_amd.ewald import mode_radius2, set_ewald
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +46,7 @@ def _md(sampler, burn=10000, nsamp=2000, every=50):
     P, Q, V = (R.to_device(a, ctx) for a in (s.pos, s.q, s.vel))
     F = torch.zeros_like(P)
     if sampler == R.RBE_SAMPLER_FIXED:
-        m, w = ewald_modes(s.alpha, s.L, mode_radius2(s.alpha, s.L, 1e-8))
-        R.rbe_reserve_modes(ctx, m.shape[1])
-        R.rbe_set_k(ctx, m, w)
+        set_ewald(ctx, mode_radius2(s.alpha, s.L, 1e-8))
     else:
         R.rbe_sample_k(ctx, 0)
     R.rbe_kspace_forces(ctx, P, Q, F)

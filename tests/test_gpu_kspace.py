@@ -83,6 +83,37 @@ def test_kspace_tiles_and_ragged_tail(prec, tiles):
     assert rel_l2(host(F), 2 * Fo) <= TOL[prec]
 
 
+def _cached_shapes():
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    shapes = set()
+    with open(os.path.join(root, "paper_2010_01559_amd", "rbe_tiles.txt")) as f:
+        for line in f:
+            v = line.split("#")[0].split()
+            if v:
+                shapes.add(tuple(map(int, v[5:9])))
+    return sorted(shapes)
+
+
+@pytest.mark.parametrize("shape", _cached_shapes())
+def test_cached_tile_shapes_keep_parity(shape):
+    """Every shape the shipped tile cache can select: the Fourier force of
+    the 3000-ion electrolyte (several tiles and a ragged tail) against the
+    oracle, and a few list-driven steps that stay finite."""
+    chunk, block, fsplit, rsplit = shape
+    s = W.langevin_electrolyte()
+    ctx = make_ctx(s, R.RBE_FP32)
+    R.rbe_set_tiles(ctx, rho_chunk=chunk, rho_block=block, force_split=fsplit, real_split=rsplit)
+    P, Q, V, F = device_state(ctx, s)
+    pos, q = rounded(s, R.RBE_FP32)
+    modes = _modes_of(ctx, 7)
+    R.rbe_kspace_forces(ctx, P, Q, F)
+    assert rel_l2(host(F), O.rbe_kspace_force(pos, q, s.L, s.alpha, modes)) <= TOL[R.RBE_FP32]
+    R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
+    R.rbe_step(ctx, P, V, Q, F, 1, 5)
+    assert np.isfinite(host(P)).all()
+
+
 def test_kspace_odd_sizes_fp32():
     # tiny, prime and single-particle-tail sizes with P not a multiple of 64
     for n, p in [(2, 1), (65, 7), (257, 33), (1025, 130)]:
@@ -120,6 +151,28 @@ def test_classical_ewald_through_set_k():
     R.rbe_kspace_forces(ctx, P, Q, F)
     Fo = O.rbe_kspace_force(s.pos, s.q, s.L, s.alpha, m[:, :50])
     assert rel_l2(host(F), Fo) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBE_FP64, 1e-12), (R.RBE_FP32, 1e-5)])
+def test_classical_ewald_list_made_by_the_library(prec, tol):
+    """rbe_set_k_ewald: the library's own classical Ewald list (every mode
+    with exp(-k^2/4 alpha) >= 1e-6, raising the mode capacity itself) gives
+    the oracle's classical Ewald Fourier force and energy on the oracle's
+    enumeration of the same mode ball (eq. 2.11)."""
+    from paper_2010_01559_amd.ewald import mode_radius2, set_ewald
+    s = W.small_fp64()
+    ctx = make_ctx(s, prec)
+    m2 = mode_radius2(s.alpha, s.L, 1e-6)
+    nm = set_ewald(ctx, m2)
+    m, w = O.ewald_modes(s.alpha, s.L, m2)
+    assert nm == m.shape[1] > s.p
+    assert ctx.nmodes == nm
+    P, Q, V, F = device_state(ctx, s)
+    pos, q = rounded(s, prec)
+    R.rbe_kspace_forces(ctx, P, Q, F)
+    assert rel_l2(host(F), O.kspace_force(pos, q, s.L, m, w)) <= tol
+    _, (e,) = R.rbe_energy(ctx, P, Q)
+    assert e["e_kspace"] == pytest.approx(O.kspace_energy(pos, q, s.L, m, w), rel=tol)
 
 
 @pytest.mark.parametrize("prec,tol", [(R.RBE_FP64, 1e-12), (R.RBE_FP32, 1e-5)])

@@ -163,3 +163,65 @@ def test_erfc_fit_reproduces_the_table():
     p, coef = erfc_table()
     assert p == m.P
     np.testing.assert_allclose(coef, c[::-1], rtol=1e-8)
+
+
+def test_tile_cache_file_is_read(tmp_path):
+    """The tile cache (filled by rbe_autotune, consulted at creation) reads
+    its file once per process; keys are power-of-two buckets of N and P."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tiles.txt"
+    cache.write_text("# arch prec n_bucket p_bucket batched rho_chunk rho_block force_split real_split\n"
+                     "gfx950 0 16 6 0 392 1024 4 4\n"
+                     "gfx950 0 19 8 1 256 512 2 8   # a batch\n"
+                     "garbage line\n")
+    code = ("import paper_2010_01559_amd.rbe as R, json; "
+            "print(json.dumps([R.rbe_tune_lookup('gfx950:sramecc+:xnack-', 0, 100000, 100), "
+            "R.rbe_tune_lookup('gfx950', 0, 600000, 300, 64), R.rbe_tune_lookup('gfx950', 1, 100000, 100), "
+            "R.rbe_tune_lookup('gfx950', 0, 200000, 100)]))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=dict(os.environ, RBE_TUNE_CACHE=str(cache)),
+                         capture_output=True, text=True, check=True).stdout
+    import json
+    a, b, c, d = json.loads(out.strip().splitlines()[-1])
+    assert a == {"rho_chunk": 392, "rho_block": 1024, "force_split": 4, "real_split": 4}
+    assert b == {"rho_chunk": 256, "rho_block": 512, "force_split": 2, "real_split": 8}
+    assert c is None and d is None   # other precision; other N bucket
+
+
+def committed_tile_cache():
+    """Entries of the tile cache that ships beside the library."""
+    rows = []
+    with open(os.path.join(ROOT, "paper_2010_01559_amd", "rbe_tiles.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].split()
+            if line:
+                assert len(line) == 9, line
+                rows.append((line[0], *map(int, line[1:])))
+    return rows
+
+
+def test_committed_tile_cache_is_well_formed(tmp_path):
+    """Every shipped entry is a shape the kernels accept (the bounds of
+    rbe_set_tiles and the 64 KiB of dynamic LDS), and the default lookup
+    (no RBE_TUNE_CACHE) finds the last entry of each key."""
+    import json
+    import subprocess
+    import sys
+    rows = committed_tile_cache()
+    assert rows
+    last = {}
+    for arch, prec, nb, pb, batched, chunk, block, fsplit, rsplit in rows:
+        assert arch == "gfx950" and prec in (0, 1) and batched in (0, 1)
+        assert 64 <= chunk <= 2048 and chunk % 8 == 0 and block in (256, 512, 1024)
+        assert fsplit in (1, 2, 4) and rsplit in (1, 2, 4, 8)
+        assert 48 * chunk + 16 * block <= 65536 and 32 * (chunk + 256) + 28 * block <= 65536
+        last[(prec, nb, pb, batched)] = dict(rho_chunk=chunk, rho_block=block, force_split=fsplit,
+                                             real_split=rsplit)
+    keys = sorted(last)
+    code = ("import paper_2010_01559_amd.rbe as R, json; print(json.dumps([R.rbe_tune_lookup('gfx950', p, 2**nb, "
+            "2**pb, 2 if b else 1) for p, nb, pb, b in %r]))" % (keys,))
+    env = {k: v for k, v in os.environ.items() if k != "RBE_TUNE_CACHE"}
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         check=True).stdout
+    got = json.loads(out.strip().splitlines()[-1])
+    assert got == [last[k] for k in keys]

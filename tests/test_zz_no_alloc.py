@@ -16,8 +16,16 @@ from gpu_util import device_state, host, make_ctx, rel_l2, rounded
 pytestmark = pytest.mark.gpu
 
 
+def _builtin_tiles(n):
+    # the shapes the no-allocation entry point always uses (a context may
+    # hold others from the tile cache or an earlier rbe_autotune)
+    chunk = min(512, max(64, ((n + 255) // 256 + 7) // 8 * 8))
+    return dict(rho_chunk=chunk, rho_block=1024, force_split=2 if n >= 500000 else 4)
+
+
 def _context_force(s, prec, modes):
     ctx = make_ctx(s, prec)
+    R.rbe_set_tiles(ctx, **_builtin_tiles(s.n))
     P, Q, V, F = device_state(ctx, s)
     R.rbe_set_k(ctx, modes)
     R.rbe_kspace_forces(ctx, P, Q, F)
