@@ -70,7 +70,7 @@ PEAK_HBM_GBS = 8000.0
 # cell pass, which reads several times more, is left out, as the timed window
 # of the N = 1e5 run holds no rebuild).
 TRAFFIC = {
-    "real": {"src": "f70e83a5391a3b37", "fetch_kib": 7840.5, "write_kib": 6408.7, "fetch_scale": 2.000,
+    "real": {"src": "61ecf50de13ea5a1", "fetch_kib": 7840.3, "write_kib": 6428.9, "fetch_scale": 2.000,
              "write_scale": 1.000},
 }
 

@@ -49,7 +49,9 @@ typedef enum rbe_status {
     RBE_ERR_CUTOFF = -3,       /* r_cut or the LJ cutoff exceeds L/2 */
     RBE_ERR_OOM = -4,          /* device allocation failed at creation */
     RBE_ERR_HIP = -5,          /* a HIP runtime call failed */
-    RBE_ERR_NONFINITE = -6,    /* non-finite value seen by a kernel */
+    RBE_ERR_NONFINITE = -6,    /* non-finite value seen by a kernel, or (single precision) a
+                                  real-space force of 2^20 or more, beyond which the exact
+                                  fixed-point pair sums lose exactness (overlapping particles) */
     RBE_ERR_STATE = -7,        /* call not valid in the current state */
     RBE_ERR_NO_DEVICE = -8,    /* no usable gfx950 device */
     RBE_ERR_TIMEOUT = -9       /* a bounded device-side wait of a neighbour-list rebuild gave
@@ -126,7 +128,8 @@ typedef struct rbe_energy_t {
                           (scaling derivative of the Fourier sum); eq. 4.3 uses
                           vir = (virial + virial_kspace) / 2 */
     double charge_sum; /* sum q_i, for the neutrality check */
-    int32_t nonfinite; /* non-zero if any kernel met a non-finite force since the last check */
+    int32_t nonfinite; /* non-zero if any kernel met a non-finite force (or a single-precision
+                          real-space force of 2^20 or more) since the last check */
     int32_t timeout;   /* non-zero if a list rebuild's bounded wait gave up since the last check */
 } rbe_energy_t;
 
@@ -274,8 +277,8 @@ rbe_status rbe_batch_step(rbe_ctx *ctx, void *pos, void *vel, const void *q, voi
 rbe_status rbe_energy(rbe_ctx *ctx, const void *pos, const void *q, const void *vel, rbe_energy_t *out);
 
 /* Pending device-side errors since the previous check (by this call, rbe_energy or
- * rbe_list_builds): RBE_ERR_NONFINITE if a kernel met a non-finite force,
- * RBE_ERR_TIMEOUT if a list rebuild's bounded wait gave up (then the cell
+ * rbe_list_builds): RBE_ERR_NONFINITE if a kernel met a non-finite force or
+ * (single precision) a real-space force of 2^20 or more, RBE_ERR_TIMEOUT if a list rebuild's bounded wait gave up (then the cell
  * state is cleared and the next step rebuilds from scratch), else RBE_OK.
  * Clears what it reports.  Synchronises the stream.  Time steps are
  * asynchronous and cannot return these errors themselves. */

@@ -1470,6 +1470,9 @@ static rbe_status device_error_status(rbe_ctx *c, int32_t bits)
         return set_err(c, RBE_ERR_TIMEOUT, "a neighbour-list rebuild met stale cell counts; the forces of the "
                                            "steps since the last check are not valid");
     if (bits & kFlagNonFinite) return set_err(c, RBE_ERR_NONFINITE, "a kernel met a non-finite force");
+    if (bits & kFlagRange)
+        return set_err(c, RBE_ERR_NONFINITE, "a real-space force reached 2^20 (overlapping particles): single-precision "
+                                             "pair sums are no longer exact and the forces are not valid");
     return RBE_OK;
 }
 
@@ -1543,7 +1546,7 @@ rbe_status rbe_energy(rbe_ctx *c, const void *pos, const void *q, const void *ve
         e.virial = acc[8 * r + 2];
         e.e_kin = vel ? acc[8 * r + 3] : 0.0;
         e.charge_sum = acc[8 * r + 5];
-        e.nonfinite = (flag[0] & kFlagNonFinite) ? 1 : 0;
+        e.nonfinite = (flag[0] & (kFlagNonFinite | kFlagRange)) ? 1 : 0;
         e.timeout = (flag[0] & (kFlagTimeout | kFlagBounds)) ? 1 : 0;
         if (std::fabs(acc[8 * r + 5]) > 1e-6 * acc[8 * r + 6] && ret == RBE_OK) {
             ret = set_err(c, RBE_ERR_NOT_NEUTRAL,

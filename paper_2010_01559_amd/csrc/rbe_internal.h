@@ -44,6 +44,7 @@ constexpr uint32_t kTagMH = 0x04000000u;
 constexpr int32_t kFlagNonFinite = 1;   // a kernel met a non-finite force
 constexpr int32_t kFlagTimeout = 2;     // a bounded wait of a list rebuild gave up
 constexpr int32_t kFlagBounds = 4;      // a rebuild index fell outside its system (skipped)
+constexpr int32_t kFlagRange = 8;       // a single-precision real-space partial sum left the exact range
 
 // Default bound on the spin iterations of a device-side wait.
 constexpr int32_t kWaitLimit = 1 << 24;

@@ -77,6 +77,17 @@ struct PairE {
 // single precision, where it is exact: the same values as
 // rint((double)(phi d) * 2^32) with fewer double-precision instructions.
 __device__ __forceinline__ float qphi(float phi) { return phi * 0x1p32f; }
+
+// Flags a single-precision partial sum (in units of 2^-32) that has reached
+// 2^52, half the range in which the grid sums are exact (checked at the end
+// of each lane's sum and after the lanes of a particle are combined): only
+// particles pressed far into each other's LJ wall get there (a force of
+// 2^20), and then the forces are reported as unusable instead of silently
+// losing exactness.
+__device__ __forceinline__ void range_check(double x, double y, double z, int32_t *flag)
+{
+    if (fmax(fabs(x), fmax(fabs(y), fabs(z))) >= 0x1p52) atomicOr(flag, kFlagRange);
+}
 __device__ __forceinline__ double qphi(double phi) { return phi; }
 __device__ __forceinline__ double qterm(float scaled) { return (double)rintf(scaled); }
 __device__ __forceinline__ double qterm(double v) { return v; }
@@ -584,6 +595,7 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
         ev[0] += e.e_real;
         ev[1] += e.e_lj;
     }
+    if constexpr (sizeof(T) == 4) range_check(fx, fy, fz, a.flag);
     fx *= qscale<T>();
     fy *= qscale<T>();
     fz *= qscale<T>();
@@ -660,6 +672,7 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
             }
         });
     }
+    if constexpr (sizeof(T) == 4) range_check(fx, fy, fz, a.flag);
     // add the nine row sums of each particle in row order
     s_red[0][tid] = fx;
     s_red[1][tid] = fy;
@@ -677,6 +690,7 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
             sy += s_red[1][tid + j];
             sz += s_red[2][tid + j];
         }
+        if constexpr (sizeof(T) == 4) range_check(sx, sy, sz, a.flag);
         if constexpr (ENERGY)
             for (int j = 0; j < 9; ++j) {
                 ev[0] += s_red[3][tid + j];
@@ -781,6 +795,7 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
             }
         }
     }
+    if constexpr (sizeof(T) == 4) range_check(fx, fy, fz, a.flag);
 #pragma unroll
     for (int o = 1; o < LPP; o <<= 1) {
         fx += __shfl_xor(fx, o, 64);
@@ -788,6 +803,7 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
         fz += __shfl_xor(fz, o, 64);
     }
     if (act && sub == 0) {
+        if constexpr (sizeof(T) == 4) range_check(fx, fy, fz, a.flag);
         fx *= qscale<T>();
         fy *= qscale<T>();
         fz *= qscale<T>();

@@ -79,3 +79,22 @@ def test_non_finite_position_is_reported_by_check():
     R.rbe_kspace_forces(ctx, P, Q, F)
     assert R.rbe_check_status(ctx) == R.RBE_ERR_NONFINITE
     assert R.rbe_check_status(ctx) == R.RBE_OK
+
+
+def test_overlap_beyond_the_exact_range_is_reported():
+    """Two ions pressed into each other's LJ wall (r = 0.3 sigma, a pair force
+    near 3e8): the single-precision pair sums would leave the range in which
+    they are exact, and rbe_check reports RBE_ERR_NONFINITE instead of
+    returning silently rounded forces; the same system at its drawn positions
+    reports nothing."""
+    s = W.langevin_electrolyte()
+    ctx = make_ctx(s, R.RBE_FP32)
+    P, Q, V, F = device_state(ctx, s)
+    R.rbe_real_forces(ctx, P, Q, F)
+    assert R.rbe_check_status(ctx) == R.RBE_OK
+    P[:, 1] = P[:, 0]
+    P[0, 1] = (P[0, 0] + 0.3) % s.L
+    R.rbe_real_forces(ctx, P, Q, F)
+    assert R.rbe_check_status(ctx) == R.RBE_ERR_NONFINITE
+    assert "2^20" in R.lib().rbe_last_error(ctx.handle).decode()
+    assert R.rbe_check_status(ctx) == R.RBE_OK
