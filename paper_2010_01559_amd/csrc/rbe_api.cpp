@@ -368,6 +368,14 @@ struct rbe_ctx {
     // runs first where that launch cannot)
     bool sample_pending = false;
     uint64_t sample_step = 0;
+    // The active modes are the exact sample of step cur_step (cur_drawn), and
+    // the totals launch of a force call draws the sample of cur_step + 1 into
+    // the alternate mode arrays (next_ready, next_step), so that an
+    // rbe_sample_k for that step only swaps the arrays.
+    bool cur_drawn = false;
+    uint64_t cur_step = 0;
+    bool next_ready = false;
+    uint64_t next_step = 0;
     LaunchCfg cfg{};
     Workspace w{};
     size_t partial_cap = 0;        // doubles allocated for partial
@@ -958,6 +966,7 @@ rbe_status rbe_reserve_modes(rbe_ctx *c, int32_t cap)
     };
     drop_graphs(c);
     c->sample_pending = false;
+    c->cur_drawn = c->next_ready = false;
     const int old_cap = c->mcap;
     c->mcap = cap;
     rbe_status s;
@@ -996,19 +1005,29 @@ rbe_status rbe_sample_k(rbe_ctx *c, uint64_t step, int32_t *modes_out)
             dirty = true;
         }
     if (dirty) {
+        c->next_ready = false;
         rbe_status s = upload_sys(c);
         if (s != RBE_OK) return s;
         refresh_cfg_modes(c);
         if ((s = upload_rho_tiles(c)) != RBE_OK) return s;
     }
     c->modes_valid = true;
-    if (!c->any_mh && !modes_out) {
+    c->cur_drawn = !c->any_mh;
+    c->cur_step = step;
+    if (!c->any_mh && c->next_ready && c->next_step == step) {
+        // drawn already by the totals launch of the last force call
+        std::swap(c->w.modes, c->w.modes_alt);
+        std::swap(c->w.mode_w, c->w.mode_w_alt);
+        c->next_ready = false;
+        c->sample_pending = false;
+    } else if (!c->any_mh && !modes_out) {
         c->sample_pending = true;
         c->sample_step = step;
         return RBE_OK;
+    } else {
+        c->sample_pending = false;
+        RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, step, c->any_mh ? 1 : 0));
     }
-    c->sample_pending = false;
-    RUN(c, K_SAMPLE, launch_sample(c->cfg, c->w, step, c->any_mh ? 1 : 0));
     if (modes_out) {
         for (int d = 0; d < 3; ++d)
             HIPCHK(c, hipMemcpyAsync(modes_out + (size_t)d * c->mtot, c->w.modes + (size_t)d * c->mcap,
@@ -1037,6 +1056,7 @@ rbe_status rbe_set_k(rbe_ctx *c, const int32_t *modes, int32_t nm, const double 
         if (!std::isfinite(wv[l])) return set_err(c, RBE_ERR_INVALID, "non-finite weight");
     }
     c->sample_pending = false;
+    c->cur_drawn = c->next_ready = false;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->w.modes, m.data(), sizeof(int32_t) * m.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->w.mode_w, wv.data(), sizeof(double) * nm, hipMemcpyHostToDevice));
@@ -1176,7 +1196,15 @@ static rbe_status kspace_impl(rbe_ctx *c, const void *pos, const void *q, void *
         }
     }
     RUN(c, K_STAGE, launch_stage(c->cfg, c->w, rq));
-    RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0));
+    // the totals launch also draws the sample of the next step into the
+    // alternate mode arrays (one block per system, beside the totals blocks)
+    const bool predict = c->cur_drawn && !c->any_mh && !c->fixed &&
+                         !(c->next_ready && c->next_step == c->cur_step + 1);
+    RUN(c, K_MID, launch_mid(c->cfg, c->w, 1, 0, nullptr, nullptr, nullptr, predict ? 1 : 0, c->cur_step + 1));
+    if (predict) {
+        c->next_ready = true;
+        c->next_step = c->cur_step + 1;
+    }
     const int fblocks = (c->cfg.n_force_tiles * c->cfg.force_split + 3) / 4;
     const int fs = c->w.fpart ? mode_split(fblocks, c->max_p, 1024) : 1;
     if (force) RUN(c, K_KFORCE, launch_kforce(c->cfg, c->w, pos, q, force, accumulate, 0, fs));
@@ -1337,7 +1365,10 @@ rbe_status rbe_step(rbe_ctx *c, void *pos, void *vel, const void *q, void *force
         if (st != RBE_OK) return st;
     } else if (nsteps > 0) {
         c->sample_pending = false;   // the first step draws its own modes
+        c->cur_drawn = false;
     }
+    // time steps draw the next step's modes into the alternate arrays
+    if (nsteps > 0) c->next_ready = false;
     for (int r = 0; r < c->R && !c->fixed; ++r)
         if (c->sysh[r].p != c->prm[r].p) {
             // explicit modes were set: stepping resamples, so restore p

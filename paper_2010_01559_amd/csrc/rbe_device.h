@@ -92,19 +92,34 @@ __device__ __forceinline__ double normal_t(uint32_t i, uint64_t seed, uint64_t s
         return normal_comp(i, seed, step, d);
 }
 
-// Smallest index k of the cumulative table t[0..K) with u < t[k]; the last
-// entry is 1 and u < 1, so the answer is in range.
-__device__ __forceinline__ int invert_cdf(const double *t, int K, double u)
+// For each of three uniforms u, the smallest index k of the cumulative table
+// t[0..K) with u < t[k] (the last entry is 1 and u < 1, so the answer is in
+// range), by bisection.  The three bisections advance together, so that
+// their table reads are in flight at the same time instead of one after
+// another: an interval of n entries needs at most ceil(log2 n) halvings, and
+// a finished bisection only rereads its entry.
+__device__ __forceinline__ void invert_cdf3(const double *t, int K, const double u[3], int out[3])
 {
-    int lo = 0, hi = K - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (u < t[mid])
-            hi = mid;
-        else
-            lo = mid + 1;
+    int lo[3] = {0, 0, 0}, hi[3] = {K - 1, K - 1, K - 1};
+    for (int n = K; n > 1; n = (n + 1) >> 1) {
+        double v[3];
+        int mid[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            mid[d] = (lo[d] + hi[d]) >> 1;
+            v[d] = t[mid[d]];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const bool below = u[d] < v[d];
+            if (lo[d] < hi[d]) {
+                hi[d] = below ? mid[d] : hi[d];
+                lo[d] = below ? lo[d] : mid[d] + 1;
+            }
+        }
     }
-    return lo;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[d] = lo[d];
 }
 
 // One exact draw from the importance distribution (Sec. 3.1, eq. 3.3): each
@@ -119,9 +134,12 @@ __device__ __forceinline__ void sample_mode(const double *t, int M, uint32_t l, 
     for (uint32_t a = 0; a < (1u << 22); ++a) {
         const U4 r0 = draw(l, kTagSample | (2u * a), seed, step);
         const U4 r1 = draw(l, kTagSample | (2u * a + 1u), seed, step);
-        mx = invert_cdf(t, K, u53(r0.x, r0.y)) - M;
-        my = invert_cdf(t, K, u53(r0.z, r0.w)) - M;
-        mz = invert_cdf(t, K, u53(r1.x, r1.y)) - M;
+        const double u[3] = {u53(r0.x, r0.y), u53(r0.z, r0.w), u53(r1.x, r1.y)};
+        int c[3];
+        invert_cdf3(t, K, u, c);
+        mx = c[0] - M;
+        my = c[1] - M;
+        mz = c[2] - M;
         if (mx | my | mz) break;
     }
 }

@@ -147,6 +147,7 @@ struct StageArgs {
     int do_integrate, do_bin, do_sample, table_lds, do_rho;
     int kick;   // deferred closing half kick of the previous step
     int chunk;
+    int single_n;          // single-system context (SINGLE launches): its particle count
     int tab_max;           // LDS doubles reserved for the table
     // neighbour-list mode of a time step
     int list_mode;
@@ -249,15 +250,18 @@ constexpr int kRhoUnroll = 8;
 // Ewald lists): without the integrator, binning, sampling and list code it
 // needs far fewer registers, so more blocks share a compute unit.  VAR = 1
 // adds the mode draw (force calls after rbe_sample_k), VAR = 2 is the full
-// time-step variant.
-template <typename T, int BS, int VAR>
+// time-step variant.  SINGLE (single-system contexts) forms the block's tile
+// from its index, as the host builds it, instead of loading it, so that the
+// first particle loads do not wait for the tile and system constants.
+template <typename T, int BS, int VAR, bool SINGLE>
 __global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T> a)
 {
     constexpr bool FULL = VAR == 2;     // integrator, binning, list bookkeeping
     constexpr bool SAMPLE = VAR >= 1;   // draws the modes in the launch
     extern __shared__ __align__(16) unsigned char smem[];
-    const Tile t = a.tiles[blockIdx.x];
-    const SysDev S = a.sys[t.sys];
+    const int bx = (int)blockIdx.x;
+    const Tile t = SINGLE ? Tile{0, bx * a.chunk, min(a.chunk, a.single_n - bx * a.chunk), bx} : a.tiles[bx];
+    const SysDev S = a.sys[SINGLE ? 0 : t.sys];
     using RR = typename RhoRec<T>::type;
     RR *sp = reinterpret_cast<RR *>(smem);
     double2 *red = reinterpret_cast<double2 *>(smem + sizeof(RR) * (a.chunk + kRhoUnroll * kRhoGroupsMax));
@@ -498,9 +502,10 @@ struct ForceArgs {
     // gridDim.y > 1: the mode list is split over y; partial sums go to
     // fpart[y][3][ntot] and k_fsum finishes the particles
     T *fpart;
+    int single_n;   // single-system context (SINGLE launches): its particle count
 };
 
-template <typename T, typename KM, int SPLIT>
+template <typename T, typename KM, int SPLIT, bool SINGLE>
 __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
 {
     __shared__ T red[4][3][64];
@@ -513,9 +518,10 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
     T qi = 0;
     int sysi = 0;
     if (ti < a.ntiles) {
-        const Tile t = a.tiles[ti];
+        // SINGLE: the host's 64-particle tile of a single system, formed here
+        const Tile t = SINGLE ? Tile{0, 64 * ti, min(64, a.single_n - 64 * ti), 0} : a.tiles[ti];
         sysi = t.sys;
-        const SysDev S = a.sys[t.sys];
+        const SysDev S = a.sys[SINGLE ? 0 : t.sys];
         double s3[3] = {0.0, 0.0, 0.0};
         if (lane < t.count) {
             i = S.off + t.start + lane;
@@ -879,6 +885,28 @@ size_t stage_lds_bytes(const LaunchCfg &c, int sample_in_kernel, int *table_lds,
     return base + sizeof(double) * (*tab_max);
 }
 
+template <typename T, int BS, bool SINGLE>
+static void stage_launch_bs(int var, dim3 g, size_t sm, hipStream_t st, const StageArgs<T> &a)
+{
+    if (var == 2)
+        launch_k(k_stage_rho<T, BS, 2, SINGLE>, g, BS, sm, st, a);
+    else if (var == 1)
+        launch_k(k_stage_rho<T, BS, 1, SINGLE>, g, BS, sm, st, a);
+    else
+        launch_k(k_stage_rho<T, BS, 0, SINGLE>, g, BS, sm, st, a);
+}
+
+template <typename T, bool SINGLE>
+static void stage_launch(int block, int var, dim3 g, size_t sm, hipStream_t st, const StageArgs<T> &a)
+{
+    if (block == 256)
+        stage_launch_bs<T, 256, SINGLE>(var, g, sm, st, a);
+    else if (block == 512)
+        stage_launch_bs<T, 512, SINGLE>(var, g, sm, st, a);
+    else
+        stage_launch_bs<T, 1024, SINGLE>(var, g, sm, st, a);
+}
+
 template <typename T>
 static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const StageRequest &rq)
 {
@@ -917,34 +945,13 @@ static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const S
     const size_t sm = stage_lds_bytes(c, rq.sample, &table_lds, &tab_max);
     a.table_lds = table_lds;
     a.tab_max = tab_max;
+    a.single_n = c.R == 1 ? (int)c.ntot : 0;
     dim3 g(c.n_rho_tiles, rq.mode_split > 1 ? rq.mode_split : 1);
     const int var = (rq.integrate || rq.bin || rq.list) ? 2 : (rq.sample ? 1 : 0);
-    switch (c.rho_block) {
-    case 256:
-        if (var == 2)
-            launch_k(k_stage_rho<T, 256, 2>, g, 256, sm, c.stream, a);
-        else if (var == 1)
-            launch_k(k_stage_rho<T, 256, 1>, g, 256, sm, c.stream, a);
-        else
-            launch_k(k_stage_rho<T, 256, 0>, g, 256, sm, c.stream, a);
-        break;
-    case 512:
-        if (var == 2)
-            launch_k(k_stage_rho<T, 512, 2>, g, 512, sm, c.stream, a);
-        else if (var == 1)
-            launch_k(k_stage_rho<T, 512, 1>, g, 512, sm, c.stream, a);
-        else
-            launch_k(k_stage_rho<T, 512, 0>, g, 512, sm, c.stream, a);
-        break;
-    default:
-        if (var == 2)
-            launch_k(k_stage_rho<T, 1024, 2>, g, 1024, sm, c.stream, a);
-        else if (var == 1)
-            launch_k(k_stage_rho<T, 1024, 1>, g, 1024, sm, c.stream, a);
-        else
-            launch_k(k_stage_rho<T, 1024, 0>, g, 1024, sm, c.stream, a);
-        break;
-    }
+    if (c.R == 1)
+        stage_launch<T, true>(c.rho_block, var, g, sm, c.stream, a);
+    else
+        stage_launch<T, false>(c.rho_block, var, g, sm, c.stream, a);
     return hipGetLastError();
 }
 
@@ -963,6 +970,8 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.R = c.R;
     a.max_p = c.max_p;
     a.n_final_blocks = do_final ? (c.R * c.max_p + 15) / 16 : 0;
+    a.single_p = c.R == 1 ? c.max_p : 0;
+    a.single_nt = c.n_rho_tiles;
     a.partial = w.partial;
     a.part_off = w.partial_off;
     a.modes = w.modes;
@@ -1039,6 +1048,22 @@ hipError_t launch_mid(const LaunchCfg &c, const Workspace &w, int do_final, int 
                                                      sample_next, sample_step, ls);
 }
 
+template <typename T, typename KM, bool SINGLE>
+static void kforce_launch(int split, int n, int ys, hipStream_t st, const ForceArgs<T, KM> &a)
+{
+    switch (split) {
+    case 1:
+        launch_k(k_kforce<T, KM, 1, SINGLE>, dim3((n + 3) / 4, ys), 256, 0, st, a);
+        break;
+    case 2:
+        launch_k(k_kforce<T, KM, 2, SINGLE>, dim3((n + 1) / 2, ys), 256, 0, st, a);
+        break;
+    default:
+        launch_k(k_kforce<T, KM, 4, SINGLE>, dim3(n, ys), 256, 0, st, a);
+        break;
+    }
+}
+
 template <typename T, typename KM>
 static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const void *pos, const void *q, void *F,
                                   int acc, int scatter, int mode_split)
@@ -1064,17 +1089,11 @@ static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const 
     a.sorted = w.sorted;
     const int n = c.n_force_tiles;
     const int ys = mode_split > 1 && w.fpart ? mode_split : 1;
-    switch (c.force_split) {
-    case 1:
-        launch_k(k_kforce<T, KM, 1>, dim3((n + 3) / 4, ys), 256, 0, c.stream, a);
-        break;
-    case 2:
-        launch_k(k_kforce<T, KM, 2>, dim3((n + 1) / 2, ys), 256, 0, c.stream, a);
-        break;
-    default:
-        launch_k(k_kforce<T, KM, 4>, dim3(n, ys), 256, 0, c.stream, a);
-        break;
-    }
+    a.single_n = c.R == 1 ? (int)c.ntot : 0;
+    if (c.R == 1)
+        kforce_launch<T, KM, true>(c.force_split, n, ys, c.stream, a);
+    else
+        kforce_launch<T, KM, false>(c.force_split, n, ys, c.stream, a);
     if (ys > 1)
         launch_k(k_fsum<T>, (int)((c.ntot + 255) / 256), 256, 0, c.stream, (const T *)w.fpart, ys, (const T *)q, c.ntot,
                                                                       (T *)F, acc, w.flag);

@@ -71,6 +71,8 @@ struct MidArgs {
     const SysDev *sys;
     int R, max_p;
     int n_final_blocks;   // blocks doing the structure-factor totals
+    int single_p;         // single-system context: its mode count (else 0) ...
+    int single_nt;        // ... and its structure-factor tile count
     const double *partial;
     const int32_t *part_off;   // [2R]: partial offsets, then tile counts
     const int32_t *modes;
@@ -165,10 +167,12 @@ __device__ void mid_final(const MidArgs<KM> &a, int gm)
 {
     const int r = gm / a.max_p, l = gm % a.max_p;
     if (r >= a.R) return;
-    const SysDev S = a.sys[r];
-    if (l >= S.p) return;
-    const int nt = a.part_off[a.R + r];
-    const double *base = a.partial + 2 * (int64_t)a.part_off[r];
+    // a single system's mode and tile counts come with the launch, so that
+    // the partial loads do not wait for the system constants and offsets
+    const int P = a.single_p ? a.single_p : a.sys[r].p;
+    if (l >= P) return;
+    const int nt = a.single_p ? a.single_nt : a.part_off[a.R + r];
+    const double *base = a.partial + (a.single_p ? 0 : 2 * (int64_t)a.part_off[r]);
     const int lane = threadIdx.x & 63;
     double c = 0.0, s = 0.0;
     // lane sums tiles lane, lane + 64, ... in order; eight loads are issued
@@ -178,7 +182,7 @@ __device__ void mid_final(const MidArgs<KM> &a, int gm)
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int t = t0 + 64 * u;
-            if (t < nt) v[u] = *reinterpret_cast<const double2 *>(base + 2 * ((int64_t)t * S.p + l));
+            if (t < nt) v[u] = *reinterpret_cast<const double2 *>(base + 2 * ((int64_t)t * P + l));
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
@@ -192,7 +196,10 @@ __device__ void mid_final(const MidArgs<KM> &a, int gm)
         c += __shfl_down(c, off, 64);
         s += __shfl_down(s, off, 64);
     }
-    if (lane == 0) make_kmode<KM>(S, a.modes, a.mode_w, a.mcap, S.moff + l, c, s, a.rho, a.km);
+    if (lane == 0) {
+        const SysDev &S = a.sys[r];
+        make_kmode<KM>(S, a.modes, a.mode_w, a.mcap, S.moff + l, c, s, a.rho, a.km);
+    }
 }
 
 // Exclusive scan of one system's cell counts with NW waves (64 NW threads).

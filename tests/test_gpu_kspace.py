@@ -114,6 +114,59 @@ def test_cached_tile_shapes_keep_parity(shape):
     assert np.isfinite(host(P)).all()
 
 
+@pytest.mark.parametrize("prec", [R.RBE_FP32, R.RBE_FP64])
+def test_next_sample_drawn_ahead(prec):
+    """A force call draws the sample of the next step ahead (in its totals
+    launch, into the alternate mode arrays); rbe_sample_k for that step then
+    takes it.  Modes and Fourier forces equal those of a context that draws
+    each step from scratch, bit for bit, whether the step was drawn ahead
+    (8, 9, 12) or not (11, after 10 was skipped), and with a time step in
+    between (which draws into the same arrays)."""
+    s = W.langevin_electrolyte()
+    a, b = make_ctx(s, prec), make_ctx(s, prec)
+    P, Q, V, F = device_state(a, s)
+    Fb = torch.zeros_like(F)
+    R.rbe_sample_k(a, 7)
+    R.rbe_kspace_forces(a, P, Q, F)
+    for step in (8, 9, 11, 12, "step", 14, 15):
+        if step == "step":
+            P2, V2, F2 = P.clone(), V.clone(), F.clone()
+            R.rbe_real_forces(a, P2, Q, F2, accumulate=True)
+            R.rbe_step(a, P2, V2, Q, F2, 13, 2)
+            continue
+        ma = torch.zeros((3, s.p), dtype=torch.int32, device="cuda")
+        mb = torch.zeros_like(ma)
+        R.rbe_sample_k(a, step, ma)
+        R.rbe_kspace_forces(a, P, Q, F)
+        R.rbe_sample_k(b, step, mb)
+        R.rbe_kspace_forces(b, P, Q, Fb)
+        assert torch.equal(ma, mb), step
+        assert np.array_equal(host(F), host(Fb)), step
+        R.rbe_sample_k(a, step + 1)      # without modes_out: the drawn-ahead arrays
+        R.rbe_kspace_forces(a, P, Q, F)
+        R.rbe_sample_k(b, step + 1)
+        R.rbe_kspace_forces(b, P, Q, Fb)
+        assert np.array_equal(host(F), host(Fb)), step + 1
+
+
+def test_next_sample_drawn_ahead_batched():
+    """The same for a batch of three replicas: every system draws its own
+    next sample ahead."""
+    systems = W.replica_systems(R=3, nmin=500, nmax=3000)
+    cat = lambda xs: np.ascontiguousarray(np.concatenate(xs, axis=-1))
+    prm = [R.params_from_system(x, R.RBE_FP32) for x in systems]
+    a, b = R.rbe_batch_create(prm), R.rbe_batch_create(prm)
+    P = R.to_device(cat([x.pos for x in systems]), a)
+    Q = R.to_device(cat([x.q for x in systems]), a)
+    F, Fb = torch.zeros_like(P), torch.zeros_like(P)
+    for step in (3, 4, 5):
+        R.rbe_sample_k(a, step)
+        R.rbe_kspace_forces(a, P, Q, F)
+        R.rbe_sample_k(b, step, torch.zeros((3, sum(p.p for p in prm)), dtype=torch.int32, device="cuda"))
+        R.rbe_kspace_forces(b, P, Q, Fb)
+        assert np.array_equal(host(F), host(Fb)), step
+
+
 def test_kspace_odd_sizes_fp32():
     # tiny, prime and single-particle-tail sizes with P not a multiple of 64
     for n, p in [(2, 1), (65, 7), (257, 33), (1025, 130)]:
