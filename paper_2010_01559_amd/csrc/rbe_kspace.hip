@@ -402,7 +402,9 @@ __global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T>
             prow[2 * l] = c;
             prow[2 * l + 1] = s;
         }
-        __syncthreads();
+        // the next mode tile reuses smode and red; after the last one the
+        // block ends without waiting for its stores
+        if (m0 + Pt < me) __syncthreads();
     }
 }
 
@@ -739,7 +741,7 @@ __global__ __launch_bounds__(BS) void k_vjp_reduce(const SysDev *__restrict__ sy
             prow[2 * l] = av;
             prow[2 * l + 1] = bv;
         }
-        __syncthreads();
+        if (m0 + Pt < P) __syncthreads();   // red is reused by the next mode tile
     }
 }
 

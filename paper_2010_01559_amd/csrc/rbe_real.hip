@@ -562,8 +562,9 @@ __device__ __forceinline__ void add_fourier(Four<T> s4, int k, T qi, double &fx,
 }
 
 // All-pairs tile: particles [start, start + count) of a one-cell system, one
-// per thread, partners in original index order.
-template <typename T, bool ENERGY>
+// per thread, partners in original index order.  DIAM compiles the
+// per-particle-diameter LJ (only launches of contexts with diameters).
+template <typename T, bool ENERGY, bool DIAM>
 __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &t, const SysDev &S, double *ev,
                                               Four<T> s4 = nullptr)
 {
@@ -574,7 +575,7 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
     if ((int)threadIdx.x >= t.count) return;
     const int il = t.start + threadIdx.x;
     const Rec pa = pk[il];
-    const double da = S.diam_on ? a.diam[S.off + il] : 0.0;
+    const double da = DIAM && S.diam_on ? a.diam[S.off + il] : 0.0;
     double fx = 0, fy = 0, fz = 0;
     PairE e{0, 0};
     for (int j = 0; j < S.n; ++j) {
@@ -584,7 +585,7 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
         T dx, dy, dz, r2;
         displacement(pa, pb, geo, dx, dy, dz, r2);
         T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
-        if (S.diam_on) phi += (T)lj_offset<ENERGY>(S, da, a.diam[S.off + j], r2_double(pa, pb, S.L), e);
+        if (DIAM && S.diam_on) phi += (T)lj_offset<ENERGY>(S, da, a.diam[S.off + j], r2_double(pa, pb, S.L), e);
         const T ph = qphi(phi);
         fx += qterm(ph * dx);
         fy += qterm(ph * dy);
@@ -606,7 +607,7 @@ __device__ __forceinline__ void allpairs_body(const RealArgs<T> &a, const Tile &
 // Row-lane tile on the cell list.  With BUILD the rows are scanned with the
 // list radius and every hit is also written to the particle's list: the nine
 // row counts are prefixed in LDS so that the list keeps row order.
-template <typename T, bool ENERGY, bool BUILD>
+template <typename T, bool ENERGY, bool BUILD, bool DIAM>
 __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *la, const Tile &t, const SysDev &S,
                                           double *ev, Four<T> s4 = nullptr)
 {
@@ -640,7 +641,7 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
         const int32_t *st = a.start + S.cell_off + t.sys;
         row_scan(pa, slot, cx, yy, zz, nc, st, gs, geo, rs, S.off, S.off + S.n);
     }
-    const double da = act && S.diam_on ? a.diam[a.sorted_idx[slot]] : 0.0;
+    const double da = DIAM && act && S.diam_on ? a.diam[a.sorted_idx[slot]] : 0.0;
     int pos = 0, total = 0;
     if constexpr (BUILD) {
         const int cnt = __builtin_popcountll(rs.m[0]) + __builtin_popcountll(rs.m[1]);
@@ -660,7 +661,8 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
             T dx, dy, dz, r2;
             displacement(pa, pb, geo, dx, dy, dz, r2);
             T phi = pair_phi<ENERGY>(pc, (T)pa.q, (T)pb.q, r2, e);
-            if (S.diam_on) phi += (T)lj_offset<ENERGY>(S, da, a.diam[a.sorted_idx[b]], r2_double(pa, pb, S.L), e);
+            if (DIAM && S.diam_on)
+                phi += (T)lj_offset<ENERGY>(S, da, a.diam[a.sorted_idx[b]], r2_double(pa, pb, S.L), e);
             const T ph = qphi(phi);
             fx += qterm(ph * dx);
             fy += qterm(ph * dy);
@@ -730,21 +732,21 @@ __device__ __forceinline__ void energy_block(double *ev, double *out)
     }
 }
 
-template <typename T, bool ENERGY>
+template <typename T, bool ENERGY, bool DIAM>
 __global__ __launch_bounds__(RL_BS) void k_real_rows(RealArgs<T> a)
 {
     const Tile t = a.tiles[blockIdx.x];
     const SysDev S = a.sys[t.sys];
     double ev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (t.aux == 1)
-        allpairs_body<T, ENERGY>(a, t, S, ev);
+        allpairs_body<T, ENERGY, DIAM>(a, t, S, ev);
     else
-        rows_body<T, ENERGY, false>(a, nullptr, t, S, ev);
+        rows_body<T, ENERGY, false, DIAM>(a, nullptr, t, S, ev);
     if constexpr (ENERGY) energy_block(ev, a.epart + 8 * blockIdx.x);
 }
 
 // List tile: LPP lanes per cell-sorted slot.
-template <typename T, int LPP>
+template <typename T, int LPP, bool DIAM>
 __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &la, const Tile &t, const SysDev &S,
                                           Four<T> s4 = nullptr)
 {
@@ -762,7 +764,7 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
         const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
         const Rec pa = gs[slot];
         qi = (T)pa.q;
-        const double da = S.diam_on ? a.diam[a.sorted_idx[slot]] : 0.0;
+        const double da = DIAM && S.diam_on ? a.diam[a.sorted_idx[slot]] : 0.0;
         const int n = la.nnb[slot];
         const int32_t *nb = la.nbr + slot;
         PairE e{0, 0};
@@ -785,7 +787,7 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
                     T dx, dy, dz, r2;
                     displacement(pa, pb[u], geo, dx, dy, dz, r2);
                     T phi = pair_phi<false>(pc, (T)pa.q, (T)pb[u].q, r2, e);
-                    if (S.diam_on)
+                    if (DIAM && S.diam_on)
                         phi += (T)lj_offset<false>(S, da, a.diam[a.sorted_idx[b[u]]], r2_double(pa, pb[u], S.L), e);
                     const T ph = qphi(phi);
                     fx += qterm(ph * dx);
@@ -816,7 +818,7 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
 // on the cell list with list build when the step's rebuild flag is set, else
 // on the list; then the closing half kick on the last step of a call.  Tiles
 // are taken in XCD order (xcd_tile).
-template <typename T, int LPP>
+template <typename T, int LPP, bool DIAM>
 __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
 {
     __shared__ T s4[4][FT_MAX][3];
@@ -837,11 +839,11 @@ __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
     fourier_tile<T>(a, S, allpairs ? a.packed : a.sorted, S.off + t.start, t.count, s4);
     __syncthreads();
     if (allpairs)
-        allpairs_body<T, false>(a, t, S, nullptr, s4);
+        allpairs_body<T, false, DIAM>(a, t, S, nullptr, s4);
     else if (rebuild)
-        rows_body<T, false, true>(a, &la, t, S, nullptr, s4);
+        rows_body<T, false, true, DIAM>(a, &la, t, S, nullptr, s4);
     else
-        list_body<T, LPP>(a, la, t, S, s4);
+        list_body<T, LPP, DIAM>(a, la, t, S, s4);
 }
 
 // Stand-alone scatter into cell order (force and energy calls; a time step
@@ -1049,12 +1051,15 @@ static RealArgs<T> real_args(const LaunchCfg &c, const Workspace &w, void *force
 hipError_t launch_real(const LaunchCfg &c, const Workspace &w, void *force, int accumulate, void *vel_kick,
                        uint64_t kick_step)
 {
+    // the per-particle-diameter LJ only in launches that need it: it costs
+    // the others registers (and with them resident blocks)
+    const bool diam = w.diam != nullptr;
     if (c.prec == RBE_FP64)
-        launch_k(k_real_rows<double, false>, c.n_real_tiles, RL_BS, 0, c.stream, 
-            real_args<double>(c, w, force, accumulate, vel_kick, nullptr, kick_step));
+        launch_k(diam ? k_real_rows<double, false, true> : k_real_rows<double, false, false>, c.n_real_tiles, RL_BS, 0,
+                 c.stream, real_args<double>(c, w, force, accumulate, vel_kick, nullptr, kick_step));
     else
-        launch_k(k_real_rows<float, false>, c.n_real_tiles, RL_BS, 0, c.stream, 
-            real_args<float>(c, w, force, accumulate, vel_kick, nullptr, kick_step));
+        launch_k(diam ? k_real_rows<float, false, true> : k_real_rows<float, false, false>, c.n_real_tiles, RL_BS, 0,
+                 c.stream, real_args<float>(c, w, force, accumulate, vel_kick, nullptr, kick_step));
     return hipGetLastError();
 }
 
@@ -1062,7 +1067,10 @@ template <typename T, int LPP>
 static void real_step_launch(const LaunchCfg &c, const RealArgs<T> &a, const ListArgs &la)
 {
     const int nb = la.n_rows > la.n_list ? la.n_rows : la.n_list;
-    launch_k(k_real_step<T, LPP>, nb, RL_BS, 0, c.stream, a, la);
+    if (a.diam)
+        launch_k(k_real_step<T, LPP, true>, nb, RL_BS, 0, c.stream, a, la);
+    else
+        launch_k(k_real_step<T, LPP, false>, nb, RL_BS, 0, c.stream, a, la);
 }
 
 template <typename T>
@@ -1106,12 +1114,13 @@ hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListSt
 
 hipError_t launch_energy(const LaunchCfg &c, const Workspace &w, const void *q, const void *vel)
 {
+    const bool diam = w.diam != nullptr;
     if (c.prec == RBE_FP64)
-        launch_k(k_real_rows<double, true>, c.n_real_tiles, RL_BS, 0, c.stream, 
-            real_args<double>(c, w, nullptr, 0, (void *)vel, q));
+        launch_k(diam ? k_real_rows<double, true, true> : k_real_rows<double, true, false>, c.n_real_tiles, RL_BS, 0,
+                 c.stream, real_args<double>(c, w, nullptr, 0, (void *)vel, q));
     else
-        launch_k(k_real_rows<float, true>, c.n_real_tiles, RL_BS, 0, c.stream, 
-            real_args<float>(c, w, nullptr, 0, (void *)vel, q));
+        launch_k(diam ? k_real_rows<float, true, true> : k_real_rows<float, true, false>, c.n_real_tiles, RL_BS, 0,
+                 c.stream, real_args<float>(c, w, nullptr, 0, (void *)vel, q));
     return hipGetLastError();
 }
 
