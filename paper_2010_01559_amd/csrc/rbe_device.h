@@ -92,6 +92,35 @@ __device__ __forceinline__ double normal_t(uint32_t i, uint64_t seed, uint64_t s
         return normal_comp(i, seed, step, d);
 }
 
+// All three components of normal_t at once, from one draw and in
+// straight-line code (the same operations per component).
+template <typename T>
+__device__ __forceinline__ void normal3_t(uint32_t i, uint64_t seed, uint64_t step, double xi[3])
+{
+    const U4 r = draw(i, kTagLangevin, seed, step);
+    if constexpr (sizeof(T) == 4) {
+        const float k = 1.0f / 4294967296.0f;
+        const float u1 = ((float)r.x + 1.0f) * k, u2 = (float)r.y * k;
+        const float u3 = ((float)r.z + 1.0f) * k, u4 = (float)r.w * k;
+        const float a = __builtin_amdgcn_sqrtf(-2.0f * 0.693147180559945309f * __builtin_amdgcn_logf(u1));
+        const float b = __builtin_amdgcn_sqrtf(-2.0f * 0.693147180559945309f * __builtin_amdgcn_logf(u3));
+        xi[0] = (double)(a * __builtin_amdgcn_cosf(u2));
+        xi[1] = (double)(a * __builtin_amdgcn_sinf(u2));
+        xi[2] = (double)(b * __builtin_amdgcn_cosf(u4));
+    } else {
+        const double k = 1.0 / 4294967296.0;
+        const double u1 = ((double)r.x + 1.0) * k, u2 = (double)r.y * k;
+        const double a = sqrt(-2.0 * log(u1));
+        double s, c;
+        sincospi(2.0 * u2, &s, &c);
+        xi[0] = a * c;
+        xi[1] = a * s;
+        const double u3 = ((double)r.z + 1.0) * k, u4 = (double)r.w * k;
+        const double b = sqrt(-2.0 * log(u3));
+        xi[2] = b * cospi(2.0 * u4);
+    }
+}
+
 // For each of three uniforms u, the smallest index k of the cumulative table
 // t[0..K) with u < t[k] (the last entry is 1 and u < 1, so the answer is in
 // range), by bisection.  The three bisections advance together, so that
@@ -391,11 +420,14 @@ __device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i
         v0[d] = vel[d * ntot + i];
         f[d] = F[d * ntot + i];
     }
+    // the three normals come from one draw outside the component loop, so
+    // that the loop unrolls and its arrays stay in registers
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (noise) normal3_t<T>((uint32_t)il, S.seed, step, xi);
     T p1[3], v1[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double xi = noise ? normal_t<T>((uint32_t)il, S.seed, step, d) : 0.0;
-        integrate_comp<T>(S, p0[d], v0[d], f[d], xi, hit, kick, dt, dt_prev, c1, c2, p1[d], v1[d]);
+        integrate_comp<T>(S, p0[d], v0[d], f[d], xi[d], hit, kick, dt, dt_prev, c1, c2, p1[d], v1[d]);
         x[d] = (double)p1[d];
     }
 #pragma unroll
