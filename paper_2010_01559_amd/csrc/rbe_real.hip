@@ -631,9 +631,11 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
     rs.walk = false;
     rs.b0[0] = rs.b0[1] = rs.b1[0] = rs.b1[1] = 0;
     rs.m[0] = rs.m[1] = 0;
+    int64_t iorig = 0;   // original index, loaded with the record (see list_body)
     if (act) {
         slot = S.off + t.start + k;
         pa = gs[slot];
+        iorig = a.sorted_idx[slot];
         const int nc = S.nc;
         int cx, cy, cz;
         cell_coords<T>(pa, nc, cx, cy, cz);
@@ -641,7 +643,7 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
         const int32_t *st = a.start + S.cell_off + t.sys;
         row_scan(pa, slot, cx, yy, zz, nc, st, gs, geo, rs, S.off, S.off + S.n);
     }
-    const double da = DIAM && act && S.diam_on ? a.diam[a.sorted_idx[slot]] : 0.0;
+    const double da = DIAM && act && S.diam_on ? a.diam[iorig] : 0.0;
     int pos = 0, total = 0;
     if constexpr (BUILD) {
         const int cnt = __builtin_popcountll(rs.m[0]) + __builtin_popcountll(rs.m[1]);
@@ -709,7 +711,7 @@ __device__ __forceinline__ void rows_body(const RealArgs<T> &a, const ListArgs *
         sy *= qscale<T>();
         sz *= qscale<T>();
         add_fourier<T>(s4, k, (T)pa.q, sx, sy, sz);
-        finish_particle<T, ENERGY>(a, S, a.sorted_idx[slot], sx, sy, sz, ev);
+        finish_particle<T, ENERGY>(a, S, iorig, sx, sy, sz, ev);
     }
 }
 
@@ -759,12 +761,16 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
     double fx = 0, fy = 0, fz = 0;
     int slot = 0;
     T qi = 0;
+    // the particle's original index (where its force goes) is loaded with
+    // its record, so that the store after the partner loop does not wait
+    int64_t iorig = 0;
     if (act) {
         slot = S.off + t.start + k;
         const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
         const Rec pa = gs[slot];
+        iorig = a.sorted_idx[slot];
         qi = (T)pa.q;
-        const double da = DIAM && S.diam_on ? a.diam[a.sorted_idx[slot]] : 0.0;
+        const double da = DIAM && S.diam_on ? a.diam[iorig] : 0.0;
         const int n = la.nnb[slot];
         const int32_t *nb = la.nbr + slot;
         PairE e{0, 0};
@@ -810,7 +816,7 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
         fy *= qscale<T>();
         fz *= qscale<T>();
         add_fourier<T>(s4, k, qi, fx, fy, fz);
-        finish_particle<T, false>(a, S, a.sorted_idx[slot], fx, fy, fz, nullptr);
+        finish_particle<T, false>(a, S, iorig, fx, fy, fz, nullptr);
     }
 }
 
