@@ -448,9 +448,8 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
         mid_bin<KM>(a, b);
         if (a.reb) {
             // publish this block's counts, cell ids and ranks
-            __threadfence();
-            __syncthreads();
-            if (threadIdx.x == 0) atomicAdd(a.rb.bins_done, 1);
+            block_release();
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(a.rb.bins_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }

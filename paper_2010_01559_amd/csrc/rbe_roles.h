@@ -305,28 +305,42 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
 // ---------------------------------------------------------------------------
 
 // Thread 0 waits (at most `limit` polls) until *p reaches want; the block
-// learns the outcome.
+// learns the outcome.  The polls are relaxed loads and one acquire follows
+// the last: on gfx950 an agent-scope acquire invalidates the XCD's L2, so
+// acquiring on every poll would keep evicting the data that the blocks still
+// working on that XCD read.  The block's waves share thread 0's compute unit
+// and L1, and the barrier orders their loads after its invalidation.
 __device__ bool block_wait(int32_t *p, int want, int limit, int32_t *flag, int32_t *poison)
 {
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
         int ok = 0;
         for (int it = 0; it < limit; ++it) {
-            if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) {
+            if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) {
                 ok = 1;
                 break;
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        if (!ok) {
+        if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);   // the invalidation is done before the barrier
+        } else {
             atomicOr(flag, kFlagTimeout);
             atomicOr(poison, 1);
         }
         s_ok = ok;
     }
     __syncthreads();
-    __threadfence();
     return s_ok != 0;
+}
+
+// Every wave of the block makes its stores visible to the agent (L2 write
+// back, no invalidation), then thread 0 may publish with a relaxed atomic.
+__device__ __forceinline__ void block_release()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
 }
 
 // Scan block of a rebuild: waits for every binning block, turns the cell
@@ -343,9 +357,8 @@ __device__ void rebuild_scan(const RebuildArgs &a)
         *a.builds += 1;
         *a.poison = 0;
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(a.ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    block_release();
+    if (threadIdx.x == 0) __hip_atomic_store(a.ready, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Scatter block b of nb: moves records into cell order once the scan is out,
