@@ -448,7 +448,7 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
         mid_bin<KM>(a, b);
         if (a.reb) {
             // publish this block's counts, cell ids and ranks
-            block_release();
+            block_stores_done();
             if (threadIdx.x == 0) __hip_atomic_fetch_add(a.rb.bins_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
@@ -961,6 +961,13 @@ hipError_t launch_stage(const LaunchCfg &c, const Workspace &w, const StageReque
     return c.prec == RBE_FP64 ? stage_dispatch<double>(c, w, rq) : stage_dispatch<float>(c, w, rq);
 }
 
+// Binning and scatter blocks of a list rebuild (each also capped at one per
+// four 256-particle tiles).  On steps without a rebuild each costs its
+// dispatch; with the flag hand-offs free of L2 write-backs and invalidations
+// the rebuild itself scales with them (measured at N = 1e5 and 1e6: 16 -> 128
+// blocks, step 41.3 -> 40.5 and 260 -> 255 us).
+constexpr int kRebBlocks = 128;
+
 template <typename KM>
 static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_final, int do_scan,
                                const int32_t *gate, const int32_t *bin_gate, int32_t *clear_flag, int sample_next,
@@ -985,7 +992,7 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.do_scan = do_scan;
     a.scan_gate = gate;
     a.bin_gate = bin_gate;
-    a.n_bin_blocks = bin_gate ? std::min(16, (c.n_part_tiles + 3) / 4) : 0;
+    a.n_bin_blocks = bin_gate ? std::min(kRebBlocks, (c.n_part_tiles + 3) / 4) : 0;
     a.part_tiles = w.part_tiles;
     a.n_part_tiles = c.n_part_tiles;
     a.packed = w.packed;
@@ -1001,7 +1008,7 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.step_base = ls ? ls->step_base : nullptr;
     // a list step: the gated rebuild runs in this launch
     a.reb = ls && bin_gate ? 1 : 0;
-    a.n_reb_scatter = a.reb ? std::min(16, (c.n_part_tiles + 3) / 4) : 0;
+    a.n_reb_scatter = a.reb ? std::min(kRebBlocks, (c.n_part_tiles + 3) / 4) : 0;
     if (a.reb) {
         RebuildArgs &r = a.rb;
         r.sys = w.sys;

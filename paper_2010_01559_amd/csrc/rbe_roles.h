@@ -108,8 +108,8 @@ struct MidArgs {
     RebuildArgs rb;
 };
 
-// Few blocks, each striding over the 256-particle tiles: on the many steps
-// where nothing is binned the launch costs only their dispatch.  A thread
+// Up to 128 blocks, each striding over the 256-particle tiles: on the many
+// steps where nothing is binned the launch costs only their dispatch.  A thread
 // takes up to kRebBatch tiles at once: it loads all their records, then
 // issues all the counter atomics, then stores the cell ids and ranks, so
 // that the memory latencies of its particles overlap instead of adding up.
@@ -292,11 +292,13 @@ __device__ void mid_scan(const SysDev &S, int r, int32_t *count, int32_t *start)
 // then each adds one to bins_done; the scan block, which comes after them in
 // block order, waits for all of them, scans every system's counts and raises
 // `ready`; the scatter blocks, last in block order, wait for it and stride
-// over the 256-particle tiles, moving records into cell order.  The launch
-// has a few dozen 1024-thread blocks, all resident at once, and a block only
-// waits for blocks of lower index, so every wait ends; the waits are bounded
-// anyway.  A wait that reaches its bound gives up: it raises the timeout bit
-// of the error word and the poison flag, and its block skips its work.  The
+// over the 256-particle tiles, moving records into cell order.  A block only
+// waits for blocks of lower index, which are dispatched before it and do not
+// wait for it, so every wait ends (with one block per compute unit the last
+// scatter blocks of a large launch start when earlier blocks finish); the
+// waits are bounded anyway.  A wait that reaches its bound gives up: it
+// raises the timeout bit of the error word and the poison flag, and its
+// block skips its work.  The
 // force launch of that step then clears the cell counts (the scan that would
 // have cleared them did not run) and the next step's staging launch asks for
 // a rebuild; the cell pass of the failed step reads the previous cell starts,
@@ -335,12 +337,21 @@ __device__ bool block_wait(int32_t *p, int want, int limit, int32_t *flag, int32
     return s_ok != 0;
 }
 
-// Every wave of the block makes its stores visible to the agent (L2 write
-// back, no invalidation), then thread 0 may publish with a relaxed atomic.
-__device__ __forceinline__ void block_release()
+// Publishing a block's stores to the other blocks of the launch: every wave
+// waits until its stores have reached the L2 (a workgroup barrier alone does
+// not wait for them), then thread 0 alone writes the XCD's L2 back (an
+// agent-scope release fence); each such write-back walks the whole L2, so one
+// per block instead of one per wave.  Thread 0 then raises the block's flag.
+__device__ __forceinline__ void block_stores_done()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);   // the write-back has completed before the flag
+    }
 }
 
 // Scan block of a rebuild: waits for every binning block, turns the cell
@@ -357,7 +368,7 @@ __device__ void rebuild_scan(const RebuildArgs &a)
         *a.builds += 1;
         *a.poison = 0;
     }
-    block_release();
+    block_stores_done();
     if (threadIdx.x == 0) __hip_atomic_store(a.ready, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
