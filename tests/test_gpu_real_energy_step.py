@@ -45,10 +45,12 @@ def test_real_forces_positions_outside_box():
 
 
 @pytest.mark.parametrize("prec", [R.RBE_FP64, R.RBE_FP32])
-@pytest.mark.parametrize("density", [1.0, 3.0])
+@pytest.mark.parametrize("density", [0.6, 1.0, 3.0])
 def test_real_forces_dense(prec, density):
-    """Dense boxes: small bricks, and at density 3 a halo larger than the
-    kernel's LDS capacity, which is then read from global memory."""
+    """Dense boxes: about 24, 47 and 111 particles per cell at densities 0.6,
+    1 and 3.  A row segment of three cells longer than the scan's 64-slot
+    bitmask is walked directly: at 0.6 some rows take each path, at 1 and 3
+    nearly all are walked."""
     n = 3000
     rng = np.random.default_rng(int(density * 10))
     L = W.box_for_density(n, density)
