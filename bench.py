@@ -68,10 +68,17 @@ PEAK_HBM_GBS = 8000.0
 # source it was taken on (sha256 prefix); otherwise reported as null.
 # k_real_step: the list-pass launches of the profiled run (the rebuild step's
 # cell pass, which reads several times more, is left out, as the timed window
-# of the N = 1e5 run holds no rebuild).
+# of the N = 1e5 run holds no rebuild); the staging launches of steps after
+# the first of a call; the Fourier-only launches at N = 1e5.
 TRAFFIC = {
-    "real": {"src": "61ecf50de13ea5a1", "fetch_kib": 7840.3, "write_kib": 6428.9, "fetch_scale": 2.000,
+    "real": {"src": "9784da6cb86613b6", "fetch_kib": 8588.1, "write_kib": 6470.7, "fetch_scale": 2.000,
              "write_scale": 1.000},
+    "stage": {"src": "12d6a9858971abe2", "fetch_kib": 3192.8, "write_kib": 7235.3, "fetch_scale": 2.000,
+              "write_scale": 1.000},
+    "stage_fourier": {"src": "12d6a9858971abe2", "fetch_kib": 872.8, "write_kib": 400.0, "fetch_scale": 2.000,
+                      "write_scale": 1.000},
+    "kforce": {"src": "12d6a9858971abe2", "fetch_kib": 843.2, "write_kib": 1171.9, "fetch_scale": 2.000,
+               "write_scale": 1.000},
 }
 
 
