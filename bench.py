@@ -59,6 +59,7 @@ OPS = {
     "cutoff_pair": (22, 3),
 }
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (published)
+WARMUP_MS = 100.0          # device warm-up before the warmup steps (GPU clocks)
 PEAK_HBM_GBS = 8000.0
 
 # HBM traffic per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
@@ -610,6 +611,23 @@ def main():
     R.rbe_kspace_forces(ctx, P, Q, F)
     R.rbe_real_forces(ctx, P, Q, F, accumulate=True)
 
+    # ---- device warm-up: after the host-side set-up the GPU idles and its
+    # clocks drop; a short window timed from there reads about 7% slow
+    # (measured: 42.0 µs per step by events for 20 steps from idle, 39.3
+    # after 100 ms of work).  Fourier-only evaluations on the same context,
+    # into a scratch force buffer, run for WARMUP_MS before the warmup steps;
+    # the MD state is not touched. ----
+    F_scratch = torch.zeros_like(P)
+    torch.cuda.synchronize()
+    t_w, k_w = time.perf_counter(), 0
+    while time.perf_counter() - t_w < WARMUP_MS / 1e3:
+        for _ in range(20):
+            R.rbe_sample_k(ctx, 3 * 10 ** 6 + k_w)
+            R.rbe_kspace_forces(ctx, P, Q, F_scratch)
+            k_w += 1
+        torch.cuda.synchronize()
+    del F_scratch
+
     # ---- full MD steps (one rbe_step call advances all K steps) ----
     R.rbe_step(ctx, P, V, Q, F, 1, args.warmup)
     builds0 = R.rbe_list_builds(ctx)
@@ -697,6 +715,10 @@ def main():
                    "r_cut": s.r_cut, "lj": list(s.lj), "dt": s.dt,
                    "precision": "fp32 (exact split phases, fp64 reductions)", "tiles": tiles},
         "md_steps_per_s": 1e3 / ms_per_step,
+        "step_ms_events_wall": [round(step_ms, 6), round(1e3 * wall / args.steps, 6)],
+        "device_warmup": {"ms": WARMUP_MS, "work": f"{k_w} Fourier-only evaluations (sample + structure factor + "
+                                                    "force) on the same context into a scratch buffer, before the "
+                                                    "warmup steps"},
         "list_builds": {"timed_window": builds_window, "profiled_window": builds_prof, "steps": args.steps},
         "kspace_pairs_per_s": pairs * 1e3 / k_ms,
         "kspace_ms": k_ms,
