@@ -340,8 +340,9 @@ __device__ bool block_wait(int32_t *p, int want, int limit, int32_t *flag, int32
 // Publishing a block's stores to the other blocks of the launch: every wave
 // waits until its stores have reached the L2 (a workgroup barrier alone does
 // not wait for them), then thread 0 alone writes the XCD's L2 back (an
-// agent-scope release fence); each such write-back walks the whole L2, so one
-// per block instead of one per wave.  Thread 0 then raises the block's flag.
+// agent-scope release fence, which writes back every dirty line of that L2;
+// issued by every wave, these write-backs took 15-30 us per hand-off).
+// Thread 0 then raises the block's flag.
 __device__ __forceinline__ void block_stores_done()
 {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
