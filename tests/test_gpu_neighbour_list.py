@@ -198,3 +198,27 @@ def test_many_systems_rebuild_inside_the_totals_launch():
         assert pos_err(P1, p[:, off:off + s.n], s.L) <= 1e-5
         assert rel_l2(host(V1), v[:, off:off + s.n]) <= 1e-5
         off += s.n
+
+
+def test_rebuilds_with_the_full_block_count_keep_every_force():
+    """N = 2e5 (more 256-particle tiles than four per rebuild block, so the
+    rebuild runs its largest block count), a thin skin and a long time step:
+    several rebuilds triggered by motion in 20 steps; after them every
+    particle's force equals the FP64 oracle's at the final positions with the
+    last step's modes (Sec. 3.1, eq. 3.6; eq. 2.11; eq. 4.1)."""
+    s = W.scaling_system(200000, 100)
+    ctx = make_ctx(s, R.RBE_FP32, skin=0.1, dt=0.005)
+    P, Q, V, F = device_state(ctx, s)
+    initial_force(ctx, P, Q, F)
+    nsteps = 20
+    R.rbe_step(ctx, P, V, Q, F, 1, nsteps)
+    builds = R.rbe_list_builds(ctx)
+    print(f"list builds in {nsteps} steps: {builds}", flush=True)
+    assert builds >= 3, builds
+    f = host(F)
+    assert np.isfinite(f).all()
+    pos, q = host(P).astype(np.float64), host(Q).astype(np.float64)
+    modes, _ = O.sample_modes(s.alpha, s.L, s.p, s.seed, nsteps)
+    fo = O.kspace_force(pos, q, s.L, modes, O.rbe_weights(s.alpha, s.L, s.p), s.coulomb)
+    fo += O.real_force(pos, q, s.L, s.alpha, s.r_cut, s.coulomb, s.lj, cells=True)[0]
+    assert rel_l2(f, fo) <= 1e-5
