@@ -356,14 +356,15 @@ __device__ __forceinline__ void row_scan(const Rec &pa, int self, int cx, int yy
         const int b0 = rs.b0[s], b1 = rs.b1[s];
         uint64_t m = 0;
         if (b1 - b0 <= 64) {
+            // two candidates per round, both loaded and tested without
+            // branches; their two bits enter the mask with one shift
             for (int b = b0; b < b1; b += 2) {
                 const int b2 = b + 1 < b1 ? b + 1 : b;
                 const Rec p0 = gs[b];
                 const Rec p1 = gs[b2];
-                const bool h0 = b != self && near_test(pa, p0, geo);
-                const bool h1 = b2 != b && b2 != self && near_test(pa, p1, geo);
-                m |= (uint64_t)(h0 ? 1u : 0u) << (b - b0);
-                m |= (uint64_t)(h1 ? 1u : 0u) << (b2 - b0);
+                const uint32_t h0 = (uint32_t)near_test(pa, p0, geo) & (uint32_t)(b != self);
+                const uint32_t h1 = (uint32_t)near_test(pa, p1, geo) & (uint32_t)(b2 != b) & (uint32_t)(b2 != self);
+                m |= (uint64_t)(h0 | (h1 << 1)) << (b - b0);
             }
         } else {
             rs.walk = true;
