@@ -842,7 +842,9 @@ rbe_status rbe_batch_create(const rbe_params *params, int32_t R, void *stream, r
     ALLOC(w.rank, sizeof(int32_t) * ntot);
     ALLOC(w.sorted_idx, sizeof(int32_t) * ntot);
     ALLOC(w.packed, pack_sz * ntot);
-    ALLOC(w.sorted, pack_sz * ntot);
+    // one padding record after the last slot: the cell pass's row scan reads
+    // candidates two at a time and may read one past a segment's end
+    ALLOC(w.sorted, pack_sz * (ntot + 1));
     ALLOC(w.modes_alt, sizeof(int32_t) * 3 * c->mcap);
     ALLOC(w.mode_w_alt, sizeof(double) * c->mcap);
     ALLOC(w.energy_part, sizeof(double) * 8 * rtiles.size());

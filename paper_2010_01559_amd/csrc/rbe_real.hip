@@ -357,15 +357,18 @@ __device__ __forceinline__ void row_scan(const Rec &pa, int self, int cx, int yy
         uint64_t m = 0;
         if (b1 - b0 <= 64) {
             // two candidates per round, both loaded and tested without
-            // branches; their two bits enter the mask with one shift
+            // branches; their two bits enter the mask with one shift.  The
+            // second record is read even one past the segment (the record
+            // array ends with a padding record) and its bit dropped there;
+            // the particle itself is dropped once, after the loop
             for (int b = b0; b < b1; b += 2) {
-                const int b2 = b + 1 < b1 ? b + 1 : b;
                 const Rec p0 = gs[b];
-                const Rec p1 = gs[b2];
-                const uint32_t h0 = (uint32_t)near_test(pa, p0, geo) & (uint32_t)(b != self);
-                const uint32_t h1 = (uint32_t)near_test(pa, p1, geo) & (uint32_t)(b2 != b) & (uint32_t)(b2 != self);
+                const Rec p1 = gs[b + 1];
+                const uint32_t h0 = (uint32_t)near_test(pa, p0, geo);
+                const uint32_t h1 = (uint32_t)near_test(pa, p1, geo) & (uint32_t)(b + 1 < b1);
                 m |= (uint64_t)(h0 | (h1 << 1)) << (b - b0);
             }
+            if (self >= b0 && self < b1) m &= ~(1ull << (self - b0));
         } else {
             rs.walk = true;
         }
