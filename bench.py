@@ -72,7 +72,7 @@ PEAK_HBM_GBS = 8000.0
 # of the N = 1e5 run holds no rebuild); the staging launches of steps after
 # the first of a call; the Fourier-only launches at N = 1e5.
 TRAFFIC = {
-    "real": {"src": "18af5d6950542b13", "fetch_kib": 8579.1, "write_kib": 6518.9, "fetch_scale": 2.000,
+    "real": {"src": "3972852752c25e0f", "fetch_kib": 8590.8, "write_kib": 6452.8, "fetch_scale": 2.000,
              "write_scale": 1.000},
     "stage": {"src": "01402b11df11ea8c", "fetch_kib": 3192.8, "write_kib": 7239.8, "fetch_scale": 2.000,
               "write_scale": 1.000},
