@@ -424,8 +424,8 @@ hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step
 
 // ---------------------------------------------------------------------------
 // k_mid: independent jobs in one launch (roles in rbe_roles.h), in block
-// order: final structure factors (one wave per (system, mode) adds the tile
-// partials in a fixed order and fills the per-mode force constants); gated
+// order: final structure factors (four waves per (system, mode) add the
+// tile partials in a fixed order and fill the per-mode force constants); gated
 // binning of a neighbour-list rebuild; the next step's modes (one block per
 // system); then either the gated rebuild's scan and scatter blocks or, for
 // cell-list force calls, one cell-scan block per system.
@@ -437,8 +437,7 @@ __global__ __launch_bounds__(1024) void k_mid(MidArgs<KM> a)
     extern __shared__ double mid_tab[];
     if (!LEAN && blockIdx.x == 0 && threadIdx.x == 0 && a.clear_flag) *a.clear_flag = 0;
     if ((int)blockIdx.x < a.n_final_blocks) {
-        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        mid_final<KM>(a, blockIdx.x * 16 + wave);
+        mid_final<KM>(a, blockIdx.x);
         return;
     }
     if constexpr (LEAN) return;
@@ -977,7 +976,7 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.sys = w.sys;
     a.R = c.R;
     a.max_p = c.max_p;
-    a.n_final_blocks = do_final ? (c.R * c.max_p + 15) / 16 : 0;
+    a.n_final_blocks = do_final ? (c.R * c.max_p + kFinalModes - 1) / kFinalModes : 0;
     a.single_p = c.R == 1 ? c.max_p : 0;
     a.single_nt = c.n_rho_tiles;
     a.partial = w.partial;

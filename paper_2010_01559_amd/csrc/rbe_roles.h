@@ -162,43 +162,70 @@ __device__ void mid_bin(const MidArgs<KM> &a, int b)
 }
 
 
+// Structure-factor totals of four modes per block, four waves per mode: the
+// wave of quarter q sums the tile partials of its mode in runs of 64 tiles
+// q, q + 4, q + 8, ... (a lane its tile of each run, in order), the waves
+// reduce across lanes, and the mode's first wave adds the four quarter sums
+// in order and writes the force constants.  The partials of one mode sit a
+// tile row apart (one cache line per tile), so spreading a mode over four
+// waves quarters the chain of dependent load batches of a long tile list.
+constexpr int kFinalWaves = 4;                          // waves per mode
+constexpr int kFinalModes = 16 / kFinalWaves;           // modes per 1024-thread block
+
 template <typename KM>
-__device__ void mid_final(const MidArgs<KM> &a, int gm)
+__device__ void mid_final(const MidArgs<KM> &a, int blk)
 {
+    __shared__ double2 q_sum[16];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gm = blk * kFinalModes + wave / kFinalWaves;
+    const int q = wave % kFinalWaves;
     const int r = gm / a.max_p, l = gm % a.max_p;
-    if (r >= a.R) return;
     // a single system's mode and tile counts come with the launch, so that
     // the partial loads do not wait for the system constants and offsets
-    const int P = a.single_p ? a.single_p : a.sys[r].p;
-    if (l >= P) return;
-    const int nt = a.single_p ? a.single_nt : a.part_off[a.R + r];
-    const double *base = a.partial + (a.single_p ? 0 : 2 * (int64_t)a.part_off[r]);
-    const int lane = threadIdx.x & 63;
+    bool ok = r < a.R;
+    int P = 0, nt = 0;
+    const double *base = a.partial;
+    if (ok) {
+        P = a.single_p ? a.single_p : a.sys[r].p;
+        ok = l < P;
+        nt = a.single_p ? a.single_nt : a.part_off[a.R + r];
+        base = a.partial + (a.single_p ? 0 : 2 * (int64_t)a.part_off[r]);
+    }
     double c = 0.0, s = 0.0;
-    // lane sums tiles lane, lane + 64, ... in order; eight loads are issued
-    // before they are added, so their latencies overlap
-    for (int t0 = lane; t0 < nt; t0 += 8 * 64) {
-        double2 v[8];
+    if (ok) {
+        // eight loads are issued before they are added, so their latencies overlap
+        constexpr int STRIDE = 64 * kFinalWaves;
+        for (int t0 = 64 * q + lane; t0 < nt; t0 += 8 * STRIDE) {
+            double2 v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = t0 + 64 * u;
-            if (t < nt) v[u] = *reinterpret_cast<const double2 *>(base + 2 * ((int64_t)t * P + l));
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + STRIDE * u;
+                if (t < nt) v[u] = *reinterpret_cast<const double2 *>(base + 2 * ((int64_t)t * P + l));
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (t0 + STRIDE * u < nt) {
+                    c += v[u].x;
+                    s += v[u].y;
+                }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (t0 + 64 * u < nt) {
-                c += v[u].x;
-                s += v[u].y;
-            }
+        for (int off = 32; off > 0; off >>= 1) {
+            c += __shfl_down(c, off, 64);
+            s += __shfl_down(s, off, 64);
+        }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        c += __shfl_down(c, off, 64);
-        s += __shfl_down(s, off, 64);
-    }
-    if (lane == 0) {
+    if (lane == 0) q_sum[wave] = make_double2(c, s);
+    __syncthreads();
+    if (ok && q == 0 && lane == 0) {
+        double cc = 0.0, ss = 0.0;
+        for (int k = 0; k < kFinalWaves; ++k) {
+            cc += q_sum[wave + k].x;
+            ss += q_sum[wave + k].y;
+        }
         const SysDev &S = a.sys[r];
-        make_kmode<KM>(S, a.modes, a.mode_w, a.mcap, S.moff + l, c, s, a.rho, a.km);
+        make_kmode<KM>(S, a.modes, a.mode_w, a.mcap, S.moff + l, cc, ss, a.rho, a.km);
     }
 }
 
