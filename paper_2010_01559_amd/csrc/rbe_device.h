@@ -396,11 +396,21 @@ template <typename T>
 __device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i, int64_t ntot, T *pos, T *vel,
                                               const T *F, uint64_t step, bool kick, double x[3])
 {
+    // all nine loads first, before the branches on the system constants (so
+    // they do not wait for them), and since the stores of one component
+    // cannot be proven apart from the loads of the next
+    T p0[3], v0[3], f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        p0[d] = pos[d * ntot + i];
+        v0[d] = vel[d * ntot + i];
+        f[d] = F[d * ntot + i];
+    }
     if (il < S.n_fixed) {
         // an immobile particle (the colloid of Sec. 4.2): no kick, drift,
         // noise or collision; its stored state is left as it is
 #pragma unroll
-        for (int d = 0; d < 3; ++d) x[d] = (double)pos[d * ntot + i];
+        for (int d = 0; d < 3; ++d) x[d] = (double)p0[d];
         return;
     }
     const bool hit = S.integrator == RBE_LANGEVIN_BAOAB ? false : andersen_hit(S, il, step);
@@ -410,15 +420,6 @@ __device__ __forceinline__ void integrate_one(const SysDev &S, int il, int64_t i
     if (S.anneal > 0.0 && S.integrator == RBE_LANGEVIN_BAOAB) {
         c1 = exp(-S.gamma * dt / S.mass);
         c2 = sqrt((1.0 - c1 * c1) * S.kT / S.mass);
-    }
-    // all nine loads first: the stores of one component cannot be proven
-    // apart from the loads of the next
-    T p0[3], v0[3], f[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        p0[d] = pos[d * ntot + i];
-        v0[d] = vel[d * ntot + i];
-        f[d] = F[d * ntot + i];
     }
     // the three normals come from one draw outside the component loop, so
     // that the loop unrolls and its arrays stay in registers

@@ -148,6 +148,7 @@ struct StageArgs {
     int kick;   // deferred closing half kick of the previous step
     int chunk;
     int single_n;          // single-system context (SINGLE launches): its particle count
+    int single_p;          // and its mode count
     int tab_max;           // LDS doubles reserved for the table
     // neighbour-list mode of a time step
     int list_mode;
@@ -261,7 +262,16 @@ __global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T>
     extern __shared__ __align__(16) unsigned char smem[];
     const int bx = (int)blockIdx.x;
     const Tile t = SINGLE ? Tile{0, bx * a.chunk, min(a.chunk, a.single_n - bx * a.chunk), bx} : a.tiles[bx];
-    const SysDev S = a.sys[SINGLE ? 0 : t.sys];
+    SysDev S = a.sys[SINGLE ? 0 : t.sys];
+    if constexpr (SINGLE) {
+        // the single system's offsets are 0, its mode count comes with the
+        // launch, and a list step implies that it uses the list: no particle,
+        // list or mode load waits for the system constants
+        S.off = 0;
+        S.moff = 0;
+        S.p = a.single_p;
+        if (a.list_mode) S.use_list = 1;
+    }
     using RR = typename RhoRec<T>::type;
     RR *sp = reinterpret_cast<RR *>(smem);
     double2 *red = reinterpret_cast<double2 *>(smem + sizeof(RR) * (a.chunk + kRhoUnroll * kRhoGroupsMax));
@@ -350,7 +360,7 @@ __global__ __launch_bounds__(BS, VAR == 2 ? 1 : 8) void k_stage_rho(StageArgs<T>
         sp[j] = z;
     }
     const double *tabp = a.table_lds ? tab : a.cdf + S.cdf_off;
-    double *prow = a.partial + 2 * ((int64_t)a.part_off[t.sys] + (int64_t)t.aux * P);
+    double *prow = a.partial + 2 * ((SINGLE ? 0 : (int64_t)a.part_off[t.sys]) + (int64_t)t.aux * P);
     for (int m0 = mb; m0 < me; m0 += Pt) {
         // modes of this tile into LDS: drawn here or read from the mode arrays
         if (tid < Pt && m0 + tid < me) {
@@ -503,6 +513,7 @@ struct ForceArgs {
     // fpart[y][3][ntot] and k_fsum finishes the particles
     T *fpart;
     int single_n;   // single-system context (SINGLE launches): its particle count
+    int single_p;   // and its mode count
 };
 
 template <typename T, typename KM, int SPLIT, bool SINGLE>
@@ -521,7 +532,14 @@ __global__ __launch_bounds__(256) void k_kforce(ForceArgs<T, KM> a)
         // SINGLE: the host's 64-particle tile of a single system, formed here
         const Tile t = SINGLE ? Tile{0, 64 * ti, min(64, a.single_n - 64 * ti), 0} : a.tiles[ti];
         sysi = t.sys;
-        const SysDev S = a.sys[SINGLE ? 0 : t.sys];
+        SysDev S = a.sys[SINGLE ? 0 : t.sys];
+        if constexpr (SINGLE) {
+            // offsets 0 and the mode count from the launch: the position and
+            // mode-constant loads do not wait for the system constants
+            S.off = 0;
+            S.moff = 0;
+            S.p = a.single_p;
+        }
         double s3[3] = {0.0, 0.0, 0.0};
         if (lane < t.count) {
             i = S.off + t.start + lane;
@@ -946,6 +964,7 @@ static hipError_t stage_dispatch(const LaunchCfg &c, const Workspace &w, const S
     a.table_lds = table_lds;
     a.tab_max = tab_max;
     a.single_n = c.R == 1 ? (int)c.ntot : 0;
+    a.single_p = c.R == 1 ? c.max_p : 0;
     dim3 g(c.n_rho_tiles, rq.mode_split > 1 ? rq.mode_split : 1);
     const int var = (rq.integrate || rq.bin || rq.list) ? 2 : (rq.sample ? 1 : 0);
     if (c.R == 1)
@@ -1097,6 +1116,7 @@ static hipError_t kforce_dispatch(const LaunchCfg &c, const Workspace &w, const 
     const int n = c.n_force_tiles;
     const int ys = mode_split > 1 && w.fpart ? mode_split : 1;
     a.single_n = c.R == 1 ? (int)c.ntot : 0;
+    a.single_p = c.R == 1 ? c.max_p : 0;
     if (c.R == 1)
         kforce_launch<T, KM, true>(c.force_split, n, ys, c.stream, a);
     else

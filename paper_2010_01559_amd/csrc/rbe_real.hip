@@ -431,6 +431,7 @@ struct ListArgs {
     int32_t *nbr;            // [kmax][Ntot] partner slots, column k of slot s at k * Ntot + s
     int32_t *nnb;
     int kmax;
+    int single_n, single_p;  // single-system context (SINGLE launches): its particle and mode counts
 };
 
 // Store (or add) the real-space force of particle i and apply the optional
@@ -827,24 +828,42 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
 // Force pass of one time step: the Fourier force plus the real-space force,
 // on the cell list with list build when the step's rebuild flag is set, else
 // on the list; then the closing half kick on the last step of a call.  Tiles
-// are taken in XCD order (xcd_tile).
-template <typename T, int LPP, bool DIAM>
+// are taken in XCD order (xcd_tile).  SINGLE (a single-system context, which
+// has no all-pairs tiles when it runs list steps) forms the tile from its
+// index as the host builds it, and takes the system's particle and mode
+// offsets (both 0) and its mode count from the launch, so that the record and
+// mode-constant loads do not wait for the tile and the system constants.
+template <typename T, int LPP, bool DIAM, bool SINGLE>
 __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
 {
     __shared__ T s4[4][FT_MAX][3];
+    // both flags are read before anything is stored, so that neither read
+    // waits for the other
+    const int poison = *la.ls.poison;
+    const int rebuild = *la.ls.rebuild;
     // no launch of this kernel reads the step number: advance the replay's
     // base for the next steps
     if (la.ls.step_bump && blockIdx.x == 0 && threadIdx.x == 0) *la.ls.step_bump += la.ls.bump;
-    if (*la.ls.poison) {
+    if (poison) {
         // this step's rebuild gave up before its scan cleared the cell counts
         for (int k = blockIdx.x * RL_BS + threadIdx.x; k < la.ncell_tot; k += gridDim.x * RL_BS) la.count[k] = 0;
     }
-    const int rebuild = *la.ls.rebuild;
     const int nb = rebuild ? la.n_rows : la.n_list;
     if ((int)blockIdx.x >= nb) return;
     const int ti = xcd_tile((int)blockIdx.x, nb);
-    const Tile t = rebuild ? a.tiles[ti] : la.list_tiles[ti];
-    const SysDev S = a.sys[t.sys];
+    Tile t;
+    if constexpr (SINGLE) {
+        const int per = rebuild ? RL_PPB : 256 / LPP;
+        t = Tile{0, ti * per, min(per, la.single_n - ti * per), rebuild ? 0 : 2};
+    } else {
+        t = rebuild ? a.tiles[ti] : la.list_tiles[ti];
+    }
+    SysDev S = a.sys[t.sys];
+    if constexpr (SINGLE) {
+        S.off = 0;
+        S.moff = 0;
+        S.p = la.single_p;
+    }
     const bool allpairs = t.aux == 1;
     fourier_tile<T>(a, S, allpairs ? a.packed : a.sorted, S.off + t.start, t.count, s4);
     __syncthreads();
@@ -1077,10 +1096,17 @@ template <typename T, int LPP>
 static void real_step_launch(const LaunchCfg &c, const RealArgs<T> &a, const ListArgs &la)
 {
     const int nb = la.n_rows > la.n_list ? la.n_rows : la.n_list;
-    if (a.diam)
-        launch_k(k_real_step<T, LPP, true>, nb, RL_BS, 0, c.stream, a, la);
-    else
-        launch_k(k_real_step<T, LPP, false>, nb, RL_BS, 0, c.stream, a, la);
+    if (c.R == 1) {
+        if (a.diam)
+            launch_k(k_real_step<T, LPP, true, true>, nb, RL_BS, 0, c.stream, a, la);
+        else
+            launch_k(k_real_step<T, LPP, false, true>, nb, RL_BS, 0, c.stream, a, la);
+    } else {
+        if (a.diam)
+            launch_k(k_real_step<T, LPP, true, false>, nb, RL_BS, 0, c.stream, a, la);
+        else
+            launch_k(k_real_step<T, LPP, false, false>, nb, RL_BS, 0, c.stream, a, la);
+    }
 }
 
 template <typename T>
@@ -1115,6 +1141,8 @@ hipError_t launch_real_step(const LaunchCfg &c, const Workspace &w, const ListSt
     la.kmax = c.kmax;
     la.count = w.cell_count;
     la.ncell_tot = c.ncell_tot;
+    la.single_n = c.R == 1 ? (int)c.ntot : 0;
+    la.single_p = c.R == 1 ? c.max_p : 0;
     if (c.prec == RBE_FP64)
         real_step_dispatch<double>(c, real_args<double>(c, w, force, 0, vel_kick, nullptr, kick_step), la);
     else
