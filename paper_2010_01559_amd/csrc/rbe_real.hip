@@ -752,10 +752,50 @@ __global__ __launch_bounds__(RL_BS) void k_real_rows(RealArgs<T> a)
     if constexpr (ENERGY) energy_block(ev, a.epart + 8 * blockIdx.x);
 }
 
-// List tile: LPP lanes per cell-sorted slot.
+// List tile: LPP lanes per cell-sorted slot, U partners per lane and round.
+constexpr int kListU = 4;
+
+// What the list pass of a tile particle loads before its partners: its
+// record, original index (where its force goes) and list length, and the
+// raw partner slots of its first round.  None depends on the Fourier part,
+// so the force launch issues these loads before it and their latency
+// overlaps the Fourier arithmetic.  The first round's slots are read whatever
+// the length (its columns, below 4 LPP <= 32, lie inside the list's kmax
+// columns; a clamp keeps them there) and replaced by the particle's own slot
+// past the length before any is used.
+template <typename T>
+struct ListHead {
+    typename RBT<T>::Rec pa;
+    int64_t iorig;
+    int n, slot;
+    int b[kListU];
+};
+
+template <typename T, int LPP>
+__device__ __forceinline__ void list_head(const RealArgs<T> &a, const ListArgs &la, const Tile &t, const SysDev &S,
+                                          ListHead<T> &h)
+{
+    using Rec = typename RBT<T>::Rec;
+    const int tid = threadIdx.x;
+    const int k = tid / LPP, sub = tid % LPP;
+    h.n = 0;
+    h.slot = 0;
+    h.iorig = 0;
+    h.pa = Rec{};
+    if (k < t.count) {
+        h.slot = S.off + t.start + k;
+        h.pa = reinterpret_cast<const Rec *>(a.sorted)[h.slot];
+        h.iorig = a.sorted_idx[h.slot];
+        h.n = la.nnb[h.slot];
+        const int32_t *nb = la.nbr + h.slot;
+#pragma unroll
+        for (int u = 0; u < kListU; ++u) h.b[u] = nb[(int64_t)min(sub + u * LPP, la.kmax - 1) * a.ntot];
+    }
+}
+
 template <typename T, int LPP, bool DIAM>
 __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &la, const Tile &t, const SysDev &S,
-                                          Four<T> s4 = nullptr)
+                                          const ListHead<T> &h, Four<T> s4 = nullptr)
 {
     using Rec = typename RBT<T>::Rec;
     const Geo geo = make_geo<T>(S);
@@ -764,34 +804,30 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
     const int k = tid / LPP, sub = tid % LPP;
     const bool act = k < t.count;
     double fx = 0, fy = 0, fz = 0;
-    int slot = 0;
-    T qi = 0;
-    // the particle's original index (where its force goes) is loaded with
-    // its record, so that the store after the partner loop does not wait
-    int64_t iorig = 0;
+    const Rec pa = h.pa;
+    const int slot = h.slot, n = h.n;
+    const T qi = (T)pa.q;
     if (act) {
-        slot = S.off + t.start + k;
         const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
-        const Rec pa = gs[slot];
-        iorig = a.sorted_idx[slot];
-        qi = (T)pa.q;
-        const double da = DIAM && S.diam_on ? a.diam[iorig] : 0.0;
-        const int n = la.nnb[slot];
+        const double da = DIAM && S.diam_on ? a.diam[h.iorig] : 0.0;
         const int32_t *nb = la.nbr + slot;
         PairE e{0, 0};
-        // four partners per round: their indices, then their records, are
-        // loaded together so that the gathers overlap
-        constexpr int U = 4;
-        for (int j = sub; j < n; j += U * LPP) {
-            int b[U];
+        constexpr int U = kListU;
+        int b[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int jj = j + u * LPP;
-                b[u] = jj < n ? nb[(int64_t)jj * a.ntot] : slot;
-            }
+        for (int u = 0; u < U; ++u) b[u] = sub + u * LPP < n ? h.b[u] : slot;
+        for (int j = sub; j < n; j += U * LPP) {
+            // this round's partner records, then the next round's partner
+            // slots, so that those loads overlap this round's pairs
             Rec pb[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) pb[u] = gs[b[u]];
+            int bn[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jj = j + U * LPP + u * LPP;
+                bn[u] = jj < n ? nb[(int64_t)jj * a.ntot] : slot;
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (j + u * LPP < n) {
@@ -806,6 +842,8 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
                     fz += qterm(ph * dz);
                 }
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u) b[u] = bn[u];
         }
     }
     if constexpr (sizeof(T) == 4) range_check(fx, fy, fz, a.flag);
@@ -821,7 +859,7 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
         fy *= qscale<T>();
         fz *= qscale<T>();
         add_fourier<T>(s4, k, qi, fx, fy, fz);
-        finish_particle<T, false>(a, S, iorig, fx, fy, fz, nullptr);
+        finish_particle<T, false>(a, S, h.iorig, fx, fy, fz, nullptr);
     }
 }
 
@@ -865,14 +903,20 @@ __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
         S.p = la.single_p;
     }
     const bool allpairs = t.aux == 1;
+    if (!allpairs && !rebuild) {
+        ListHead<T> h;
+        list_head<T, LPP>(a, la, t, S, h);
+        fourier_tile<T>(a, S, a.sorted, S.off + t.start, t.count, s4);
+        __syncthreads();
+        list_body<T, LPP, DIAM>(a, la, t, S, h, s4);
+        return;
+    }
     fourier_tile<T>(a, S, allpairs ? a.packed : a.sorted, S.off + t.start, t.count, s4);
     __syncthreads();
     if (allpairs)
         allpairs_body<T, false, DIAM>(a, t, S, nullptr, s4);
-    else if (rebuild)
-        rows_body<T, false, true, DIAM>(a, &la, t, S, nullptr, s4);
     else
-        list_body<T, LPP, DIAM>(a, la, t, S, s4);
+        rows_body<T, false, true, DIAM>(a, &la, t, S, nullptr, s4);
 }
 
 // Stand-alone scatter into cell order (force and energy calls; a time step
