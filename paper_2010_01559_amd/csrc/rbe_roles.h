@@ -16,17 +16,40 @@
 
 namespace rbe {
 
-// Structure factor totals and force constants of mode o:
+// What the force constants of one mode take besides its structure factor:
+// the mode, its weight and the system's constants, and its index o in the
+// mode arrays.  The totals load these before the partial sums, so that their
+// latency overlaps the sums.
+struct KModeIn {
+    double mx, my, mz, w, coulomb, L;
+    int o;
+};
+
+__device__ __forceinline__ KModeIn kmode_in(const SysDev &S, int moff, int l, const int32_t *modes,
+                                            const double *mode_w, int mcap)
+{
+    KModeIn in;
+    in.o = moff + l;
+    in.mx = modes[in.o];
+    in.my = modes[mcap + in.o];
+    in.mz = modes[2 * mcap + in.o];
+    in.w = mode_w[in.o];
+    in.coulomb = S.coulomb;
+    in.L = S.L;
+    return in;
+}
+
+// Structure factor totals and force constants of mode in.o:
 //   a_l = coulomb w_l 2 m_l / (L^2 |m_l|^2)   (eq. 3.6 with k = 2 pi m / L).
 template <typename KM>
-__device__ __forceinline__ void make_kmode(const SysDev &S, const int32_t *modes, const double *mode_w, int mcap,
-                                           int o, double c, double s, double *rho, KM *km)
+__device__ __forceinline__ void make_kmode(const KModeIn &in, double c, double s, double *rho, KM *km)
 {
+    const int o = in.o;
     rho[2 * o] = c;
     rho[2 * o + 1] = s;
-    const double mx = modes[o], my = modes[mcap + o], mz = modes[2 * mcap + o];
+    const double mx = in.mx, my = in.my, mz = in.mz;
     const double m2 = mx * mx + my * my + mz * mz;
-    const double f = S.coulomb * mode_w[o] * 2.0 / (S.L * S.L * m2);
+    const double f = in.coulomb * in.w * 2.0 / (in.L * in.L * m2);
     KM k;
     k.m[0] = mx;
     k.m[1] = my;
@@ -192,6 +215,12 @@ __device__ void mid_final(const MidArgs<KM> &a, int blk)
         nt = a.single_p ? a.single_nt : a.part_off[a.R + r];
         base = a.partial + (a.single_p ? 0 : 2 * (int64_t)a.part_off[r]);
     }
+    // the inputs of the force constants, loaded by the thread that forms them
+    KModeIn in{};
+    if (ok && q == 0 && lane == 0) {
+        const SysDev &S = a.sys[r];
+        in = kmode_in(S, a.single_p ? 0 : S.moff, l, a.modes, a.mode_w, a.mcap);
+    }
     double c = 0.0, s = 0.0;
     if (ok) {
         // eight loads are issued before they are added, so their latencies overlap
@@ -224,8 +253,7 @@ __device__ void mid_final(const MidArgs<KM> &a, int blk)
             cc += q_sum[wave + k].x;
             ss += q_sum[wave + k].y;
         }
-        const SysDev &S = a.sys[r];
-        make_kmode<KM>(S, a.modes, a.mode_w, a.mcap, S.moff + l, cc, ss, a.rho, a.km);
+        make_kmode<KM>(in, cc, ss, a.rho, a.km);
     }
 }
 
