@@ -793,21 +793,23 @@ __device__ __forceinline__ void list_head(const RealArgs<T> &a, const ListArgs &
     }
 }
 
+// Real-space force of tile particle k from its list, summed over the
+// particle's LPP lanes (each of them holds the sum).
 template <typename T, int LPP, bool DIAM>
-__device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &la, const Tile &t, const SysDev &S,
-                                          const ListHead<T> &h, Four<T> s4 = nullptr)
+__device__ __forceinline__ void list_pairs(const RealArgs<T> &a, const ListArgs &la, const Tile &t, const SysDev &S,
+                                           const ListHead<T> &h, double &fx, double &fy, double &fz)
 {
     using Rec = typename RBT<T>::Rec;
     const Geo geo = make_geo<T>(S);
     const auto pc = pair_consts<T>(S);
     const int tid = threadIdx.x;
     const int k = tid / LPP, sub = tid % LPP;
-    const bool act = k < t.count;
-    double fx = 0, fy = 0, fz = 0;
+    fx = 0;
+    fy = 0;
+    fz = 0;
     const Rec pa = h.pa;
     const int slot = h.slot, n = h.n;
-    const T qi = (T)pa.q;
-    if (act) {
+    if (k < t.count) {
         const Rec *gs = reinterpret_cast<const Rec *>(a.sorted);
         const double da = DIAM && S.diam_on ? a.diam[h.iorig] : 0.0;
         const int32_t *nb = la.nbr + slot;
@@ -853,20 +855,39 @@ __device__ __forceinline__ void list_body(const RealArgs<T> &a, const ListArgs &
         fy += __shfl_xor(fy, o, 64);
         fz += __shfl_xor(fz, o, 64);
     }
-    if (act && sub == 0) {
+}
+
+// Last step of a list particle (its first lane): scale of the real-space sum,
+// the Fourier force from the tile's quarter sums, store.
+template <typename T, int LPP>
+__device__ __forceinline__ void list_finish(const RealArgs<T> &a, const Tile &t, const SysDev &S, const ListHead<T> &h,
+                                            Four<T> s4, double fx, double fy, double fz)
+{
+    const int tid = threadIdx.x;
+    const int k = tid / LPP, sub = tid % LPP;
+    if (k < t.count && sub == 0) {
         if constexpr (sizeof(T) == 4) range_check(fx, fy, fz, a.flag);
         fx *= qscale<T>();
         fy *= qscale<T>();
         fz *= qscale<T>();
-        add_fourier<T>(s4, k, qi, fx, fy, fz);
+        add_fourier<T>(s4, k, (T)h.pa.q, fx, fy, fz);
         finish_particle<T, false>(a, S, h.iorig, fx, fy, fz, nullptr);
     }
 }
 
+// Slot of the calling wave on its SIMD: bits 3:0 (WAVE_ID) of the HW_ID
+// hardware register, read with s_getreg_b32 (operand: (size - 1) << 11 |
+// offset << 6 | register, HW_ID being register 4).  It only orders
+// independent work; no result depends on it.
+__device__ __forceinline__ int wave_slot() { return __builtin_amdgcn_s_getreg((4 - 1) << 11 | 0 << 6 | 4); }
+
 // Force pass of one time step: the Fourier force plus the real-space force,
 // on the cell list with list build when the step's rebuild flag is set, else
 // on the list; then the closing half kick on the last step of a call.  Tiles
-// are taken in XCD order (xcd_tile).  SINGLE (a single-system context, which
+// are taken in XCD order (xcd_tile).  On the list, a particle's real-space sum
+// stays in registers and its Fourier force in the tile's LDS quarter sums
+// until the finish, which adds them in a fixed order, so the order of the
+// two phases does not change any result.  SINGLE (a single-system context, which
 // has no all-pairs tiles when it runs list steps) forms the tile from its
 // index as the host builds it, and takes the system's particle and mode
 // offsets (both 0) and its mode count from the launch, so that the record and
@@ -906,9 +927,20 @@ __global__ __launch_bounds__(RL_BS) void k_real_step(RealArgs<T> a, ListArgs la)
     if (!allpairs && !rebuild) {
         ListHead<T> h;
         list_head<T, LPP>(a, la, t, S, h);
-        fourier_tile<T>(a, S, a.sorted, S.off + t.start, t.count, s4);
+        double fx, fy, fz;
+        // the two phases are independent until the finish: waves in odd
+        // slots of their SIMD take the list pairs first, the others the
+        // Fourier terms, so that the waves sharing a SIMD do not all wait on
+        // loads at the same time
+        if (wave_slot() & 1) {
+            list_pairs<T, LPP, DIAM>(a, la, t, S, h, fx, fy, fz);
+            fourier_tile<T>(a, S, a.sorted, S.off + t.start, t.count, s4);
+        } else {
+            fourier_tile<T>(a, S, a.sorted, S.off + t.start, t.count, s4);
+            list_pairs<T, LPP, DIAM>(a, la, t, S, h, fx, fy, fz);
+        }
         __syncthreads();
-        list_body<T, LPP, DIAM>(a, la, t, S, h, s4);
+        list_finish<T, LPP>(a, t, S, h, s4, fx, fy, fz);
         return;
     }
     fourier_tile<T>(a, S, allpairs ? a.packed : a.sorted, S.off + t.start, t.count, s4);
