@@ -589,6 +589,8 @@ rbe_status upload_rho_tiles(rbe_ctx *c)
     std::vector<int32_t> poff;
     build_rho_tiles(c, tiles, poff, c->cfg.rho_chunk, c->mcap);
     c->cfg.n_rho_tiles = (int)tiles.size();
+    c->cfg.max_sys_rho_tiles = 0;
+    for (int nt : c->ntiles_rho) c->cfg.max_sys_rho_tiles = std::max(c->cfg.max_sys_rho_tiles, nt);
     HIPCHK(c, hipMemcpy(c->w.rho_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->w.partial_off, poff.data(), poff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     return RBE_OK;
@@ -1902,6 +1904,7 @@ rbe_status rbe_kspace_forces_noalloc(const rbe_params *params, const int32_t *mo
     c.rho_block = 1024;
     c.force_split = default_force_split(p.n);
     c.n_rho_tiles = (p.n + c.rho_chunk - 1) / c.rho_chunk;
+    c.max_sys_rho_tiles = c.n_rho_tiles;
     c.n_force_tiles = (p.n + 63) / 64;
     if (c.n_rho_tiles > kStaticMaxRhoTiles) {
         null_errf("internal: %d structure-factor tiles exceed the fixed workspace", c.n_rho_tiles);

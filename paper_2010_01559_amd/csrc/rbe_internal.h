@@ -195,6 +195,7 @@ struct LaunchCfg {
     int64_t ntot;
     int mcap;
     int n_rho_tiles, n_force_tiles, n_part_tiles, n_real_tiles;
+    int max_sys_rho_tiles;   // most structure-factor tiles of one system
     int rho_chunk, rho_block, force_split, real_split;
     int ncell_tot;
     int max_cells;   // largest cell count of one system

@@ -432,10 +432,12 @@ hipError_t launch_set_step(const LaunchCfg &c, const Workspace &w, uint64_t step
 }
 
 
+int final_waves_log2(int max_tiles_per_system) { return max_tiles_per_system > 64 ? 2 : 0; }
+
 // ---------------------------------------------------------------------------
 // k_mid: independent jobs in one launch (roles in rbe_roles.h), in block
-// order: final structure factors (four waves per (system, mode) add the
-// tile partials in a fixed order and fill the per-mode force constants); gated
+// order: final structure factors (one or four waves per (system, mode) add
+// the tile partials in a fixed order and fill the per-mode force constants); gated
 // binning of a neighbour-list rebuild; the next step's modes (one block per
 // system); then either the gated rebuild's scan and scatter blocks or, for
 // cell-list force calls, one cell-scan block per system.
@@ -995,7 +997,9 @@ static hipError_t mid_dispatch(const LaunchCfg &c, const Workspace &w, int do_fi
     a.sys = w.sys;
     a.R = c.R;
     a.max_p = c.max_p;
-    a.n_final_blocks = do_final ? (c.R * c.max_p + kFinalModes - 1) / kFinalModes : 0;
+    a.final_lw = final_waves_log2(c.max_sys_rho_tiles);
+    const int final_modes = 16 >> a.final_lw;   // modes per totals block
+    a.n_final_blocks = do_final ? (c.R * c.max_p + final_modes - 1) / final_modes : 0;
     a.single_p = c.R == 1 ? c.max_p : 0;
     a.single_nt = c.n_rho_tiles;
     a.partial = w.partial;

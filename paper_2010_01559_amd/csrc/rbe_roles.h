@@ -96,6 +96,7 @@ struct MidArgs {
     int n_final_blocks;   // blocks doing the structure-factor totals
     int single_p;         // single-system context: its mode count (else 0) ...
     int single_nt;        // ... and its structure-factor tile count
+    int final_lw;         // log2 of the waves per mode of the totals (0 or 2)
     const double *partial;
     const int32_t *part_off;   // [2R]: partial offsets, then tile counts
     const int32_t *modes;
@@ -185,15 +186,16 @@ __device__ void mid_bin(const MidArgs<KM> &a, int b)
 }
 
 
-// Structure-factor totals of four modes per block, four waves per mode: the
-// wave of quarter q sums the tile partials of its mode in runs of 64 tiles
-// q, q + 4, q + 8, ... (a lane its tile of each run, in order), the waves
-// reduce across lanes, and the mode's first wave adds the four quarter sums
-// in order and writes the force constants.  The partials of one mode sit a
-// tile row apart (one cache line per tile), so spreading a mode over four
-// waves quarters the chain of dependent load batches of a long tile list.
-constexpr int kFinalWaves = 4;                          // waves per mode
-constexpr int kFinalModes = 16 / kFinalWaves;           // modes per 1024-thread block
+// Structure-factor totals, W = 2^final_lw waves per mode (1 or 4) and 16 / W
+// modes per 1024-thread block: the wave of part q sums the tile partials of
+// its mode in runs of 64 tiles q, q + W, q + 2W, ... (a lane its tile of
+// each run, in order), the waves reduce across lanes, and the mode's first
+// wave adds the W part sums in order and writes the force constants.  The
+// partials of one mode sit a tile row apart (one cache line per tile), so
+// four waves per mode quarter the chain of dependent load batches of a long
+// tile list; a context whose systems all have at most 64 tiles takes one
+// wave per mode and a quarter of the blocks.
+int final_waves_log2(int max_tiles_per_system);
 
 template <typename KM>
 __device__ void mid_final(const MidArgs<KM> &a, int blk)
@@ -201,8 +203,9 @@ __device__ void mid_final(const MidArgs<KM> &a, int blk)
     __shared__ double2 q_sum[16];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int gm = blk * kFinalModes + wave / kFinalWaves;
-    const int q = wave % kFinalWaves;
+    const int lw = a.final_lw, W = 1 << lw;
+    const int gm = (blk << (4 - lw)) + (wave >> lw);
+    const int q = wave & (W - 1);
     const int r = gm / a.max_p, l = gm % a.max_p;
     // a single system's mode and tile counts come with the launch, so that
     // the partial loads do not wait for the system constants and offsets
@@ -224,7 +227,7 @@ __device__ void mid_final(const MidArgs<KM> &a, int blk)
     double c = 0.0, s = 0.0;
     if (ok) {
         // eight loads are issued before they are added, so their latencies overlap
-        constexpr int STRIDE = 64 * kFinalWaves;
+        const int STRIDE = 64 * W;
         for (int t0 = 64 * q + lane; t0 < nt; t0 += 8 * STRIDE) {
             double2 v[8];
 #pragma unroll
@@ -249,7 +252,7 @@ __device__ void mid_final(const MidArgs<KM> &a, int blk)
     __syncthreads();
     if (ok && q == 0 && lane == 0) {
         double cc = 0.0, ss = 0.0;
-        for (int k = 0; k < kFinalWaves; ++k) {
+        for (int k = 0; k < W; ++k) {
             cc += q_sum[wave + k].x;
             ss += q_sum[wave + k].y;
         }
