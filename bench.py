@@ -72,13 +72,13 @@ PEAK_HBM_GBS = 8000.0
 # of the N = 1e5 run holds no rebuild); the staging launches of steps after
 # the first of a call; the Fourier-only launches at N = 1e5.
 TRAFFIC = {
-    "real": {"src": "3972852752c25e0f", "fetch_kib": 8590.8, "write_kib": 6452.8, "fetch_scale": 2.000,
+    "real": {"src": "eec603a65a2ee666", "fetch_kib": 8589.8, "write_kib": 6187.7, "fetch_scale": 2.000,
              "write_scale": 1.000},
-    "stage": {"src": "01402b11df11ea8c", "fetch_kib": 3192.8, "write_kib": 7239.8, "fetch_scale": 2.000,
+    "stage": {"src": "adaeb3e7b6491e46", "fetch_kib": 3012.7, "write_kib": 6995.3, "fetch_scale": 2.000,
               "write_scale": 1.000},
-    "stage_fourier": {"src": "01402b11df11ea8c", "fetch_kib": 872.8, "write_kib": 400.0, "fetch_scale": 2.000,
+    "stage_fourier": {"src": "adaeb3e7b6491e46", "fetch_kib": 875.8, "write_kib": 400.0, "fetch_scale": 2.000,
                       "write_scale": 1.000},
-    "kforce": {"src": "01402b11df11ea8c", "fetch_kib": 843.2, "write_kib": 1171.9, "fetch_scale": 2.000,
+    "kforce": {"src": "adaeb3e7b6491e46", "fetch_kib": 840.8, "write_kib": 1171.9, "fetch_scale": 2.000,
                "write_scale": 1.000},
 }
 
