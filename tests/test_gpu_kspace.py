@@ -167,6 +167,36 @@ def test_next_sample_drawn_ahead_batched():
         assert np.array_equal(host(F), host(Fb)), step
 
 
+@pytest.mark.parametrize("prec", [R.RBE_FP64, R.RBE_FP32])
+def test_batched_totals_with_a_long_tile_list(prec):
+    """A batch whose largest system has more than 64 structure-factor tiles
+    sums every mode's tile partials with four waves (the small system's waves
+    past its tiles add nothing): each system's Fourier force against the
+    oracle on its own modes (eq. 3.6)."""
+    a = W.alpha_for_real_space_error(0.1, 3.5)
+    systems = [W.electrolyte_system("big-n20000", 20000, 0.1, a, 3.5, 100, 71),
+               W.electrolyte_system("small-n1500", 1500, 0.1, a, 3.5, 60, 72, divalent_fraction=0.1)]
+    ctx = R.rbe_batch_create([R.params_from_system(x, prec) for x in systems])
+    chunk = R.rbe_get_tiles(ctx)["rho_chunk"]
+    assert (systems[0].n + chunk - 1) // chunk > 64 >= (systems[1].n + chunk - 1) // chunk, chunk
+    dt = torch.float64 if prec == R.RBE_FP64 else torch.float32
+    cat = lambda xs: np.ascontiguousarray(np.concatenate(xs, axis=-1))
+    P = torch.as_tensor(cat([x.pos for x in systems]), dtype=dt, device="cuda").contiguous()
+    Q = torch.as_tensor(cat([x.q for x in systems]), dtype=dt, device="cuda").contiguous()
+    F = torch.zeros_like(P)
+    step = 5
+    R.rbe_sample_k(ctx, step)
+    R.rbe_kspace_forces(ctx, P, Q, F)
+    pos, q, f = host(P), host(Q), host(F)
+    off = 0
+    for x in systems:
+        sl = slice(off, off + x.n)
+        modes, _ = O.sample_modes(x.alpha, x.L, x.p, x.seed, step)
+        fo = O.kspace_force(pos[:, sl], q[sl], x.L, modes, O.rbe_weights(x.alpha, x.L, x.p), x.coulomb)
+        assert rel_l2(f[:, sl], fo) <= TOL[prec], (x.name, rel_l2(f[:, sl], fo))
+        off += x.n
+
+
 def test_kspace_odd_sizes_fp32():
     # tiny, prime and single-particle-tail sizes with P not a multiple of 64
     for n, p in [(2, 1), (65, 7), (257, 33), (1025, 130)]:
